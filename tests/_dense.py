@@ -1,0 +1,74 @@
+"""Brute-force dense evaluation of one discrete velocity's upwind system.
+
+For a fixed velocity xi and a frozen source nu * f~S, the first-order upwind
+finite-volume discretisation of eq. "iter_outer" (written out for one octant
+in eq. "sweeping_example") is a linear system over all cells:
+
+    (nu_c + sum_d a_d) f_c - sum_{d: upwind neighbour fluid} a_d f_up(c,d)
+        = nu_c f~S_c + sum_{d: upwind side is a boundary} a_d f_boundary
+
+with a_d = |xi_d| / dx_d.  Here it is assembled as a dense matrix and solved
+with LU (numpy), i.e. without any notion of sweep order, so it checks the
+oracle's sweep (traversal order, upwind selection, boundary bookkeeping).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_1810_00348_amd.cases import FREE, SPECULAR, WALL
+
+
+def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=None):
+    nx, ny, nz = case.n
+    N = nx * ny * nz
+    mx, my, mz = case.m
+    a3 = alpha % mx
+    b3 = (alpha // mx) % my
+    c3 = alpha // (mx * my)
+    axes = []
+    for d in range(3):
+        M, V = case.m[d], case.vmax[d]
+        axes.append(np.linspace(-V, V, M))
+    xi = np.array([axes[0][a3], axes[1][b3], axes[2][c3]])
+    dx = np.array([case.L[0] / nx, case.L[1] / ny, case.L[2] / nz])
+    solid = case.solid_flat() if case.solid is not None else np.zeros(N, np.uint8)
+    A = np.zeros((N, N))
+    b = np.zeros(N)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                c = i + nx * (j + ny * k)
+                if solid[c]:
+                    A[c, c] = 1.0
+                    continue
+                A[c, c] = nu[c]
+                b[c] = nu[c] * feq[c]
+                pos = [i, j, k]
+                ext = [nx, ny, nz]
+                for d in range(3):
+                    ad = abs(xi[d]) / dx[d]
+                    if ad == 0:
+                        continue
+                    A[c, c] += ad
+                    step = -1 if xi[d] >= 0 else +1       # towards the upwind side
+                    side = 2 * d + (0 if xi[d] >= 0 else 1)
+                    p = list(pos)
+                    p[d] += step
+                    if 0 <= p[d] < ext[d]:
+                        nb = p[0] + nx * (p[1] + ny * p[2])
+                        if not solid[nb]:
+                            A[c, nb] -= ad
+                            continue
+                        fb = rho_w[side, c] * ghat_of_kind(6)[alpha]
+                    else:
+                        kind = case.faces[side].code
+                        if kind == WALL:
+                            fb = rho_w[side, c] * ghat_of_kind(side)[alpha]
+                        elif kind == FREE:
+                            fb = case.faces[side].rho * ghat_of_kind(side)[alpha]
+                        elif kind == SPECULAR:
+                            fb = spec_mirror[i + nx * j]
+                        else:
+                            raise ValueError(kind)
+                    b[c] += ad * fb
+    return np.linalg.solve(A, b)
