@@ -1,0 +1,193 @@
+/*
+ * dvm.h -- C ABI of libdvm_hip.so, the MI355X (gfx950) implementation of the
+ * iterative discrete-velocity scheme for the steady Shakhov model equation
+ * (Zhu, Wang, Chen, Guo, Zhang, "GPU acceleration of an iterative scheme for
+ * gas-kinetic model equations with memory reduction techniques",
+ * arXiv:1810.00348).
+ *
+ * One outer iteration n -> n+1 (Sec. 2.2, eq. "iter_outer"):
+ *   1. per cell, from the conserved moments W^n = (rho, rho U, rho E) and the
+ *      heat flux q^n (eq. "mom"): U, T, the relaxation rate 1/tau
+ *      (tau = mu/p, viscosity law and mu_ref of Sec. 4, eq. "mu_ref"), the
+ *      parameters of the Shakhov equilibrium f^S (eq. "feq") and of its
+ *      conservative correction (discrete mass, momentum and energy of the
+ *      corrected equilibrium equal those of f, computed in FP64);
+ *   2. for every discrete velocity, the first-order upwind implicit sweep
+ *      along its characteristic direction (eq. "sweeping_example"), with the
+ *      equilibrium evaluated on the fly, never stored;
+ *   3. the discrete moments of the new f (eq. "macros"), accumulated in FP64,
+ *      the wall densities from the non-penetration condition
+ *      (eqs. "maxwell_wall", "rho_wall"), the total-mass rescaling of a
+ *      closed domain (Sec. 3.4) and the relative change of the conserved
+ *      fields (Sec. 4.1).
+ *
+ * Units: lengths in units of the reference length that defines Kn,
+ * velocities in units of sqrt(2 R T0), temperature in T0, density in rho0.
+ *
+ * Conventions
+ *   - Cell index c = i + nx*(j + ny*k); field arrays are structure-of-arrays
+ *     FP64 (a 3-vector field u is u[d*N + c]).
+ *   - Host arrays are owned by the caller; every call that reads or writes
+ *     them copies synchronously on the context's stream.
+ *   - Device memory: the library allocates none.  The caller (the Python
+ *     binding uses torch) allocates a workspace of dvm_required_workspace()
+ *     bytes and lends it with dvm_bind_workspace(); the library never frees
+ *     it.  The workspace must stay alive and untouched until dvm_destroy().
+ *   - Every call returns a dvm_status; on an error the context keeps the
+ *     last good iterate and dvm_last_error() describes the failure.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Call order: dvm_create -> dvm_set_face_bc / dvm_set_solid /
+ *     dvm_set_closed -> dvm_required_workspace -> dvm_bind_workspace ->
+ *     dvm_init_uniform | dvm_init_fields | dvm_set_state -> dvm_iterate ...
+ */
+#ifndef DVM_H
+#define DVM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dvm_ctx dvm_ctx;
+
+typedef enum {
+    DVM_OK = 0,
+    DVM_NOT_CONVERGED = 1,   /* max_iters reached before the tolerance      */
+    DVM_ERR_ARG = -1,        /* invalid argument                           */
+    DVM_ERR_STATE = -2,      /* call out of order                          */
+    DVM_ERR_OOM = -3,        /* workspace too small / host allocation      */
+    DVM_ERR_DEVICE = -4,     /* HIP runtime error                          */
+    DVM_ERR_NONPHYSICAL = -5 /* rho <= 0, T <= 0 or NaN                     */
+} dvm_status;
+
+typedef enum { DVM_F64 = 0, DVM_F32 = 1 } dvm_precision;
+
+/* boundary kinds of a box face */
+typedef enum {
+    DVM_BC_WALL = 0,     /* Maxwell diffuse wall (eqs. "maxwell_wall", "rho_wall") */
+    DVM_BC_FREE = 1,     /* particles entering get the free-stream equilibrium   */
+    DVM_BC_SPECULAR = 2  /* symmetry plane (z- face only, even velocity count)   */
+} dvm_bc_kind;
+
+typedef struct { int nx, ny, nz; double lx, ly, lz; } dvm_grid;       /* uniform cells */
+typedef struct { int m[3]; double vmax[3]; } dvm_vgrid;                /* m[d] >= 2 uniform nodes
+                                                                          on [-vmax, vmax], both
+                                                                          ends included, trapezoid
+                                                                          weights (Sec. 4.1)      */
+typedef struct {
+    double kn;      /* Knudsen number: tau(rho=1,T=1) = kn*15 sqrt(pi)/((5-2w)(7-2w)) */
+    double omega;   /* viscosity index, mu ~ T^omega (0.81 for argon, Sec. 4)        */
+    double pr;      /* Prandtl number of the Shakhov model (2/3); pr = 1 gives BGK   */
+    int conservative_correction;  /* 1 (default): corrected equilibrium            */
+} dvm_gas;
+
+typedef struct {
+    int kind;       /* dvm_bc_kind                                                   */
+    double u[3];    /* wall or free-stream velocity                                  */
+    double T;       /* wall or free-stream temperature                               */
+    double rho;     /* free-stream density (DVM_BC_FREE only)                        */
+} dvm_face_bc;
+
+typedef struct {
+    int nx, ny, nz, ncells, nfluid;
+    int m[3], nvel;
+    int precision;              /* dvm_precision                                  */
+    int brick[3];               /* cells per brick of the sweep schedule          */
+    int vel_per_lane;           /* discrete velocities handled by one lane        */
+    int tiles_per_octant;       /* 64-lane velocity tiles per octant              */
+    int sweep_launches;         /* sweep kernel launches per iteration            */
+    size_t workspace_bytes;
+} dvm_info;
+
+/* Create a context.  precision: DVM_F64 or DVM_F32 (storage and update type of
+   f; moments, correction and all per-cell quantities stay FP64).  hip_stream:
+   a hipStream_t on which every kernel and copy is issued (NULL = null stream).
+   Defaults: all six faces diffuse walls at rest with T = 1, no solid, closed.
+   Errors: DVM_ERR_ARG for non-positive sizes, lengths, kn, pr or T. */
+dvm_status dvm_create(const dvm_grid* grid, const dvm_vgrid* vgrid, const dvm_gas* gas,
+                      int precision, void* hip_stream, dvm_ctx** out);
+
+/* Boundary condition of box face 0..5 = x-, x+, y-, y+, z-, z+.  Errors:
+   DVM_ERR_ARG (bad face/kind, T <= 0, specular on a face other than z- or
+   with an odd velocity count along z), DVM_ERR_STATE after binding. */
+dvm_status dvm_set_face_bc(dvm_ctx* ctx, int face, const dvm_face_bc* bc);
+
+/* Solid cells (mask[c] != 0) inside the box; their faces are diffuse walls
+   with velocity u_wall and temperature T_wall.  mask may be NULL (no solid). */
+dvm_status dvm_set_solid(dvm_ctx* ctx, const unsigned char* mask, const double u_wall[3],
+                         double T_wall);
+
+/* closed != 0: rescale the density field after every iteration so that the
+   total mass stays that of the initial state (Sec. 3.4, internal flows). */
+dvm_status dvm_set_closed(dvm_ctx* ctx, int closed);
+
+/* Bytes of device workspace the context needs with its current settings. */
+dvm_status dvm_required_workspace(dvm_ctx* ctx, size_t* bytes);
+
+/* Lend the workspace (device pointer, >= required bytes, 256-byte aligned).
+   Uploads the velocity set and boundary tables and computes the wall
+   emission shapes on the device. */
+dvm_status dvm_bind_workspace(dvm_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Uniform initial state (rho, u, T); q = 0; wall densities from the
+   non-penetration flux of the initial equilibrium (Sec. 2.2, initial
+   equilibrium from uniform macroscopic fields). */
+dvm_status dvm_init_uniform(dvm_ctx* ctx, double rho, const double u[3], double T);
+
+/* Initial state from host fields rho[N], u[3N], T[N] (solid cells ignored).
+   target_mass > 0: rho is first scaled so that sum(rho) dV = target_mass.
+   Errors: DVM_ERR_NONPHYSICAL if a fluid cell has rho <= 0, T <= 0 or a
+   non-finite value. */
+dvm_status dvm_init_fields(dvm_ctx* ctx, const double* rho, const double* u, const double* T,
+                           double target_mass);
+
+/* Run up to max_iters outer iterations, stopping after the first one whose
+   residual is <= tol (tol <= 0: run exactly max_iters).  Residual: the max
+   over rho, rho Ux, rho Uy, rho Uz, rho E of ||phi^{n+1}-phi^n||_2 /
+   ||phi^{n+1}||_2 over fluid cells.  iters_done, residual may be NULL.
+   Returns DVM_OK (converged or tol <= 0), DVM_NOT_CONVERGED, or an error
+   (DVM_ERR_NONPHYSICAL leaves the last good iterate in place). */
+dvm_status dvm_iterate(dvm_ctx* ctx, int max_iters, double tol, int* iters_done,
+                       double* residual);
+
+/* Residual of each conserved field after the last iteration (5 values). */
+dvm_status dvm_get_residuals(dvm_ctx* ctx, double r[5]);
+
+/* Macroscopic fields of the current iterate: rho[N], u[3N], T[N], q[3N]
+   (any may be NULL); solid cells get 0. */
+dvm_status dvm_get_fields(dvm_ctx* ctx, double* rho, double* u, double* T, double* q);
+
+/* Checkpoint / resume: W[5N] (rho, rho U, rho E), q[3N], rho_w[6N] (wall
+   density of each cell face, side-major), M0 (total mass of the initial
+   state).  Any pointer may be NULL on get. */
+dvm_status dvm_get_state(dvm_ctx* ctx, double* W, double* q, double* rho_w, double* M0);
+dvm_status dvm_set_state(dvm_ctx* ctx, const double* W, const double* q, const double* rho_w,
+                         double M0);
+
+/* Sizes and schedule of the context. */
+dvm_status dvm_get_info(dvm_ctx* ctx, dvm_info* info);
+
+/* Per-phase device timing.  enable != 0 records HIP events around the
+   parameter, sweep and finalisation phases of every following iteration
+   (on the context's stream).  dvm_get_timings returns the accumulated
+   milliseconds and the number of timed iterations, then resets them. */
+dvm_status dvm_set_timing(dvm_ctx* ctx, int enable);
+dvm_status dvm_get_timings(dvm_ctx* ctx, double* ms_params, double* ms_sweep,
+                           double* ms_finalize, int* iterations);
+
+/* Check of the wave-level 13-moment reduction used by the sweep kernel:
+   in[64*13] (lane-major: in[lane*13 + k]) -> out[13] = sum over lanes. */
+dvm_status dvm_selftest_wave_reduce(const double* in, double* out);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dvm_last_error(void);
+
+/* Release the context (not the borrowed workspace). */
+void dvm_destroy(dvm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DVM_H */

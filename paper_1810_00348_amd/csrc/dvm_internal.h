@@ -1,0 +1,108 @@
+// Internal declarations shared by the kernels and the host runtime of
+// libdvm_hip.so.  Not part of the public ABI (include/dvm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dvm {
+
+constexpr int NMOM = 13;     // raw velocity moments accumulated per cell
+constexpr int PSTRIDE = 16;  // per-cell equilibrium parameter slots
+constexpr int MAXM = 512;    // velocity nodes per axis (upper bound)
+constexpr int NKIND = 7;     // emission kinds: 6 box faces + the solid body
+
+// per-cell equilibrium parameter slots (see params_kernel)
+enum {
+    P_NU = 0,   // 1/tau
+    P_UX, P_UY, P_UZ,
+    P_L0,       // 1 + lambda_0
+    P_L1, P_L2, P_L3, P_L4,
+    P_QX, P_QY, P_QZ,  // sigma * q
+    P_TWO_T,    // 2 / T
+    P_NPARAM
+};
+
+// cell info word: 4 bits per side (side s = 2 d + (upper ? 1 : 0)):
+//   0       interior fluid neighbour
+//   1..7    emission kind + 1 (0..5 box face, 6 solid body)
+//   8       specular plane
+// bit 24: the cell itself is solid
+constexpr uint32_t SOLID_BIT = 1u << 24;
+constexpr uint32_t CODE_SPECULAR = 8;
+
+// lane table layout (doubles) per (octant, lane slot):
+//   [0] xi_y [1] xi_z [2] a_y [3] a_z [4] b (y node) [5] c (z node)
+//   then per velocity v of the lane: [6+4v] xi_x [7+4v] a_x [8+4v] w [9+4v] a (x node)
+constexpr int LT_SHARED = 6;
+constexpr int LT_PER_V = 4;
+
+struct Consts {
+    int nx, ny, nz, N;
+    int mx, my, mz, MT, NV;
+    double kappa_kn;      // kappa * Kn
+    double omega, pr;
+    int correct;
+    int closed;
+    double dV;
+    double kind_rho[8];   // fixed emission density (free stream), per kind
+    int kind_wall[8];     // 1: density from non-penetration
+};
+
+struct DevPtrs {
+    const double* xi;     // [3][MAXM] axis nodes
+    const double* wt;     // [3][MAXM] axis weights
+    const uint32_t* cellinfo;
+    const int* bricks;    // int4 (I, J, K, 0) per brick, grouped by diagonal
+    const double* lanetab;
+};
+
+template <typename S>
+struct SweepArgs {
+    const S* params;      // [N][PSTRIDE]
+    const S* etab;        // [N][MT]: exp tables x | y | z (z scaled by nu * prefactor)
+    const uint32_t* cellinfo;
+    const double* rho_w;  // [6][N] wall densities of iteration n
+    const S* ghat;        // [NKIND][NV] unit-density emission shapes
+    const double* lanetab;
+    const int* bricks;
+    S* xface;
+    S* yface;
+    S* zface;
+    S* spec;
+    double* partial;      // [8*ntiles][N][NMOM]
+    int nx, ny, nz, N, mx, my, MT, NV;
+    int nbx, nby, nbz, bz;
+    int ntiles, slots, lstride;
+    int brick_off, brick_cnt;
+    int oct_base, noct;
+    int spec_on;
+    int nblocks;
+    double kind_rho[8];
+    int kind_wall[8];
+};
+
+// kernel launchers (dvm_kernels.hip)
+hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, const double* q,
+                         void* params, void* etab, int prec, int* flag, hipStream_t st);
+hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind_state /*[NKIND][4]*/,
+                           int nkind, void* ghat, double* ghat64, double* gout, int prec,
+                           hipStream_t st);
+hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* params, const void* etab,
+                            const double* ghat64, const double* gout, double* rho_w, int prec,
+                            hipStream_t st);
+hipError_t launch_sweep(int prec, int vl, int bx, int by, const void* args, hipStream_t st);
+hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
+                           const double* gout, double* Wn, double* qn, double* rwn,
+                           double* blockmass, int nblocks, int* flag, hipStream_t st);
+hipError_t launch_scale_residual(const Consts& C, const DevPtrs& D, double M0,
+                                 const double* blockmass, int nbm, double* Wn, double* qn,
+                                 double* rwn, const double* Wo, double* respart, int nblocks,
+                                 hipStream_t st);
+hipError_t launch_residual_final(const double* respart, int nblocks, const double* blockmass,
+                                 int nbm, double* out, const int* flag, hipStream_t st);
+hipError_t launch_selftest_reduce(const double* in, double* out, hipStream_t st);
+bool sweep_variant_available(int prec, int vl, int bx, int by);
+
+}  // namespace dvm

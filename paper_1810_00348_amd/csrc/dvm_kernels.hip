@@ -1,0 +1,935 @@
+// HIP kernels (gfx950) of the iterative discrete-velocity scheme for the
+// steady Shakhov model equation (arXiv:1810.00348, Secs. 2-3).
+//
+// Per outer iteration (eq. "iter_outer"):
+//   params_kernel     per cell: U, T, 1/tau, Shakhov and conservative-correction
+//                     parameters in FP64, and the three 1-D Gaussian factor
+//                     tables of the Maxwellian (eqs. "feq", "mom", "mu_ref").
+//   sweep_kernel      the hot path: first-order upwind implicit sweep of every
+//                     discrete velocity (eq. "sweeping_example") over 3-D bricks
+//                     scheduled along brick diagonals, equilibrium evaluated on
+//                     the fly, 13 raw moments reduced across the wave
+//                     (eq. "macros") into deterministic per-tile partials.
+//   finalize_kernel   per cell: sum of the partials, new conserved moments,
+//                     heat flux about the new bulk velocity, wall densities from
+//                     the non-penetration condition (eq. "rho_wall").
+//   scale_residual /  closed-domain mass rescaling (Sec. 3.4) and the relative
+//   residual_final    change of the conserved fields (Sec. 4.1).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "dvm_internal.h"
+
+namespace dvm {
+
+// --------------------------------------------------------------------------
+// small helpers
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ double ldpar(const double* p) { return *p; }
+
+// 5x5 symmetric positive definite solve by Cholesky (FP64).
+__device__ bool chol5_solve(double A[5][5], const double b[5], double x[5])
+{
+    double L[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) L[i][j] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i][i] = sqrt(s);
+            } else {
+                L[i][j] = s / L[j][j];
+            }
+        }
+    }
+    double y[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+        y[i] = s / L[i][i];
+    }
+#pragma unroll
+    for (int i = 4; i >= 0; --i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 5; ++k) s -= L[k][i] * x[k];
+        x[i] = s / L[i][i];
+    }
+    return true;
+}
+
+// Correction multipliers from separable 1-D moments.
+//   Mx[p] = sum_a w_a (xi_a - Ux)^p exp(-(xi_a - Ux)^2 / T), p = 0..5 (same y, z),
+// so that sum over the grid of w c^(p,q,r) f^M = pre * Mx[p] My[q] Mz[r].
+// Basis phi = (1, cx, cy, cz, |c|^2).  Solves A lam = t - sum w phi f^S with
+// A_lk = sum w phi_l phi_k f^M and targets t = (rho, 0, 0, 0, 3 rho T / 2):
+// the corrected equilibrium f^S + f^M lam.phi has exactly the discrete mass,
+// momentum and energy of the state it is built from.
+__device__ bool correction_lambda(const double Mx[6], const double My[6], const double Mz[6],
+                                  double pre, double rho, double T, double sig, double qx,
+                                  double qy, double qz, double lam[5])
+{
+    // monomials of phi_l: up to three exponent triples each
+    const int nmon[5] = {1, 1, 1, 1, 3};
+    const int ex[5][3][3] = {
+        {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}},
+        {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}},
+        {{0, 1, 0}, {0, 0, 0}, {0, 0, 0}},
+        {{0, 0, 1}, {0, 0, 0}, {0, 0, 0}},
+        {{2, 0, 0}, {0, 2, 0}, {0, 0, 2}},
+    };
+    auto mom = [&](int p, int q, int r) { return pre * Mx[p] * My[q] * Mz[r]; };
+    double A[5][5], b[5];
+    const double qv[3] = {qx, qy, qz};
+    const double two_T = 2.0 / T;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            double s = 0.0;
+            for (int u = 0; u < nmon[l]; ++u)
+                for (int v = 0; v < nmon[k]; ++v)
+                    s += mom(ex[l][u][0] + ex[k][v][0], ex[l][u][1] + ex[k][v][1],
+                             ex[l][u][2] + ex[k][v][2]);
+            A[l][k] = s;
+        }
+        // sum w phi_l f^S = sum w phi_l f^M [1 + sig (c.q)(2|c|^2/T - 5)]
+        double s = 0.0;
+        for (int u = 0; u < nmon[l]; ++u) {
+            const int p0 = ex[l][u][0], q0 = ex[l][u][1], r0 = ex[l][u][2];
+            s += mom(p0, q0, r0);
+            for (int d = 0; d < 3; ++d) {
+                int pd = p0 + (d == 0), qd = q0 + (d == 1), rd = r0 + (d == 2);
+                double t = -5.0 * mom(pd, qd, rd);
+                t += two_T * (mom(pd + 2, qd, rd) + mom(pd, qd + 2, rd) + mom(pd, qd, rd + 2));
+                s += sig * qv[d] * t;
+            }
+        }
+        b[l] = -s;
+    }
+    b[0] += rho;
+    b[4] += 1.5 * rho * T;
+    return chol5_solve(A, b, lam);
+}
+
+// --------------------------------------------------------------------------
+// A1: per-cell parameters
+// --------------------------------------------------------------------------
+
+template <typename S>
+__global__ __launch_bounds__(128) void params_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
+                                                     const double* __restrict__ q, S* __restrict__ params,
+                                                     S* __restrict__ etab, int* __restrict__ flag)
+{
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= C.N) return;
+    if (D.cellinfo[cell] & SOLID_BIT) return;
+    const int N = C.N;
+    const double rho = W[cell];
+    const double Ux = W[N + cell] / rho, Uy = W[2 * N + cell] / rho, Uz = W[3 * N + cell] / rho;
+    const double T = (W[4 * N + cell] - 0.5 * rho * (Ux * Ux + Uy * Uy + Uz * Uz)) / (0.75 * rho);
+    S* P = params + (size_t)cell * PSTRIDE;
+    S* E = etab + (size_t)cell * C.MT;
+    if (!(rho > 0.0) || !(T > 0.0) || !isfinite(Ux) || !isfinite(Uy) || !isfinite(Uz) ||
+        !isfinite(T)) {
+        atomicOr(flag, 1);
+        for (int k = 0; k < PSTRIDE; ++k) P[k] = (S)0;
+        P[P_NU] = (S)1;
+        for (int k = 0; k < C.MT; ++k) E[k] = (S)0;
+        return;
+    }
+    const double qx = q[cell], qy = q[N + cell], qz = q[2 * N + cell];
+    const double nu = rho * pow(T, 1.0 - C.omega) / C.kappa_kn;
+    const double pre = rho * pow(M_PI * T, -1.5);
+    const double sig = (1.0 - C.pr) * 4.0 / (5.0 * rho * T * T);
+    const double invT = 1.0 / T;
+    double Mx[6], My[6], Mz[6];
+    const double U3[3] = {Ux, Uy, Uz};
+    const int m3[3] = {C.mx, C.my, C.mz};
+    int off = 0;
+    for (int d = 0; d < 3; ++d) {
+        double* M = d == 0 ? Mx : d == 1 ? My : Mz;
+        for (int p = 0; p < 6; ++p) M[p] = 0.0;
+        const double scale = d == 2 ? nu * pre : 1.0;
+        const double* xi = D.xi + d * MAXM;
+        const double* wt = D.wt + d * MAXM;
+        for (int a = 0; a < m3[d]; ++a) {
+            const double c = xi[a] - U3[d];
+            const double g = exp(-c * c * invT);
+            E[off + a] = (S)(g * scale);
+            double t = wt[a] * g;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                M[p] += t;
+                t *= c;
+            }
+        }
+        off += m3[d];
+    }
+    double lam[5] = {0, 0, 0, 0, 0};
+    if (C.correct) {
+        if (!correction_lambda(Mx, My, Mz, pre, rho, T, sig, qx, qy, qz, lam)) {
+            atomicOr(flag, 2);
+        }
+    }
+    P[P_NU] = (S)nu;
+    P[P_UX] = (S)Ux;
+    P[P_UY] = (S)Uy;
+    P[P_UZ] = (S)Uz;
+    P[P_L0] = (S)(1.0 + lam[0]);
+    P[P_L1] = (S)lam[1];
+    P[P_L2] = (S)lam[2];
+    P[P_L3] = (S)lam[3];
+    P[P_L4] = (S)lam[4];
+    P[P_QX] = (S)(sig * qx);
+    P[P_QY] = (S)(sig * qy);
+    P[P_QZ] = (S)(sig * qz);
+    P[P_TWO_T] = (S)(2.0 * invT);
+}
+
+hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, const double* q,
+                         void* params, void* etab, int prec, int* flag, hipStream_t st)
+{
+    const int tpb = 128;
+    const int nb = (C.N + tpb - 1) / tpb;
+    if (prec == 0)
+        params_kernel<double><<<nb, tpb, 0, st>>>(C, D, W, q, (double*)params, (double*)etab, flag);
+    else
+        params_kernel<float><<<nb, tpb, 0, st>>>(C, D, W, q, (float*)params, (float*)etab, flag);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Wall and free-stream emission shapes: the corrected equilibrium with unit
+// density, velocity u_k, temperature T_k and no heat flux, over the whole
+// velocity set, and its emitted-flux normaliser for every face orientation:
+//   gout[k][s] = sum over xi.n > 0 of w (xi.n) ghat_k,  n the normal of side s
+//   pointing into the gas (eq. "rho_wall" with the discrete quadrature).
+// One block per kind.
+// --------------------------------------------------------------------------
+
+template <typename S>
+__global__ __launch_bounds__(256) void emission_kernel(Consts C, DevPtrs D, const double* kind_state,
+                                                       S* ghat, double* ghat64, double* gout)
+{
+    const int k = blockIdx.x;
+    const double ux = kind_state[4 * k + 0], uy = kind_state[4 * k + 1], uz = kind_state[4 * k + 2];
+    const double T = kind_state[4 * k + 3];
+    __shared__ double lam_s[5];
+    __shared__ double pre_s;
+    __shared__ double red[6][256];
+    if (threadIdx.x == 0) {
+        const double pre = pow(M_PI * T, -1.5);
+        double M[3][6];
+        const double U3[3] = {ux, uy, uz};
+        const int m3[3] = {C.mx, C.my, C.mz};
+        for (int d = 0; d < 3; ++d) {
+            for (int p = 0; p < 6; ++p) M[d][p] = 0.0;
+            for (int a = 0; a < m3[d]; ++a) {
+                const double c = D.xi[d * MAXM + a] - U3[d];
+                double t = D.wt[d * MAXM + a] * exp(-c * c / T);
+                for (int p = 0; p < 6; ++p) {
+                    M[d][p] += t;
+                    t *= c;
+                }
+            }
+        }
+        double lam[5] = {0, 0, 0, 0, 0};
+        if (C.correct) correction_lambda(M[0], M[1], M[2], pre, 1.0, T, 0.0, 0, 0, 0, lam);
+        for (int l = 0; l < 5; ++l) lam_s[l] = lam[l];
+        pre_s = pre;
+    }
+    __syncthreads();
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int al = threadIdx.x; al < C.NV; al += blockDim.x) {
+        const int a = al % C.mx, b = (al / C.mx) % C.my, c = al / (C.mx * C.my);
+        const double xx = D.xi[a], xy = D.xi[MAXM + b], xz = D.xi[2 * MAXM + c];
+        const double cx = xx - ux, cy = xy - uy, cz = xz - uz;
+        const double c2 = cx * cx + cy * cy + cz * cz;
+        const double fm = pre_s * exp(-c2 / T);
+        const double g = fm * (1.0 + lam_s[0] + lam_s[1] * cx + lam_s[2] * cy + lam_s[3] * cz +
+                               lam_s[4] * c2);
+        ghat[(size_t)k * C.NV + al] = (S)g;
+        ghat64[(size_t)k * C.NV + al] = g;
+        const double w = D.wt[a] * D.wt[MAXM + b] * D.wt[2 * MAXM + c];
+        const double xv[3] = {xx, xy, xz};
+        for (int s = 0; s < 6; ++s) {
+            const double xn = (s & 1) ? -xv[s >> 1] : xv[s >> 1];
+            if (xn > 0) acc[s] += w * xn * g;
+        }
+    }
+    for (int s = 0; s < 6; ++s) red[s][threadIdx.x] = acc[s];
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int s = 0; s < 6; ++s) red[s][threadIdx.x] += red[s][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) gout[k * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind_state, int nkind,
+                           void* ghat, double* ghat64, double* gout, int prec, hipStream_t st)
+{
+    if (prec == 0)
+        emission_kernel<double><<<nkind, 256, 0, st>>>(C, D, kind_state, (double*)ghat, ghat64, gout);
+    else
+        emission_kernel<float><<<nkind, 256, 0, st>>>(C, D, kind_state, (float*)ghat, ghat64, gout);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Initial wall densities: non-penetration flux of the initial corrected
+// equilibrium at every wall face, divided by the emitted-flux normaliser.
+// --------------------------------------------------------------------------
+
+template <typename S>
+__global__ __launch_bounds__(128) void wall_init_kernel(Consts C, DevPtrs D, const S* __restrict__ params,
+                                                        const S* __restrict__ etab,
+                                                        const double* __restrict__ gout,
+                                                        double* __restrict__ rho_w)
+{
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= C.N) return;
+    const uint32_t info = D.cellinfo[cell];
+    for (int s = 0; s < 6; ++s) rho_w[(size_t)s * C.N + cell] = 0.0;
+    if (info & SOLID_BIT) return;
+    const S* P = params + (size_t)cell * PSTRIDE;
+    const S* E = etab + (size_t)cell * C.MT;
+    const double nu = (double)P[P_NU];
+    for (int s = 0; s < 6; ++s) {
+        const uint32_t code = (info >> (4 * s)) & 15u;
+        if (code == 0 || code == CODE_SPECULAR) continue;
+        const int kind = (int)code - 1;
+        if (!C.kind_wall[kind]) continue;
+        const int d = s >> 1;
+        double flux = 0.0;
+        for (int c = 0; c < C.mz; ++c)
+            for (int b = 0; b < C.my; ++b)
+                for (int a = 0; a < C.mx; ++a) {
+                    const double xv[3] = {D.xi[a], D.xi[MAXM + b], D.xi[2 * MAXM + c]};
+                    const double xn = (s & 1) ? -xv[d] : xv[d];  // xi . n, n into the gas
+                    if (!(xn < 0)) continue;
+                    const double cx = xv[0] - (double)P[P_UX];
+                    const double cy = xv[1] - (double)P[P_UY];
+                    const double cz = xv[2] - (double)P[P_UZ];
+                    const double c2 = cx * cx + cy * cy + cz * cz;
+                    const double poly = (double)P[P_L0] + (double)P[P_L1] * cx + (double)P[P_L2] * cy +
+                                        (double)P[P_L3] * cz + (double)P[P_L4] * c2 +
+                                        ((double)P[P_QX] * cx + (double)P[P_QY] * cy + (double)P[P_QZ] * cz) *
+                                            (c2 * (double)P[P_TWO_T] - 5.0);
+                    const double nfs = (double)E[a] * (double)E[C.mx + b] * (double)E[C.mx + C.my + c] * poly;
+                    const double w = D.wt[a] * D.wt[MAXM + b] * D.wt[2 * MAXM + c];
+                    flux += w * (-xn) * nfs / nu;
+                }
+        rho_w[(size_t)s * C.N + cell] = flux / gout[kind * 6 + s];
+    }
+}
+
+hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* params, const void* etab,
+                            const double* ghat64, const double* gout, double* rho_w, int prec,
+                            hipStream_t st)
+{
+    (void)ghat64;
+    const int tpb = 128;
+    const int nb = (C.N + tpb - 1) / tpb;
+    if (prec == 0)
+        wall_init_kernel<double><<<nb, tpb, 0, st>>>(C, D, (const double*)params, (const double*)etab, gout, rho_w);
+    else
+        wall_init_kernel<float><<<nb, tpb, 0, st>>>(C, D, (const float*)params, (const float*)etab, gout, rho_w);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Wave-level reduction of 13 FP64 values over the 64 lanes.
+//
+// Recursive halving: every step pairs two value registers and two lane
+// groups, so the number of live registers halves while the lanes each
+// register's partial spans double.  gfx950 permlane32/permlane16 swaps do the
+// 32- and 16-lane steps, DPP row shifts with bank masks the 8- and 4-lane
+// steps, quad permutes the last two.  After the call, lane
+// L = 16 r + 4 b + x holds the full sum of value
+//   idx(r, b) = {0, 8, 4, 12}[b] + {0, 2, 1, 3}[r]   (valid if <= 12).
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ void pl32_swap(double& x, double& y)
+{
+    // afterwards x = [x(0..31) | y(0..31)], y = [x(32..63) | y(32..63)]
+    const unsigned x0 = (unsigned)__double2loint(x), x1 = (unsigned)__double2hiint(x);
+    const unsigned y0 = (unsigned)__double2loint(y), y1 = (unsigned)__double2hiint(y);
+    const auto r0 = __builtin_amdgcn_permlane32_swap(x0, y0, false, false);
+    const auto r1 = __builtin_amdgcn_permlane32_swap(x1, y1, false, false);
+    x = __hiloint2double((int)r1[0], (int)r0[0]);
+    y = __hiloint2double((int)r1[1], (int)r0[1]);
+}
+
+__device__ __forceinline__ void pl16_swap(double& x, double& y)
+{
+    // rows of 16 lanes: afterwards x = [x r0, y r0, x r2, y r2], y = [x r1, y r1, x r3, y r3]
+    const unsigned x0 = (unsigned)__double2loint(x), x1 = (unsigned)__double2hiint(x);
+    const unsigned y0 = (unsigned)__double2loint(y), y1 = (unsigned)__double2hiint(y);
+    const auto r0 = __builtin_amdgcn_permlane16_swap(x0, y0, false, false);
+    const auto r1 = __builtin_amdgcn_permlane16_swap(x1, y1, false, false);
+    x = __hiloint2double((int)r1[0], (int)r0[0]);
+    y = __hiloint2double((int)r1[1], (int)r0[1]);
+}
+
+template <int CTRL, int ROWMASK, int BANKMASK>
+__device__ __forceinline__ double dpp_merge(double old, double src)
+{
+    const int o0 = __double2loint(old), o1 = __double2hiint(old);
+    const int s0 = __double2loint(src), s1 = __double2hiint(src);
+    const int r0 = __builtin_amdgcn_update_dpp(o0, s0, CTRL, ROWMASK, BANKMASK, false);
+    const int r1 = __builtin_amdgcn_update_dpp(o1, s1, CTRL, ROWMASK, BANKMASK, false);
+    return __hiloint2double(r1, r0);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double src)
+{
+    const int s0 = __double2loint(src), s1 = __double2hiint(src);
+    const int r0 = __builtin_amdgcn_update_dpp(0, s0, CTRL, 0xF, 0xF, true);
+    const int r1 = __builtin_amdgcn_update_dpp(0, s1, CTRL, 0xF, 0xF, true);
+    return __hiloint2double(r1, r0);
+}
+
+constexpr int DPP_ROW_SHL8 = 0x108, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_SHL4 = 0x104, DPP_ROW_SHR4 = 0x114;
+constexpr int DPP_QUAD_2301 = 0x4E, DPP_QUAD_1032 = 0xB1;
+
+__device__ __forceinline__ double halve8(double x, double y)
+{
+    // within each row: lanes 0-7 <- x(0..7) + x(8..15); lanes 8-15 <- y(0..7) + y(8..15)
+    const double a = dpp_merge<DPP_ROW_SHR8, 0xF, 0xC>(x, y);  // lanes 8-15 take y(l-8)
+    const double b = dpp_merge<DPP_ROW_SHL8, 0xF, 0x3>(y, x);  // lanes 0-7 take x(l+8)
+    return a + b;
+}
+
+__device__ __forceinline__ double halve4(double x, double y)
+{
+    // banks of 4: bank0 <- x b0 + x b1, bank1 <- y b0 + y b1, bank2 <- x b2 + x b3, bank3 <- y b2 + y b3
+    const double a = dpp_merge<DPP_ROW_SHR4, 0xF, 0xA>(x, y);
+    const double b = dpp_merge<DPP_ROW_SHL4, 0xF, 0x5>(y, x);
+    return a + b;
+}
+
+__device__ __forceinline__ double wave_reduce13(const double v[13])
+{
+    double r0 = v[0], r1 = v[1], r2 = v[2], r3 = v[3], r4 = v[4], r5 = v[5], r6 = v[6];
+    double s0 = v[7], s1 = v[8], s2 = v[9], s3 = v[10], s4 = v[11], s5 = v[12], z = 0.0;
+    // 64 -> 32 lanes: pairs (0,1) (2,3) (4,5) (6,7) (8,9) (10,11) (12,-)
+    double a0 = r0, b0 = r1; pl32_swap(a0, b0); const double R0 = a0 + b0;
+    double a1 = r2, b1 = r3; pl32_swap(a1, b1); const double R1 = a1 + b1;
+    double a2 = r4, b2 = r5; pl32_swap(a2, b2); const double R2 = a2 + b2;
+    double a3 = r6, b3 = s0; pl32_swap(a3, b3); const double R3 = a3 + b3;
+    double a4 = s1, b4 = s2; pl32_swap(a4, b4); const double R4 = a4 + b4;
+    double a5 = s3, b5 = s4; pl32_swap(a5, b5); const double R5 = a5 + b5;
+    double a6 = s5, b6 = z;  pl32_swap(a6, b6); const double R6 = a6 + b6;
+    // 32 -> 16 lanes
+    double c0 = R0, d0 = R1; pl16_swap(c0, d0); const double Q0 = c0 + d0;  // rows: v0 v2 v1 v3
+    double c1 = R2, d1 = R3; pl16_swap(c1, d1); const double Q1 = c1 + d1;  // rows: v4 v6 v5 v7
+    double c2 = R4, d2 = R5; pl16_swap(c2, d2); const double Q2 = c2 + d2;  // rows: v8 v10 v9 v11
+    double c3 = R6, d3 = z;  pl16_swap(c3, d3); const double Q3 = c3 + d3;  // rows: v12 - - -
+    // 16 -> 8 -> 4 lanes within rows
+    const double P0 = halve8(Q0, Q1);
+    const double P1 = halve8(Q2, Q3);
+    double O = halve4(P0, P1);  // banks: Q0 Q2 Q1 Q3
+    // 4 -> 1
+    O += dpp_mov<DPP_QUAD_2301>(O);
+    O += dpp_mov<DPP_QUAD_1032>(O);
+    return O;
+}
+
+__device__ __forceinline__ int reduce13_index(int lane)
+{
+    const int r = lane >> 4, b = (lane >> 2) & 3;
+    const int base[4] = {0, 8, 4, 12};
+    const int rowm[4] = {0, 2, 1, 3};
+    return base[b] + rowm[r];
+}
+
+__global__ __launch_bounds__(64) void selftest_reduce_kernel(const double* in, double* out)
+{
+    const int lane = threadIdx.x;
+    double v[13];
+    for (int k = 0; k < 13; ++k) v[k] = in[lane * 13 + k];
+    const double s = wave_reduce13(v);
+    const int idx = reduce13_index(lane);
+    if ((lane & 3) == 0 && idx < 13) out[idx] = s;
+}
+
+hipError_t launch_selftest_reduce(const double* in, double* out, hipStream_t st)
+{
+    selftest_reduce_kernel<<<1, 64, 0, st>>>(in, out);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// A3/A4: the sweep.
+//
+// Work unit = (octant o, brick (I,J,K) in the octant's sweep-reflected
+// coordinates, tile of 64 lanes).  Each lane owns VL discrete velocities of
+// the octant that share (xi_y, xi_z) and march through the brick in upwind
+// order: z planes outer, y rows, x cells inner.  The brick's current plane of
+// f lives in registers (plane[v][jj][ii] holds the newest value of that
+// column), so in-brick upwind operands never leave the VGPRs; only the three
+// inflow faces are read from, and the three outflow faces written to, HBM
+// face buffers (double-buffered by brick parity along each axis).  All bricks
+// of one diagonal I+J+K = T are independent and form one launch; the
+// per-velocity upwind system is triangular, so any such order reproduces the
+// sequential sweep exactly.
+//
+// Per cell the lane evaluates nu * f~S from the cell's FP64-derived
+// parameters (wave-uniform, scalar loads) and the separable Gaussian tables,
+// updates f, and accumulates the 13 raw moments of its velocities; one
+// wave reduction per cell gives the tile's partial, written to a
+// deterministic slot partial[o*ntiles + tile][cell].
+// --------------------------------------------------------------------------
+
+template <typename S, int VL, int BX, int BY>
+__global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
+{
+    const int lane = threadIdx.x;
+    int bid = blockIdx.x;
+    // XCD-aware order: consecutive block ids go round-robin over the 8 XCDs,
+    // so regroup them to give each XCD a contiguous range of work units
+    // (neighbouring tiles of the same brick share the cell tables in L2).
+    {
+        const int nb = A.nblocks;
+        const int per = nb / 8, rem = nb % 8;
+        const int xcd = bid % 8, k = bid / 8;
+        const int start = xcd * per + (xcd < rem ? xcd : rem);
+        const int len = per + (xcd < rem ? 1 : 0);
+        if (k < len) bid = start + k;   // always true for a consistent mapping
+    }
+    const int tile = bid % A.ntiles;
+    bid /= A.ntiles;
+    const int bi = bid % A.brick_cnt;
+    const int o = A.oct_base + bid / A.brick_cnt;
+    const int* br = A.bricks + 4 * (A.brick_off + bi);
+    const int I = br[0], J = br[1], K = br[2];
+    const bool px = (o & 1) != 0, py = (o & 2) != 0, pz = (o & 4) != 0;
+    const int slot = tile * 64 + lane;
+    const int N = A.N;
+
+    // lane constants
+    const double* lt = A.lanetab + ((size_t)o * A.slots + slot) * A.lstride;
+    const double xiy_d = lt[0], xiz_d = lt[1];
+    const S xiy = (S)xiy_d, xiz = (S)xiz_d;
+    const S ay = (S)lt[2], az = (S)lt[3];
+    const int vb = (int)lt[4], vc = (int)lt[5];
+    S xix[VL], ax[VL], asum[VL];
+    double wm0[VL], wm1[VL], wm2[VL], wm3[VL];
+    int va[VL], alpha[VL];
+#pragma unroll
+    for (int v = 0; v < VL; ++v) {
+        const double x = lt[LT_SHARED + LT_PER_V * v + 0];
+        const double w = lt[LT_SHARED + LT_PER_V * v + 2];
+        xix[v] = (S)x;
+        ax[v] = (S)lt[LT_SHARED + LT_PER_V * v + 1];
+        asum[v] = ax[v] + ay + az;
+        va[v] = (int)lt[LT_SHARED + LT_PER_V * v + 3];
+        alpha[v] = va[v] + A.mx * (vb + A.my * vc);
+        wm0[v] = w;
+        wm1[v] = w * x;
+        wm2[v] = w * x * x;
+        wm3[v] = w * x * x * x;
+    }
+    const double yz2 = xiy_d * xiy_d + xiz_d * xiz_d;
+    const double xiyy = xiy_d * xiy_d, xizz = xiz_d * xiz_d, xiyz = xiy_d * xiz_d;
+
+    const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
+    const size_t fstride = (size_t)A.slots * VL;
+    const size_t lofs = (size_t)slot * VL;
+    const int ridx = reduce13_index(lane);
+    const bool writer = ((lane & 3) == 0) && ridx < NMOM;
+    double* part = A.partial + ((size_t)(o * A.ntiles + tile) * N) * NMOM;
+
+    S plane[VL][BY][BX];
+#pragma unroll
+    for (int v = 0; v < VL; ++v)
+#pragma unroll
+        for (int jj = 0; jj < BY; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < BX; ++ii) plane[v][jj][ii] = (S)0;
+
+    for (int kk = 0; kk < A.bz; ++kk) {
+        const int kr = K * A.bz + kk;
+        if (kr >= A.nz) break;
+        const int k = pz ? kr : A.nz - 1 - kr;
+#pragma unroll
+        for (int jj = 0; jj < BY; ++jj) {
+            const int jr = J * BY + jj;
+            if (jr >= A.ny) break;
+            const int j = py ? jr : A.ny - 1 - jr;
+#pragma unroll
+            for (int ii = 0; ii < BX; ++ii) {
+                const int ir = I * BX + ii;
+                if (ir >= A.nx) break;
+                const int i = px ? ir : A.nx - 1 - ir;
+                const int cell = i + A.nx * (j + A.ny * k);
+                const uint32_t info = A.cellinfo[cell];
+                if (info & SOLID_BIT) continue;
+
+                // ---- upwind operands
+                S fx[VL], fy[VL], fz[VL];
+                {
+                    const uint32_t code = (info >> (4 * sideX)) & 15u;
+                    if (code == 0) {
+                        if (ii > 0) {
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) fx[v] = plane[v][jj][ii - 1];
+                        } else {
+                            const S* src = A.xface + ((size_t)((o * 2 + ((I - 1) & 1)) * A.nz + kr) * A.ny + jr) * fstride + lofs;
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) fx[v] = src[v];
+                        }
+                    } else {
+                        const int kind = (int)code - 1;
+                        const S rf = (S)(A.kind_wall[kind] ? A.rho_w[(size_t)sideX * N + cell] : A.kind_rho[kind]);
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) fx[v] = rf * A.ghat[(size_t)kind * A.NV + alpha[v]];
+                    }
+                }
+                {
+                    const uint32_t code = (info >> (4 * sideY)) & 15u;
+                    if (code == 0) {
+                        if (jj > 0) {
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) fy[v] = plane[v][jj - 1][ii];
+                        } else {
+                            const S* src = A.yface + ((size_t)((o * 2 + ((J - 1) & 1)) * A.nz + kr) * A.nx + ir) * fstride + lofs;
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) fy[v] = src[v];
+                        }
+                    } else {
+                        const int kind = (int)code - 1;
+                        const S rf = (S)(A.kind_wall[kind] ? A.rho_w[(size_t)sideY * N + cell] : A.kind_rho[kind]);
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) fy[v] = rf * A.ghat[(size_t)kind * A.NV + alpha[v]];
+                    }
+                }
+                {
+                    const uint32_t code = (info >> (4 * sideZ)) & 15u;
+                    if (code == 0) {
+                        if (kk > 0) {
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) fz[v] = plane[v][jj][ii];
+                        } else {
+                            const S* src = A.zface + ((size_t)((o * 2 + ((K - 1) & 1)) * A.ny + jr) * A.nx + ir) * fstride + lofs;
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) fz[v] = src[v];
+                        }
+                    } else if (code == CODE_SPECULAR) {
+                        const S* src = A.spec + ((size_t)((o & 3) * A.ny + j) * A.nx + i) * fstride + lofs;
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) fz[v] = src[v];
+                    } else {
+                        const int kind = (int)code - 1;
+                        const S rf = (S)(A.kind_wall[kind] ? A.rho_w[(size_t)sideZ * N + cell] : A.kind_rho[kind]);
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) fz[v] = rf * A.ghat[(size_t)kind * A.NV + alpha[v]];
+                    }
+                }
+
+                // ---- equilibrium (wave-uniform cell parameters) and update
+                const S* P = A.params + (size_t)cell * PSTRIDE;
+                const S nu = P[P_NU], Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
+                const S L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
+                const S qx = P[P_QX], qy = P[P_QY], qz = P[P_QZ], tT = P[P_TWO_T];
+                const S* E = A.etab + (size_t)cell * A.MT;
+                const S gyz = E[A.mx + vb] * E[A.mx + A.my + vc];
+                const S cy = xiy - Uy, cz = xiz - Uz;
+                const S cyz2 = cy * cy + cz * cz;
+                const S Lyz = L0 + L2 * cy + L3 * cz;
+                const S Qyz = qy * cy + qz * cz;
+                double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) {
+                    const S cx = xix[v] - Ux;
+                    const S c2 = cx * cx + cyz2;
+                    const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
+                    const S nfs = gyz * E[va[v]] * poly;
+                    const S num = ax[v] * fx[v] + ay * fy[v] + az * fz[v] + nfs;
+                    const S f = num / (asum[v] + nu);
+                    plane[v][jj][ii] = f;
+                    const double fd = (double)f;
+                    u0 += wm0[v] * fd;
+                    u1 += wm1[v] * fd;
+                    u2 += wm2[v] * fd;
+                    u3 += wm3[v] * fd;
+                }
+
+                // ---- outflow faces for the downstream bricks
+                if (ii == BX - 1 && I < A.nbx - 1) {
+                    S* dst = A.xface + ((size_t)((o * 2 + (I & 1)) * A.nz + kr) * A.ny + jr) * fstride + lofs;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                }
+                if (jj == BY - 1 && J < A.nby - 1) {
+                    S* dst = A.yface + ((size_t)((o * 2 + (J & 1)) * A.nz + kr) * A.nx + ir) * fstride + lofs;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                }
+                if (kk == A.bz - 1 && K < A.nbz - 1) {
+                    S* dst = A.zface + ((size_t)((o * 2 + (K & 1)) * A.ny + jr) * A.nx + ir) * fstride + lofs;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                }
+                if (A.spec_on && !pz && k == 0) {
+                    S* dst = A.spec + ((size_t)((o & 3) * A.ny + j) * A.nx + i) * fstride + lofs;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                }
+
+                // ---- 13 raw moments of this tile at this cell
+                double m[13];
+                m[0] = u0;
+                m[1] = u1;
+                m[2] = xiy_d * u0;
+                m[3] = xiz_d * u0;
+                m[4] = u2;
+                m[5] = xiyy * u0;
+                m[6] = xizz * u0;
+                m[7] = xiy_d * u1;
+                m[8] = xiz_d * u1;
+                m[9] = xiyz * u0;
+                m[10] = u3 + yz2 * u1;
+                const double t2 = u2 + yz2 * u0;
+                m[11] = xiy_d * t2;
+                m[12] = xiz_d * t2;
+                const double tot = wave_reduce13(m);
+                if (writer) part[(size_t)cell * NMOM + ridx] = tot;
+            }
+        }
+    }
+}
+
+// instantiated variants: (precision, VL, BX, BY)
+#define DVM_SWEEP_VARIANTS(X) \
+    X(double, 1, 4, 4) X(double, 2, 4, 4) X(double, 4, 4, 4) \
+    X(double, 1, 8, 8) X(double, 2, 8, 4) X(double, 1, 8, 4) \
+    X(float, 1, 4, 4) X(float, 2, 4, 4) X(float, 4, 4, 4) \
+    X(float, 1, 8, 8) X(float, 2, 8, 4) X(float, 2, 8, 8)
+
+bool sweep_variant_available(int prec, int vl, int bx, int by)
+{
+#define X(T, V, BXX, BYY) \
+    if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) return true;
+    DVM_SWEEP_VARIANTS(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_sweep(int prec, int vl, int bx, int by, const void* args, hipStream_t st)
+{
+#define X(T, V, BXX, BYY)                                                                  \
+    if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) {            \
+        const SweepArgs<T>& a = *(const SweepArgs<T>*)args;                                \
+        sweep_kernel<T, V, BXX, BYY><<<a.nblocks, 64, 0, st>>>(a);                          \
+        return hipGetLastError();                                                          \
+    }
+    DVM_SWEEP_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// --------------------------------------------------------------------------
+// A5: finalisation
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, const double* __restrict__ partial,
+                                                       int ntiles, const double* __restrict__ gout,
+                                                       double* __restrict__ Wn, double* __restrict__ qn,
+                                                       double* __restrict__ rwn, double* __restrict__ blockmass,
+                                                       int* __restrict__ flag)
+{
+    __shared__ double red[256];
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = C.N;
+    double mass = 0.0;
+    if (cell < N) {
+        const uint32_t info = D.cellinfo[cell];
+        if (info & SOLID_BIT) {
+            for (int v = 0; v < 5; ++v) Wn[(size_t)v * N + cell] = 0.0;
+            for (int v = 0; v < 3; ++v) qn[(size_t)v * N + cell] = 0.0;
+            for (int s = 0; s < 6; ++s) rwn[(size_t)s * N + cell] = 0.0;
+        } else {
+            double m[13];
+            for (int k = 0; k < 13; ++k) m[k] = 0.0;
+            double hp[3] = {0, 0, 0}, hm[3] = {0, 0, 0};  // half-range mass fluxes
+            for (int o = 0; o < 8; ++o) {
+                double g1 = 0, g2 = 0, g3 = 0;
+                for (int t = 0; t < ntiles; ++t) {
+                    const double* p = partial + ((size_t)(o * ntiles + t) * N + cell) * NMOM;
+#pragma unroll
+                    for (int k = 0; k < 13; ++k) m[k] += p[k];
+                    g1 += p[1];
+                    g2 += p[2];
+                    g3 += p[3];
+                }
+                if (o & 1) hp[0] += g1; else hm[0] += g1;
+                if (o & 2) hp[1] += g2; else hm[1] += g2;
+                if (o & 4) hp[2] += g3; else hm[2] += g3;
+            }
+            const double rho = m[0];
+            if (!(rho > 0.0) || !isfinite(rho)) atomicOr(flag, 4);
+            const double Ux = m[1] / rho, Uy = m[2] / rho, Uz = m[3] / rho;
+            const double trM = m[4] + m[5] + m[6];
+            Wn[cell] = rho;
+            Wn[(size_t)N + cell] = m[1];
+            Wn[(size_t)2 * N + cell] = m[2];
+            Wn[(size_t)3 * N + cell] = m[3];
+            Wn[(size_t)4 * N + cell] = 0.5 * trM;
+            // q_i = 1/2 sum w c_i |c|^2 f, c = xi - U^{n+1}, expanded in raw moments
+            const double U[3] = {Ux, Uy, Uz};
+            const double U2 = Ux * Ux + Uy * Uy + Uz * Uz;
+            const double Mij[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+            for (int d = 0; d < 3; ++d) {
+                const double UM = Mij[d][0] * Ux + Mij[d][1] * Uy + Mij[d][2] * Uz;
+                const double val = m[10 + d] - 2.0 * UM - U[d] * trM + 2.0 * rho * U[d] * U2;
+                qn[(size_t)d * N + cell] = 0.5 * val;
+            }
+            for (int s = 0; s < 6; ++s) {
+                const uint32_t code = (info >> (4 * s)) & 15u;
+                double r = 0.0;
+                if (code != 0 && code != CODE_SPECULAR && C.kind_wall[code - 1]) {
+                    const int d = s >> 1;
+                    // particles hitting side s move along -n: s odd (upper) -> xi_d > 0
+                    const double flux = (s & 1) ? hp[d] : -hm[d];
+                    r = flux / gout[(code - 1) * 6 + s];
+                }
+                rwn[(size_t)s * N + cell] = r;
+            }
+            mass = rho;
+        }
+    }
+    red[threadIdx.x] = mass;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blockmass[blockIdx.x] = red[0];
+}
+
+hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
+                           const double* gout, double* Wn, double* qn, double* rwn, double* blockmass,
+                           int nblocks, int* flag, hipStream_t st)
+{
+    finalize_kernel<<<nblocks, 256, 0, st>>>(C, D, partial, ntiles, gout, Wn, qn, rwn, blockmass, flag);
+    return hipGetLastError();
+}
+
+// deterministic block sum of n values (fixed strided order + fixed tree)
+__device__ double block_sum_fixed(const double* x, int n, double* red)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void scale_residual_kernel(Consts C, DevPtrs D, double M0,
+                                                             const double* __restrict__ blockmass, int nbm,
+                                                             double* __restrict__ Wn, double* __restrict__ qn,
+                                                             double* __restrict__ rwn, const double* __restrict__ Wo,
+                                                             double* __restrict__ respart)
+{
+    __shared__ double red[256];
+    const double total = block_sum_fixed(blockmass, nbm, red);
+    const double s = C.closed ? M0 / (total * C.dV) : 1.0;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = C.N;
+    double dd[5] = {0, 0, 0, 0, 0}, nn[5] = {0, 0, 0, 0, 0};
+    if (cell < N && !(D.cellinfo[cell] & SOLID_BIT)) {
+        for (int v = 0; v < 5; ++v) {
+            const double w = Wn[(size_t)v * N + cell] * s;
+            Wn[(size_t)v * N + cell] = w;
+            const double d = w - Wo[(size_t)v * N + cell];
+            dd[v] = d * d;
+            nn[v] = w * w;
+        }
+        if (C.closed) {
+            for (int v = 0; v < 3; ++v) qn[(size_t)v * N + cell] *= s;
+            for (int v = 0; v < 6; ++v) rwn[(size_t)v * N + cell] *= s;
+        }
+    }
+    for (int v = 0; v < 10; ++v) {
+        red[threadIdx.x] = v < 5 ? dd[v] : nn[v - 5];
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) respart[(size_t)blockIdx.x * 10 + v] = red[0];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_scale_residual(const Consts& C, const DevPtrs& D, double M0, const double* blockmass,
+                                 int nbm, double* Wn, double* qn, double* rwn, const double* Wo,
+                                 double* respart, int nblocks, hipStream_t st)
+{
+    scale_residual_kernel<<<nblocks, 256, 0, st>>>(C, D, M0, blockmass, nbm, Wn, qn, rwn, Wo, respart);
+    return hipGetLastError();
+}
+
+// out[0..4]: residual per field, out[5]: total mass before rescaling (sum rho),
+// out[6]: error flag
+__global__ __launch_bounds__(256) void residual_final_kernel(const double* __restrict__ respart, int nblocks,
+                                                             const double* __restrict__ blockmass, int nbm,
+                                                             double* __restrict__ out, const int* __restrict__ flag)
+{
+    __shared__ double red[256];
+    double vals[10];
+    for (int v = 0; v < 10; ++v) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += respart[(size_t)b * 10 + v];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        vals[v] = red[0];
+        __syncthreads();
+    }
+    const double mass = block_sum_fixed(blockmass, nbm, red);
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < 5; ++v) {
+            const double dn = vals[v], nn = vals[5 + v];
+            out[v] = nn > 0 ? sqrt(dn / nn) : (dn > 0 ? sqrt(dn) : 0.0);
+        }
+        out[5] = mass;
+        out[6] = (double)(*flag);
+    }
+}
+
+hipError_t launch_residual_final(const double* respart, int nblocks, const double* blockmass, int nbm,
+                                 double* out, const int* flag, hipStream_t st)
+{
+    residual_final_kernel<<<1, 256, 0, st>>>(respart, nblocks, blockmass, nbm, out, flag);
+    return hipGetLastError();
+}
+
+}  // namespace dvm

@@ -1,0 +1,841 @@
+// Host runtime of libdvm_hip.so: the C ABI declared in include/dvm.h.
+//
+// The runtime owns no device memory: the caller lends one workspace and the
+// runtime carves it into the buffers below.  Each outer iteration is a fixed
+// sequence of launches on the context's stream (parameters, one sweep launch
+// per brick diagonal, finalisation, rescaling/residual) followed by one
+// 64-byte device-to-host copy of the residual, which is the only host
+// synchronisation per iteration.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "dvm.h"
+#include "dvm_internal.h"
+
+using namespace dvm;
+
+namespace {
+
+thread_local std::string g_err;
+
+dvm_status fail(dvm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(DVM_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int env_int(const char* name, int dflt)
+{
+    const char* s = getenv(name);
+    if (!s || !*s) return dflt;
+    return atoi(s);
+}
+
+}  // namespace
+
+struct dvm_ctx {
+    dvm_grid g;
+    dvm_vgrid vg;
+    dvm_gas gas;
+    int prec;
+    hipStream_t stream;
+    dvm_face_bc faces[6];
+    std::vector<uint8_t> solid;
+    double solid_u[3] = {0, 0, 0};
+    double solid_T = 1.0;
+    int closed = 1;
+
+    // derived
+    int N = 0, NV = 0, nfluid = 0;
+    double dx[3];
+    int hsplit[3];  // number of nodes with xi < 0 along each axis
+    int VL = 2, BX = 4, BY = 4, BZ = 8;
+    int nbx = 0, nby = 0, nbz = 0;
+    int ntiles = 0, slots = 0, lstride = 0;
+    std::vector<int> bricks;           // I, J, K, 0 per brick, grouped by diagonal
+    std::vector<int> diag_off, diag_cnt;
+    int ndiag = 0;
+    bool spec_on = false;
+
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    struct {
+        size_t axes, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
+            partial, xface, yface, zface, spec, blockmass, respart, out, flag, end;
+    } off;
+    size_t Ssz = 8;
+    int nbF = 0;  // blocks of the per-cell kernels (256 threads)
+
+    // state
+    int cur = 0;
+    bool initialized = false;
+    double M0 = 0;
+    double res[5] = {0, 0, 0, 0, 0};
+    std::vector<uint32_t> cellinfo;
+    double kind_rho[8] = {0};
+    int kind_wall[8] = {0};
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double t_params = 0, t_sweep = 0, t_final = 0;
+    int t_iters = 0;
+
+    template <typename T>
+    T* P(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+};
+
+namespace {
+
+void derive_schedule(dvm_ctx* c)
+{
+    c->N = c->g.nx * c->g.ny * c->g.nz;
+    c->NV = c->vg.m[0] * c->vg.m[1] * c->vg.m[2];
+    c->dx[0] = c->g.lx / c->g.nx;
+    c->dx[1] = c->g.ly / c->g.ny;
+    c->dx[2] = c->g.lz / c->g.nz;
+    for (int d = 0; d < 3; ++d) c->hsplit[d] = c->vg.m[d] / 2;
+    c->Ssz = c->prec == DVM_F64 ? 8 : 4;
+
+    // velocities per lane, brick shape (overridable for tuning)
+    const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
+    int vl = c->prec == DVM_F64 ? 2 : 4;
+    if (nax % vl) vl = (nax % 2) ? 1 : 2;
+    vl = env_int("DVM_VL", vl);
+    int bx = env_int("DVM_BX", 4), by = env_int("DVM_BY", 4);
+    if (!sweep_variant_available(c->prec, vl, bx, by)) { vl = 1; bx = 4; by = 4; }
+    c->VL = vl;
+    c->BX = bx;
+    c->BY = by;
+    c->BZ = env_int("DVM_BZ", 8);
+    if (c->BZ < 1) c->BZ = 1;
+    c->nbx = (c->g.nx + c->BX - 1) / c->BX;
+    c->nby = (c->g.ny + c->BY - 1) / c->BY;
+    c->nbz = (c->g.nz + c->BZ - 1) / c->BZ;
+
+    // tiles: lanes per octant = ceil(na_x / VL) * na_y * na_z
+    int nt = 0;
+    for (int o = 0; o < 8; ++o) {
+        int na[3];
+        for (int d = 0; d < 3; ++d) na[d] = ((o >> d) & 1) ? c->vg.m[d] - c->hsplit[d] : c->hsplit[d];
+        const int ng = (na[0] + c->VL - 1) / c->VL;
+        const int lanes = ng * na[1] * na[2];
+        const int t = (lanes + 63) / 64;
+        if (t > nt) nt = t;
+    }
+    c->ntiles = nt;
+    c->slots = nt * 64;
+    c->lstride = LT_SHARED + LT_PER_V * c->VL;
+    if (c->lstride & 1) c->lstride++;
+
+    // bricks grouped by diagonal I + J + K
+    c->ndiag = c->nbx + c->nby + c->nbz - 2;
+    c->bricks.clear();
+    c->diag_off.assign(c->ndiag, 0);
+    c->diag_cnt.assign(c->ndiag, 0);
+    for (int T = 0; T < c->ndiag; ++T) {
+        c->diag_off[T] = (int)(c->bricks.size() / 4);
+        for (int K = 0; K < c->nbz; ++K)
+            for (int J = 0; J < c->nby; ++J) {
+                const int I = T - J - K;
+                if (I < 0 || I >= c->nbx) continue;
+                c->bricks.push_back(I);
+                c->bricks.push_back(J);
+                c->bricks.push_back(K);
+                c->bricks.push_back(0);
+            }
+        c->diag_cnt[T] = (int)(c->bricks.size() / 4) - c->diag_off[T];
+    }
+    c->nbF = (c->N + 255) / 256;
+}
+
+void layout(dvm_ctx* c)
+{
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t N = (size_t)c->N, S = c->Ssz;
+    const size_t fst = (size_t)c->slots * c->VL;
+    c->off.axes = take(sizeof(double) * 2 * 3 * MAXM);
+    c->off.cellinfo = take(sizeof(uint32_t) * N);
+    c->off.bricks = take(sizeof(int) * c->bricks.size());
+    c->off.lanetab = take(sizeof(double) * 8 * (size_t)c->slots * c->lstride);
+    c->off.kstate = take(sizeof(double) * 4 * NKIND);
+    c->off.ghat = take(S * NKIND * (size_t)c->NV);
+    c->off.ghat64 = take(sizeof(double) * NKIND * (size_t)c->NV);
+    c->off.gout = take(sizeof(double) * 6 * NKIND);
+    c->off.W = take(sizeof(double) * 2 * 5 * N);
+    c->off.q = take(sizeof(double) * 2 * 3 * N);
+    c->off.rw = take(sizeof(double) * 2 * 6 * N);
+    c->off.params = take(S * PSTRIDE * N);
+    c->off.etab = take(S * (size_t)(c->vg.m[0] + c->vg.m[1] + c->vg.m[2]) * N);
+    c->off.partial = take(sizeof(double) * NMOM * 8 * (size_t)c->ntiles * N);
+    c->off.xface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.ny * fst);
+    c->off.yface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.nx * fst);
+    c->off.zface = take(S * 8 * 2 * (size_t)c->g.ny * c->g.nx * fst);
+    c->off.spec = take(c->spec_on ? S * 4 * (size_t)c->g.ny * c->g.nx * fst : 0);
+    c->off.blockmass = take(sizeof(double) * c->nbF);
+    c->off.respart = take(sizeof(double) * 10 * c->nbF);
+    c->off.out = take(sizeof(double) * 8);
+    c->off.flag = take(sizeof(int) * 4);
+    c->off.end = o;
+}
+
+Consts make_consts(const dvm_ctx* c)
+{
+    Consts C;
+    memset(&C, 0, sizeof C);
+    C.nx = c->g.nx;
+    C.ny = c->g.ny;
+    C.nz = c->g.nz;
+    C.N = c->N;
+    C.mx = c->vg.m[0];
+    C.my = c->vg.m[1];
+    C.mz = c->vg.m[2];
+    C.MT = C.mx + C.my + C.mz;
+    C.NV = c->NV;
+    const double w = c->gas.omega;
+    const double kappa = 15.0 * sqrt(M_PI) / ((5.0 - 2.0 * w) * (7.0 - 2.0 * w));
+    C.kappa_kn = kappa * c->gas.kn;
+    C.omega = w;
+    C.pr = c->gas.pr;
+    C.correct = c->gas.conservative_correction;
+    C.closed = c->closed;
+    C.dV = c->dx[0] * c->dx[1] * c->dx[2];
+    for (int k = 0; k < 8; ++k) {
+        C.kind_rho[k] = c->kind_rho[k];
+        C.kind_wall[k] = c->kind_wall[k];
+    }
+    return C;
+}
+
+DevPtrs make_ptrs(const dvm_ctx* c)
+{
+    DevPtrs D;
+    D.xi = c->P<double>(c->off.axes);
+    D.wt = c->P<double>(c->off.axes) + 3 * MAXM;
+    D.cellinfo = c->P<uint32_t>(c->off.cellinfo);
+    D.bricks = c->P<int>(c->off.bricks);
+    D.lanetab = c->P<double>(c->off.lanetab);
+    return D;
+}
+
+void build_cellinfo(dvm_ctx* c)
+{
+    const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
+    c->cellinfo.assign(c->N, 0);
+    for (int s = 0; s < 6; ++s) {
+        c->kind_wall[s] = c->faces[s].kind == DVM_BC_WALL;
+        c->kind_rho[s] = c->faces[s].kind == DVM_BC_FREE ? c->faces[s].rho : 0.0;
+    }
+    c->kind_wall[6] = 1;
+    c->kind_rho[6] = 0.0;
+    c->nfluid = 0;
+    auto is_solid = [&](int i, int j, int k) {
+        return !c->solid.empty() && c->solid[i + nx * (j + ny * k)] != 0;
+    };
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int id = i + nx * (j + ny * k);
+                uint32_t info = 0;
+                if (is_solid(i, j, k)) {
+                    info = SOLID_BIT;
+                } else {
+                    c->nfluid++;
+                    for (int s = 0; s < 6; ++s) {
+                        int p[3] = {i, j, k};
+                        const int ext[3] = {nx, ny, nz};
+                        const int d = s >> 1;
+                        p[d] += (s & 1) ? 1 : -1;
+                        uint32_t code;
+                        if (p[d] < 0 || p[d] >= ext[d]) {
+                            code = c->faces[s].kind == DVM_BC_SPECULAR ? CODE_SPECULAR : (uint32_t)(s + 1);
+                        } else if (is_solid(p[0], p[1], p[2])) {
+                            code = 7;
+                        } else {
+                            code = 0;
+                        }
+                        info |= code << (4 * s);
+                    }
+                }
+                c->cellinfo[id] = info;
+            }
+}
+
+std::vector<double> build_lanetab(const dvm_ctx* c, const std::vector<double> xi[3])
+{
+    std::vector<double> lt((size_t)8 * c->slots * c->lstride, 0.0);
+    for (int o = 0; o < 8; ++o) {
+        int na[3];
+        bool pos[3];
+        for (int d = 0; d < 3; ++d) {
+            pos[d] = ((o >> d) & 1) != 0;
+            na[d] = pos[d] ? c->vg.m[d] - c->hsplit[d] : c->hsplit[d];
+        }
+        const int ng = (na[0] + c->VL - 1) / c->VL;
+        const int lanes = ng * na[1] * na[2];
+        auto node = [&](int d, int local) {
+            return pos[d] ? c->hsplit[d] + local : c->hsplit[d] - 1 - local;
+        };
+        auto weight = [&](int d, int a) {
+            const int M = c->vg.m[d];
+            const double h = 2.0 * c->vg.vmax[d] / (M - 1);
+            return (a == 0 || a == M - 1) ? 0.5 * h : h;
+        };
+        for (int s = 0; s < c->slots; ++s) {
+            double* L = &lt[((size_t)o * c->slots + s) * c->lstride];
+            const bool lane_on = s < lanes && na[1] > 0 && na[2] > 0 && na[0] > 0;
+            const int ss = lane_on ? s : 0;
+            int g = 0, bl = 0, cl = 0;
+            if (na[0] > 0 && na[1] > 0 && na[2] > 0) {
+                g = ss % ng;
+                bl = (ss / ng) % na[1];
+                cl = ss / (ng * na[1]);
+            }
+            const int b = na[1] > 0 ? node(1, bl) : 0, cc = na[2] > 0 ? node(2, cl) : 0;
+            L[0] = xi[1][b];
+            L[1] = xi[2][cc];
+            L[2] = fabs(xi[1][b]) / c->dx[1];
+            L[3] = fabs(xi[2][cc]) / c->dx[2];
+            L[4] = b;
+            L[5] = cc;
+            for (int v = 0; v < c->VL; ++v) {
+                int al = g * c->VL + v;
+                bool on = lane_on && al < na[0];
+                if (al >= na[0]) al = na[0] > 0 ? na[0] - 1 : 0;
+                const int a = na[0] > 0 ? node(0, al) : 0;
+                double* Lv = L + LT_SHARED + LT_PER_V * v;
+                Lv[0] = xi[0][a];
+                Lv[1] = fabs(xi[0][a]) / c->dx[0];
+                Lv[2] = on ? weight(0, a) * weight(1, b) * weight(2, cc) : 0.0;
+                Lv[3] = a;
+            }
+        }
+    }
+    return lt;
+}
+
+dvm_status check_ctx(dvm_ctx* c)
+{
+    if (!c) return fail(DVM_ERR_ARG, "null context");
+    return DVM_OK;
+}
+
+// one outer iteration; writes the candidate state into slot 1-cur and the
+// residual summary into out[0..7] on the host
+dvm_status run_iteration(dvm_ctx* c, double* hout)
+{
+    const Consts C = make_consts(c);
+    const DevPtrs D = make_ptrs(c);
+    const int cur = c->cur, nxt = 1 - cur;
+    const size_t N = c->N;
+    double* W = c->P<double>(c->off.W);
+    double* q = c->P<double>(c->off.q);
+    double* rw = c->P<double>(c->off.rw);
+    int* flag = c->P<int>(c->off.flag);
+    hipStream_t st = c->stream;
+
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[0], st));
+    HIPCHK(launch_params(C, D, W + cur * 5 * N, q + cur * 3 * N, c->ws + c->off.params,
+                         c->ws + c->off.etab, c->prec, flag, st));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[1], st));
+
+    // sweep: one launch per brick diagonal; with a specular plane the
+    // octants moving towards it go first so that the others can read their
+    // mirror images
+    const int phases = c->spec_on ? 2 : 1;
+    for (int ph = 0; ph < phases; ++ph) {
+        for (int T = 0; T < c->ndiag; ++T) {
+            const int cnt = c->diag_cnt[T];
+            if (cnt == 0) continue;
+            auto fill = [&](auto& a) {
+                using S = typename std::remove_pointer<decltype(a.xface)>::type;
+                a.params = c->P<S>(c->off.params);
+                a.etab = c->P<S>(c->off.etab);
+                a.cellinfo = c->P<uint32_t>(c->off.cellinfo);
+                a.rho_w = rw + cur * 6 * N;
+                a.ghat = c->P<S>(c->off.ghat);
+                a.lanetab = c->P<double>(c->off.lanetab);
+                a.bricks = c->P<int>(c->off.bricks);
+                a.xface = c->P<S>(c->off.xface);
+                a.yface = c->P<S>(c->off.yface);
+                a.zface = c->P<S>(c->off.zface);
+                a.spec = c->spec_on ? c->P<S>(c->off.spec) : nullptr;
+                a.partial = c->P<double>(c->off.partial);
+                a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.N = c->N;
+                a.mx = c->vg.m[0]; a.my = c->vg.m[1]; a.MT = C.MT; a.NV = c->NV;
+                a.nbx = c->nbx; a.nby = c->nby; a.nbz = c->nbz; a.bz = c->BZ;
+                a.ntiles = c->ntiles; a.slots = c->slots; a.lstride = c->lstride;
+                a.brick_off = c->diag_off[T]; a.brick_cnt = cnt;
+                a.oct_base = c->spec_on ? 4 * ph : 0;
+                a.noct = c->spec_on ? 4 : 8;
+                a.spec_on = c->spec_on ? 1 : 0;
+                a.nblocks = a.noct * cnt * c->ntiles;
+                for (int k = 0; k < 8; ++k) { a.kind_rho[k] = c->kind_rho[k]; a.kind_wall[k] = c->kind_wall[k]; }
+            };
+            hipError_t e;
+            if (c->prec == DVM_F64) {
+                SweepArgs<double> a;
+                fill(a);
+                e = launch_sweep(0, c->VL, c->BX, c->BY, &a, st);
+            } else {
+                SweepArgs<float> a;
+                fill(a);
+                e = launch_sweep(1, c->VL, c->BX, c->BY, &a, st);
+            }
+            if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+        }
+    }
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[2], st));
+
+    double* blockmass = c->P<double>(c->off.blockmass);
+    double* respart = c->P<double>(c->off.respart);
+    double* out = c->P<double>(c->off.out);
+    HIPCHK(launch_finalize(C, D, c->P<double>(c->off.partial), c->ntiles, c->P<double>(c->off.gout),
+                           W + nxt * 5 * N, q + nxt * 3 * N, rw + nxt * 6 * N, blockmass, c->nbF, flag,
+                           st));
+    HIPCHK(launch_scale_residual(C, D, c->M0, blockmass, c->nbF, W + nxt * 5 * N, q + nxt * 3 * N,
+                                 rw + nxt * 6 * N, W + cur * 5 * N, respart, c->nbF, st));
+    HIPCHK(launch_residual_final(respart, c->nbF, blockmass, c->nbF, out, flag, st));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[3], st));
+    HIPCHK(hipMemcpyAsync(hout, out, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (c->timing) {
+        float a = 0, b = 0, d = 0;
+        HIPCHK(hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+        HIPCHK(hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
+        HIPCHK(hipEventElapsedTime(&d, c->ev[2], c->ev[3]));
+        c->t_params += a;
+        c->t_sweep += b;
+        c->t_final += d;
+        c->t_iters++;
+    }
+    return DVM_OK;
+}
+
+dvm_status upload_initial(dvm_ctx* c, const std::vector<double>& Wh)
+{
+    const size_t N = c->N;
+    hipStream_t st = c->stream;
+    c->cur = 0;
+    double* W = c->P<double>(c->off.W);
+    double* q = c->P<double>(c->off.q);
+    double* rw = c->P<double>(c->off.rw);
+    int* flag = c->P<int>(c->off.flag);
+    HIPCHK(hipMemcpyAsync(W, Wh.data(), sizeof(double) * 5 * N, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(q, 0, sizeof(double) * 3 * N, st));
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+    const Consts C = make_consts(c);
+    const DevPtrs D = make_ptrs(c);
+    HIPCHK(launch_params(C, D, W, q, c->ws + c->off.params, c->ws + c->off.etab, c->prec, flag, st));
+    HIPCHK(launch_wall_init(C, D, c->ws + c->off.params, c->ws + c->off.etab, c->P<double>(c->off.ghat64),
+                            c->P<double>(c->off.gout), rw, c->prec, st));
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hflag) return fail(DVM_ERR_NONPHYSICAL, "non-physical initial state (flag %d)", hflag);
+    double m = 0;
+    for (size_t i = 0; i < N; ++i)
+        if (!(c->cellinfo[i] & SOLID_BIT)) m += Wh[i];
+    c->M0 = m * c->dx[0] * c->dx[1] * c->dx[2];
+    for (int v = 0; v < 5; ++v) c->res[v] = 0;
+    c->initialized = true;
+    return DVM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dvm_last_error(void) { return g_err.c_str(); }
+
+dvm_status dvm_create(const dvm_grid* grid, const dvm_vgrid* vgrid, const dvm_gas* gas, int precision,
+                      void* hip_stream, dvm_ctx** out)
+{
+    if (!out) return fail(DVM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid || !vgrid || !gas) return fail(DVM_ERR_ARG, "NULL argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(DVM_ERR_ARG, "grid sizes must be >= 1");
+    if (!(grid->lx > 0) || !(grid->ly > 0) || !(grid->lz > 0)) return fail(DVM_ERR_ARG, "lengths must be > 0");
+    if ((double)grid->nx * grid->ny * grid->nz > 2.0e9) return fail(DVM_ERR_ARG, "too many cells");
+    for (int d = 0; d < 3; ++d) {
+        if (vgrid->m[d] < 2 || vgrid->m[d] > MAXM) return fail(DVM_ERR_ARG, "velocity nodes must be in [2, %d]", MAXM);
+        if (!(vgrid->vmax[d] > 0)) return fail(DVM_ERR_ARG, "vmax must be > 0");
+    }
+    if (!(gas->kn > 0) || !(gas->pr > 0) || !(gas->omega >= 0) || !(gas->omega < 2.5))
+        return fail(DVM_ERR_ARG, "bad gas constants (kn > 0, pr > 0, 0 <= omega < 2.5)");
+    if (precision != DVM_F64 && precision != DVM_F32) return fail(DVM_ERR_ARG, "precision must be DVM_F64 or DVM_F32");
+    dvm_ctx* c = new dvm_ctx();
+    c->g = *grid;
+    c->vg = *vgrid;
+    c->gas = *gas;
+    c->prec = precision;
+    c->stream = (hipStream_t)hip_stream;
+    for (int s = 0; s < 6; ++s) {
+        c->faces[s].kind = DVM_BC_WALL;
+        c->faces[s].u[0] = c->faces[s].u[1] = c->faces[s].u[2] = 0.0;
+        c->faces[s].T = 1.0;
+        c->faces[s].rho = 1.0;
+    }
+    derive_schedule(c);
+    *out = c;
+    return DVM_OK;
+}
+
+dvm_status dvm_set_face_bc(dvm_ctx* c, int face, const dvm_face_bc* bc)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "boundary conditions must be set before binding the workspace");
+    if (face < 0 || face > 5 || !bc) return fail(DVM_ERR_ARG, "face must be 0..5");
+    if (bc->kind < 0 || bc->kind > 2) return fail(DVM_ERR_ARG, "bad boundary kind");
+    if (bc->kind != DVM_BC_SPECULAR && !(bc->T > 0)) return fail(DVM_ERR_ARG, "T must be > 0");
+    if (bc->kind == DVM_BC_FREE && !(bc->rho > 0)) return fail(DVM_ERR_ARG, "free-stream rho must be > 0");
+    if (bc->kind == DVM_BC_SPECULAR) {
+        if (face != 4) return fail(DVM_ERR_ARG, "a specular plane is supported on the z- face only");
+        if (c->vg.m[2] % 2) return fail(DVM_ERR_ARG, "a specular plane needs an even velocity count along z");
+    }
+    c->faces[face] = *bc;
+    c->spec_on = c->faces[4].kind == DVM_BC_SPECULAR;
+    return DVM_OK;
+}
+
+dvm_status dvm_set_solid(dvm_ctx* c, const unsigned char* mask, const double u_wall[3], double T_wall)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "the solid must be set before binding the workspace");
+    if (!mask) {
+        c->solid.clear();
+        return DVM_OK;
+    }
+    if (!(T_wall > 0)) return fail(DVM_ERR_ARG, "T_wall must be > 0");
+    c->solid.assign(mask, mask + c->N);
+    if (u_wall) for (int d = 0; d < 3; ++d) c->solid_u[d] = u_wall[d];
+    c->solid_T = T_wall;
+    return DVM_OK;
+}
+
+dvm_status dvm_set_closed(dvm_ctx* c, int closed)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    c->closed = closed ? 1 : 0;
+    return DVM_OK;
+}
+
+dvm_status dvm_required_workspace(dvm_ctx* c, size_t* bytes)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!bytes) return fail(DVM_ERR_ARG, "bytes is NULL");
+    layout(c);
+    *bytes = c->off.end;
+    return DVM_OK;
+}
+
+dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "workspace already bound");
+    if (!ptr) return fail(DVM_ERR_ARG, "workspace pointer is NULL");
+    if ((uintptr_t)ptr & 255) return fail(DVM_ERR_ARG, "workspace must be 256-byte aligned");
+    layout(c);
+    if (bytes < c->off.end) return fail(DVM_ERR_OOM, "workspace too small: %zu < %zu bytes", bytes, c->off.end);
+    c->ws = (char*)ptr;
+    c->ws_bytes = bytes;
+    hipStream_t st = c->stream;
+
+    // velocity axes (exactly antisymmetric nodes), trapezoid weights
+    std::vector<double> axes(2 * 3 * MAXM, 0.0);
+    std::vector<double> xi[3];
+    for (int d = 0; d < 3; ++d) {
+        const int M = c->vg.m[d];
+        const double V = c->vg.vmax[d];
+        const double half = V / (M - 1), h = 2.0 * V / (M - 1);
+        xi[d].resize(M);
+        for (int a = 0; a < M; ++a) {
+            xi[d][a] = (double)(2 * a - (M - 1)) * half;
+            axes[d * MAXM + a] = xi[d][a];
+            axes[3 * MAXM + d * MAXM + a] = (a == 0 || a == M - 1) ? 0.5 * h : h;
+        }
+    }
+    build_cellinfo(c);
+    std::vector<double> lt = build_lanetab(c, xi);
+    std::vector<double> ks(4 * NKIND, 0.0);
+    for (int k = 0; k < NKIND; ++k) {
+        const double* u = k < 6 ? c->faces[k].u : c->solid_u;
+        double T = k < 6 ? c->faces[k].T : c->solid_T;
+        if (!(T > 0)) T = 1.0;
+        ks[4 * k + 0] = u[0];
+        ks[4 * k + 1] = u[1];
+        ks[4 * k + 2] = u[2];
+        ks[4 * k + 3] = T;
+    }
+    HIPCHK(hipMemcpyAsync(c->ws + c->off.axes, axes.data(), sizeof(double) * axes.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->ws + c->off.cellinfo, c->cellinfo.data(), sizeof(uint32_t) * c->N, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->ws + c->off.bricks, c->bricks.data(), sizeof(int) * c->bricks.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->ws + c->off.lanetab, lt.data(), sizeof(double) * lt.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->ws + c->off.kstate, ks.data(), sizeof(double) * ks.size(), hipMemcpyHostToDevice, st));
+    // partial slots of tiles that an octant does not have stay zero
+    HIPCHK(hipMemsetAsync(c->ws + c->off.partial, 0, c->off.xface - c->off.partial, st));
+    const Consts C = make_consts(c);
+    const DevPtrs D = make_ptrs(c);
+    HIPCHK(launch_emission(C, D, c->P<double>(c->off.kstate), NKIND, c->ws + c->off.ghat,
+                           c->P<double>(c->off.ghat64), c->P<double>(c->off.gout), c->prec, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->bound = true;
+    c->initialized = false;
+    return DVM_OK;
+}
+
+dvm_status dvm_init_fields(dvm_ctx* c, const double* rho, const double* u, const double* T, double target_mass)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!c->bound) return fail(DVM_ERR_STATE, "bind a workspace first");
+    if (!rho || !u || !T) return fail(DVM_ERR_ARG, "NULL field");
+    const size_t N = c->N;
+    double mass = 0;
+    for (size_t i = 0; i < N; ++i) {
+        if (c->cellinfo[i] & SOLID_BIT) continue;
+        if (!(rho[i] > 0) || !(T[i] > 0) || !isfinite(rho[i]) || !isfinite(T[i]) || !isfinite(u[i]) ||
+            !isfinite(u[N + i]) || !isfinite(u[2 * N + i]))
+            return fail(DVM_ERR_NONPHYSICAL, "cell %zu: rho, T must be > 0 and finite", i);
+        mass += rho[i];
+    }
+    const double dV = c->dx[0] * c->dx[1] * c->dx[2];
+    const double scale = target_mass > 0 ? target_mass / (mass * dV) : 1.0;
+    std::vector<double> Wh(5 * N, 0.0);
+    for (size_t i = 0; i < N; ++i) {
+        if (c->cellinfo[i] & SOLID_BIT) continue;
+        const double r = rho[i] * scale;
+        const double ux = u[i], uy = u[N + i], uz = u[2 * N + i];
+        Wh[i] = r;
+        Wh[N + i] = r * ux;
+        Wh[2 * N + i] = r * uy;
+        Wh[3 * N + i] = r * uz;
+        Wh[4 * N + i] = 0.5 * r * (ux * ux + uy * uy + uz * uz) + 0.75 * r * T[i];
+    }
+    return upload_initial(c, Wh);
+}
+
+dvm_status dvm_init_uniform(dvm_ctx* c, double rho, const double u[3], double T)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!c->bound) return fail(DVM_ERR_STATE, "bind a workspace first");
+    if (!u) return fail(DVM_ERR_ARG, "u is NULL");
+    const size_t N = c->N;
+    std::vector<double> r(N, rho), uu(3 * N), t(N, T);
+    for (size_t i = 0; i < N; ++i) {
+        uu[i] = u[0];
+        uu[N + i] = u[1];
+        uu[2 * N + i] = u[2];
+    }
+    return dvm_init_fields(c, r.data(), uu.data(), t.data(), 0.0);
+}
+
+dvm_status dvm_iterate(dvm_ctx* c, int max_iters, double tol, int* iters_done, double* residual)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!c->initialized) return fail(DVM_ERR_STATE, "initialise the state first");
+    if (max_iters < 0) return fail(DVM_ERR_ARG, "max_iters must be >= 0");
+    if (iters_done) *iters_done = 0;
+    double hout[8];
+    double r = INFINITY;
+    for (int it = 0; it < max_iters; ++it) {
+        const dvm_status st = run_iteration(c, hout);
+        if (st != DVM_OK) return st;
+        const int flag = (int)hout[6];
+        bool finite = true;
+        for (int v = 0; v < 5; ++v) finite = finite && isfinite(hout[v]);
+        if (flag || !finite) {
+            if (residual) *residual = r;
+            return fail(DVM_ERR_NONPHYSICAL, "non-physical state in iteration %d (flag %d); kept the last good iterate",
+                        it + 1, flag);
+        }
+        c->cur = 1 - c->cur;
+        r = 0;
+        for (int v = 0; v < 5; ++v) {
+            c->res[v] = hout[v];
+            if (hout[v] > r) r = hout[v];
+        }
+        if (iters_done) *iters_done = it + 1;
+        if (residual) *residual = r;
+        if (tol > 0 && r <= tol) return DVM_OK;
+    }
+    if (tol > 0 && max_iters > 0) return DVM_NOT_CONVERGED;
+    return DVM_OK;
+}
+
+dvm_status dvm_get_residuals(dvm_ctx* c, double r[5])
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!r) return fail(DVM_ERR_ARG, "NULL");
+    for (int v = 0; v < 5; ++v) r[v] = c->res[v];
+    return DVM_OK;
+}
+
+dvm_status dvm_get_state(dvm_ctx* c, double* W, double* q, double* rho_w, double* M0)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!c->initialized) return fail(DVM_ERR_STATE, "no state yet");
+    const size_t N = c->N;
+    hipStream_t st = c->stream;
+    if (W) HIPCHK(hipMemcpyAsync(W, c->P<double>(c->off.W) + c->cur * 5 * N, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, st));
+    if (q) HIPCHK(hipMemcpyAsync(q, c->P<double>(c->off.q) + c->cur * 3 * N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st));
+    if (rho_w) HIPCHK(hipMemcpyAsync(rho_w, c->P<double>(c->off.rw) + c->cur * 6 * N, sizeof(double) * 6 * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (M0) *M0 = c->M0;
+    return DVM_OK;
+}
+
+dvm_status dvm_set_state(dvm_ctx* c, const double* W, const double* q, const double* rho_w, double M0)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!c->bound) return fail(DVM_ERR_STATE, "bind a workspace first");
+    if (!W || !q || !rho_w) return fail(DVM_ERR_ARG, "NULL");
+    const size_t N = c->N;
+    for (size_t i = 0; i < N; ++i) {
+        if (c->cellinfo[i] & SOLID_BIT) continue;
+        if (!(W[i] > 0) || !isfinite(W[i])) return fail(DVM_ERR_NONPHYSICAL, "cell %zu: rho must be > 0", i);
+    }
+    hipStream_t st = c->stream;
+    c->cur = 0;
+    HIPCHK(hipMemcpyAsync(c->P<double>(c->off.W), W, sizeof(double) * 5 * N, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->P<double>(c->off.q), q, sizeof(double) * 3 * N, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->P<double>(c->off.rw), rho_w, sizeof(double) * 6 * N, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->M0 = M0;
+    c->initialized = true;
+    for (int v = 0; v < 5; ++v) c->res[v] = 0;
+    return DVM_OK;
+}
+
+dvm_status dvm_get_fields(dvm_ctx* c, double* rho, double* u, double* T, double* q)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!c->initialized) return fail(DVM_ERR_STATE, "no state yet");
+    const size_t N = c->N;
+    std::vector<double> W(5 * N), qq(3 * N);
+    dvm_status st = dvm_get_state(c, W.data(), qq.data(), nullptr, nullptr);
+    if (st) return st;
+    for (size_t i = 0; i < N; ++i) {
+        const bool sol = (c->cellinfo[i] & SOLID_BIT) != 0;
+        const double r = sol ? 0.0 : W[i];
+        double U[3] = {0, 0, 0}, t = 0;
+        if (!sol) {
+            for (int d = 0; d < 3; ++d) U[d] = W[(d + 1) * N + i] / r;
+            t = (W[4 * N + i] - 0.5 * r * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2])) / (0.75 * r);
+        }
+        if (rho) rho[i] = r;
+        if (T) T[i] = t;
+        if (u) for (int d = 0; d < 3; ++d) u[d * N + i] = U[d];
+        if (q) for (int d = 0; d < 3; ++d) q[d * N + i] = sol ? 0.0 : qq[d * N + i];
+    }
+    return DVM_OK;
+}
+
+dvm_status dvm_get_info(dvm_ctx* c, dvm_info* info)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!info) return fail(DVM_ERR_ARG, "NULL");
+    layout(c);
+    int nfluid = c->N;
+    if (!c->solid.empty()) {
+        nfluid = 0;
+        for (uint8_t s : c->solid) nfluid += s ? 0 : 1;
+    }
+    info->nx = c->g.nx;
+    info->ny = c->g.ny;
+    info->nz = c->g.nz;
+    info->ncells = c->N;
+    info->nfluid = nfluid;
+    for (int d = 0; d < 3; ++d) info->m[d] = c->vg.m[d];
+    info->nvel = c->NV;
+    info->precision = c->prec;
+    info->brick[0] = c->BX;
+    info->brick[1] = c->BY;
+    info->brick[2] = c->BZ;
+    info->vel_per_lane = c->VL;
+    info->tiles_per_octant = c->ntiles;
+    int launches = 0;
+    for (int T = 0; T < c->ndiag; ++T) launches += c->diag_cnt[T] > 0;
+    info->sweep_launches = launches * (c->spec_on ? 2 : 1);
+    info->workspace_bytes = c->off.end;
+    return DVM_OK;
+}
+
+dvm_status dvm_set_timing(dvm_ctx* c, int enable)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (enable && !c->ev[0])
+        for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&c->ev[k]));
+    c->timing = enable != 0;
+    c->t_params = c->t_sweep = c->t_final = 0;
+    c->t_iters = 0;
+    return DVM_OK;
+}
+
+dvm_status dvm_get_timings(dvm_ctx* c, double* ms_params, double* ms_sweep, double* ms_finalize, int* iterations)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (ms_params) *ms_params = c->t_params;
+    if (ms_sweep) *ms_sweep = c->t_sweep;
+    if (ms_finalize) *ms_finalize = c->t_final;
+    if (iterations) *iterations = c->t_iters;
+    c->t_params = c->t_sweep = c->t_final = 0;
+    c->t_iters = 0;
+    return DVM_OK;
+}
+
+dvm_status dvm_selftest_wave_reduce(const double* in, double* out)
+{
+    if (!in || !out) return fail(DVM_ERR_ARG, "NULL");
+    double *din = nullptr, *dout = nullptr;
+    HIPCHK(hipMalloc(&din, sizeof(double) * 64 * 13));
+    HIPCHK(hipMalloc(&dout, sizeof(double) * 13));
+    HIPCHK(hipMemcpy(din, in, sizeof(double) * 64 * 13, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(dout, 0, sizeof(double) * 13));
+    HIPCHK(launch_selftest_reduce(din, dout, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(out, dout, sizeof(double) * 13, hipMemcpyDeviceToHost));
+    HIPCHK(hipFree(din));
+    HIPCHK(hipFree(dout));
+    return DVM_OK;
+}
+
+void dvm_destroy(dvm_ctx* c)
+{
+    if (!c) return;
+    for (int k = 0; k < 4; ++k)
+        if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    delete c;
+}
+
+}  // extern "C"

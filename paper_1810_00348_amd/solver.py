@@ -1,0 +1,129 @@
+"""Python front end of the HIP solver: one context per case, workspace and
+stream from torch, everything else done by libdvm_hip.so."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .cases import Case
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Solver:
+    """Iterative DVM solver for one ``Case`` on one GPU.
+
+    precision: "f64" (default) or "f32" (f stored and updated in FP32; moments,
+    correction and per-cell quantities in FP64).
+    """
+
+    def __init__(self, case: Case, precision: str = "f64", device: str = "cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP solver needs a GPU")
+        self.case = case
+        self.device = torch.device(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self.precision = {"f64": L.DVM_F64, "f32": L.DVM_F32}[precision]
+        lib = L.lib()
+        g = L.Grid(*case.n, *case.L)
+        vg = L.VGrid((C.c_int * 3)(*case.m), (C.c_double * 3)(*case.vmax))
+        gas = L.Gas(case.kn, case.omega, case.pr, int(case.correction))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(lib.dvm_create(C.byref(g), C.byref(vg), C.byref(gas), self.precision,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        for f, face in enumerate(case.faces):
+            bc = L.FaceBC(face.code, (C.c_double * 3)(*face.u), face.T, face.rho)
+            L.check(lib.dvm_set_face_bc(h, f, C.byref(bc)))
+        if case.solid is not None:
+            self._solid = case.solid_flat()
+            u = np.ascontiguousarray(case.solid_u, dtype=np.float64)
+            L.check(lib.dvm_set_solid(h, self._solid.ctypes.data_as(C.c_void_p), _ptr(u), case.solid_T))
+        L.check(lib.dvm_set_closed(h, int(case.closed)))
+        nbytes = C.c_size_t()
+        L.check(lib.dvm_required_workspace(h, C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(lib.dvm_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value))
+        self.N = case.ncells
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            L.lib().dvm_destroy(h)
+            self._h = None
+
+    # ---- state
+    def init_uniform(self, rho=None, u=None, T=None):
+        c = self.case
+        u = np.ascontiguousarray(c.init_u if u is None else u, dtype=np.float64)
+        L.check(L.lib().dvm_init_uniform(self._h, c.init_rho if rho is None else rho, _ptr(u),
+                                         c.init_T if T is None else T))
+
+    def init_fields(self, rho, u, T, target_mass: float = 0.0):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, -1)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        L.check(L.lib().dvm_init_fields(self._h, _ptr(rho), _ptr(u), _ptr(T), target_mass))
+
+    def iterate(self, n: int = 1, tol: float = 0.0):
+        """Run up to n iterations (stop at residual <= tol if tol > 0).
+        Returns (iterations done, residual, converged)."""
+        it = C.c_int()
+        r = C.c_double()
+        st = L.check(L.lib().dvm_iterate(self._h, n, tol, C.byref(it), C.byref(r)))
+        return it.value, r.value, st == L.DVM_OK
+
+    def residual(self, per_field: bool = False):
+        r = np.zeros(5)
+        L.check(L.lib().dvm_get_residuals(self._h, _ptr(r)))
+        return r if per_field else float(r.max())
+
+    def fields(self):
+        N = self.N
+        rho = np.empty(N); u = np.empty((3, N)); T = np.empty(N); q = np.empty((3, N))
+        L.check(L.lib().dvm_get_fields(self._h, _ptr(rho), _ptr(u), _ptr(T), _ptr(q)))
+        return {"rho": rho, "u": u, "T": T, "q": q}
+
+    def state(self):
+        N = self.N
+        W = np.empty((5, N)); q = np.empty((3, N)); rw = np.empty((6, N)); M0 = C.c_double()
+        L.check(L.lib().dvm_get_state(self._h, _ptr(W), _ptr(q), _ptr(rw), C.byref(M0)))
+        return W, q, rw, M0.value
+
+    def set_state(self, W, q, rho_w, M0):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        rho_w = np.ascontiguousarray(rho_w, dtype=np.float64)
+        L.check(L.lib().dvm_set_state(self._h, _ptr(W), _ptr(q), _ptr(rho_w), M0))
+
+    def info(self) -> dict:
+        inf = L.Info()
+        L.check(L.lib().dvm_get_info(self._h, C.byref(inf)))
+        return {"cells": [inf.nx, inf.ny, inf.nz], "nfluid": inf.nfluid, "m": list(inf.m),
+                "nvel": inf.nvel, "precision": inf.precision, "brick": list(inf.brick),
+                "vel_per_lane": inf.vel_per_lane, "tiles_per_octant": inf.tiles_per_octant,
+                "sweep_launches": inf.sweep_launches, "workspace_bytes": inf.workspace_bytes}
+
+    def set_timing(self, enable: bool = True):
+        L.check(L.lib().dvm_set_timing(self._h, int(enable)))
+
+    def timings(self):
+        a = C.c_double(); b = C.c_double(); d = C.c_double(); n = C.c_int()
+        L.check(L.lib().dvm_get_timings(self._h, C.byref(a), C.byref(b), C.byref(d), C.byref(n)))
+        return {"params_ms": a.value, "sweep_ms": b.value, "finalize_ms": d.value, "iterations": n.value}
+
+
+def selftest_wave_reduce(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(64, 13)
+    out = np.zeros(13)
+    L.check(L.lib().dvm_selftest_wave_reduce(_ptr(x), _ptr(out)))
+    return out

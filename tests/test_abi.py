@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every entry point include/dvm.h
+declares; host-only calls (no GPU work) behave as documented."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "dvm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:dvm_status|const char\*|void)\s+(dvm_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1810_00348_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1810_00348_amd import build
+        build.build()
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(L):
+    lib = L.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) <= set(L.EXPORTS), set(syms) - set(L.EXPORTS)
+
+
+def _ctx(L, case, prec=0):
+    lib = L.lib()
+    g = L.Grid(*case.n, *case.L)
+    vg = L.VGrid((C.c_int * 3)(*case.m), (C.c_double * 3)(*case.vmax))
+    gas = L.Gas(case.kn, case.omega, case.pr, 1)
+    h = C.c_void_p()
+    assert lib.dvm_create(C.byref(g), C.byref(vg), C.byref(gas), prec, None, C.byref(h)) == 0
+    return h
+
+
+def test_workspace_sizes_fit_one_gpu(L):
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    for name, prec in (("c1", 0), ("c2", 0), ("c3", 1), ("c3", 0), ("c4", 1)):
+        case = cases.config(name)
+        h = _ctx(L, case, prec)
+        for f, face in enumerate(case.faces):
+            bc = L.FaceBC(face.code, (C.c_double * 3)(*face.u), face.T, face.rho)
+            assert lib.dvm_set_face_bc(h, f, C.byref(bc)) == 0
+        n = C.c_size_t()
+        assert lib.dvm_required_workspace(h, C.byref(n)) == 0
+        info = L.Info()
+        assert lib.dvm_get_info(h, C.byref(info)) == 0
+        assert info.nvel == case.nvel and info.ncells == case.ncells
+        assert 0 < n.value < 200 * 2 ** 30, (name, n.value / 2 ** 30)
+        lib.dvm_destroy(h)
+
+
+def test_argument_errors(L):
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    case = cases.config("c1")
+    g = L.Grid(0, 4, 4, 1.0, 1.0, 1.0)
+    vg = L.VGrid((C.c_int * 3)(8, 8, 8), (C.c_double * 3)(5, 5, 5))
+    gas = L.Gas(1.0, 0.81, 2 / 3, 1)
+    h = C.c_void_p()
+    assert lib.dvm_create(C.byref(g), C.byref(vg), C.byref(gas), 0, None, C.byref(h)) == -1
+    assert b"grid" in lib.dvm_last_error()
+    h = _ctx(L, case)
+    bc = L.FaceBC(2, (C.c_double * 3)(0, 0, 0), 1.0, 1.0)
+    assert lib.dvm_set_face_bc(h, 0, C.byref(bc)) == -1          # specular only on z-
+    assert lib.dvm_set_face_bc(h, 4, C.byref(bc)) == 0
+    assert lib.dvm_iterate(h, 1, 0.0, None, None) == -2           # not initialised
+    assert lib.dvm_init_uniform(h, 1.0, (C.c_double * 3)(0, 0, 0), 1.0) == -2  # no workspace
+    assert lib.dvm_bind_workspace(h, C.c_void_p(1024), 10) == -3  # too small
+    lib.dvm_destroy(h)

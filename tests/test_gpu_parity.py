@@ -1,0 +1,154 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Error measure per macroscopic field x in {rho, Ux, Uy, Uz, T} (and q):
+max_c |x_gpu - x_oracle| / max_c |x_oracle|, compared after the same number
+of iterations from the same initial state.  Bar: 1e-10 in FP64.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1810_00348_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def _solver():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_00348_amd.solver import Solver
+    return Solver
+
+
+def field_errors(g, r):
+    out = {}
+    for name in ("rho", "T"):
+        out[name] = np.abs(g[name] - r[name]).max() / np.abs(r[name]).max()
+    for d, name in enumerate(("ux", "uy", "uz")):
+        den = np.abs(r["u"][d]).max()
+        out[name] = np.abs(g["u"][d] - r["u"][d]).max() / den if den > 0 else np.abs(g["u"][d]).max()
+    for d, name in enumerate(("qx", "qy", "qz")):
+        den = np.abs(r["q"][d]).max()
+        out[name] = np.abs(g["q"][d] - r["q"][d]).max() / den if den > 0 else np.abs(g["q"][d]).max()
+    return out
+
+
+def run_pair(case, iters, oracle_mod, precision="f64", init=None):
+    Solver = _solver()
+    s = Solver(case, precision=precision)
+    o = oracle_mod.Oracle(case)
+    if init is None:
+        s.init_uniform(); o.init_uniform()
+    else:
+        s.init_fields(*init); o.init_fields(*init)
+    for _ in range(iters):
+        s.iterate(1)
+        o.iterate(1)
+    return s, o
+
+
+def test_wave_reduce_selftest():
+    _solver()
+    from paper_1810_00348_amd.solver import selftest_wave_reduce
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((64, 13)) * 10.0 ** rng.integers(-3, 3, (64, 13))
+    out = selftest_wave_reduce(x)
+    ref = x.sum(axis=0)
+    assert np.abs(out - ref).max() <= 1e-13 * np.abs(x).sum(axis=0).max()
+
+
+@pytest.mark.parametrize("iters", [1, 5])
+def test_c1_cavity_matches_oracle(oracle_mod, iters):
+    case = cases.config("c1")
+    s, o = run_pair(case, iters, oracle_mod)
+    err = field_errors(s.fields(), o.fields())
+    print(iters, err, s.info())
+    for k in ("rho", "ux", "uy", "uz", "T", "qx", "qy"):
+        assert err[k] <= FP64_TOL, (k, err)
+    rg, ro = s.residual(per_field=True), o.residual(per_field=True)
+    assert np.abs(rg - ro).max() <= 1e-8 * ro.max()
+    Wg, qg, rwg, M0g = s.state()
+    Wo, qo, rwo = o.state()
+    assert np.abs(rwg - rwo).max() <= FP64_TOL * np.abs(rwo).max()
+    assert abs(M0g - o.initial_mass()) <= 1e-14
+
+
+def test_c1_cavity_converges_like_oracle(oracle_mod):
+    case = cases.config("c1")
+    Solver = _solver()
+    s = Solver(case)
+    s.init_uniform()
+    n, r, ok = s.iterate(200, tol=1e-6)
+    assert ok
+    o = oracle_mod.Oracle(case)
+    o.init_uniform()
+    for _ in range(n):
+        o.iterate(1)
+    assert o.residual() <= 1e-6
+    err = field_errors(s.fields(), o.fields())
+    print(n, err)
+    for k in ("rho", "ux", "uy", "uz", "T"):
+        assert err[k] <= FP64_TOL, (k, err)
+
+
+def _ragged_cases():
+    a = cases.cavity((13, 10, 19), 8, kn=0.3, lid=0.4, vmax=4.5)      # ragged bricks
+    b = cases.cavity((9, 11, 7), 9, kn=2.0, lid=0.2, vmax=5.0)         # odd M: xi = 0 nodes
+    c = cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=10, vmax=7.0, mach=2.0, kn=0.5)
+    d = dataclasses.replace(cases.cavity((8, 8, 8), 16, kn=10.0, lid=0.16), correction=False)
+    e = cases.cavity((6, 5, 9), 12, kn=0.1, lid=0.5, pr=1.0)            # BGK
+    return {"ragged": a, "oddM": b, "cube": c, "nocorr": d, "bgk": e}
+
+
+@pytest.mark.parametrize("name", ["ragged", "oddM", "cube", "nocorr", "bgk"])
+def test_small_cases_match_oracle(oracle_mod, name):
+    case = _ragged_cases()[name]
+    init = None
+    if name in ("ragged", "bgk"):
+        init = cases.random_fields(case, seed=7)
+    s, o = run_pair(case, 3, oracle_mod, init=init)
+    err = field_errors(s.fields(), o.fields())
+    print(name, err, s.info())
+    for k in ("rho", "ux", "uy", "uz", "T"):
+        assert err[k] <= FP64_TOL, (k, err)
+
+
+def test_rest_equilibrium_is_fixed_point_on_gpu():
+    Solver = _solver()
+    case = cases.cavity((20, 12, 17), 16, kn=0.8, lid=0.0)
+    s = Solver(case)
+    s.init_uniform()
+    W0, _, _, _ = s.state()
+    s.iterate(2)
+    W, q, rw, _ = s.state()
+    assert np.abs(W - W0).max() < 1e-14
+    assert np.abs(q).max() < 1e-14
+
+
+def test_mass_conserved_on_gpu():
+    Solver = _solver()
+    case = cases.cavity((16, 12, 10), 12, kn=0.5, lid=0.3)
+    s = Solver(case)
+    rho, u, T = cases.random_fields(case, seed=2)
+    s.init_fields(rho, u, T)
+    dv = 1.0 / case.ncells
+    M0 = s.state()[3]
+    for _ in range(3):
+        s.iterate(1)
+        W = s.state()[0]
+        assert abs(W[0].sum() * dv - M0) < 1e-13 * M0
+
+
+def test_fp32_storage_error_is_bounded(oracle_mod):
+    case = cases.config("c1")
+    s, o = run_pair(case, 5, oracle_mod, precision="f32")
+    err = field_errors(s.fields(), o.fields())
+    print("fp32", err)
+    for k in ("rho", "T"):
+        assert err[k] <= 1e-5, (k, err)
+    for k in ("ux", "uy"):
+        assert err[k] <= 1e-4, (k, err)
