@@ -1,0 +1,256 @@
+"""Benchmark: phase-space point-updates per second of one outer iteration.
+
+One step = one full outer iteration of the HIP path (per-cell parameters, the
+upwind sweep of every discrete velocity with the on-the-fly equilibrium, the
+moment reduction, finalisation, mass rescaling and the residual read-back) on
+the 3D lid-driven cavity with 64^3 cells and 32^3 discrete velocities on
+[-5,5]^3, Kn = 1, lid speed 0.16, FP64 -- synthetic input, resident in HBM.
+
+Prints ONE JSON line (rank 0).  Options:
+  --gpus N      only N = 1 is supported (this build targets one GPU)
+  --steps K     timed iterations (default 10)
+  --warmup W    untimed iterations first (default 2)
+  --workload    c2 (default), c3 (FP32 storage form) or c4 (cube, FP32)
+  --precision   override f64/f32
+  --no-cpu      skip the CPU oracle baseline
+  --traffic F   JSON file with measured HBM bytes per sweep launch (from
+                rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, calibrated)
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak figures of one MI355X (vendor): HBM3E 8 TB/s; FP64 vector 78.6 TFLOP/s
+# (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz).
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+# algorithmic work of one point-update of the sweep: one write of f^{n+1} and
+# one read of the upwind operand (2 s bytes, s = bytes of the storage type),
+# ~65 flops (equilibrium on the fly with separable Gaussian factors ~25,
+# relaxation update ~14, 13 FP64 moment sums ~26)
+FLOPS_PER_POINT = 65.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1810_00348_amd", "csrc", "dvm_kernels.hip")
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _pmc_sum(path: str, counter: str, kernel_substr: str):
+    """Sum of a counter over the dispatches of one kernel, and their count."""
+    tot, n = 0.0, 0
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and kernel_substr in r["Kernel_Name"]:
+                tot += float(r["Counter_Value"])
+                n += 1
+    return tot, n
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, out, label):
+    """Calibrated HBM bytes per sweep launch from rocprofv3 --pmc runs."""
+    cf, _ = _pmc_sum(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
+    cw, _ = _pmc_sum(copy_write_csv, "WRITE_SIZE", "copyBuffer")
+    ffac = copy_bytes / (cf * 1024.0)
+    wfac = copy_bytes / (cw * 1024.0)
+    f, nf = _pmc_sum(fetch_csv, "FETCH_SIZE", "sweep_kernel")
+    w, nw = _pmc_sum(write_csv, "WRITE_SIZE", "sweep_kernel")
+    rec = {
+        "kernel_source_sha256_16": kernel_sha(),
+        "label": label,
+        "launches": nf,
+        "fetch_kib_total": f, "write_kib_total": w,
+        "fetch_factor": round(ffac, 4), "write_factor": round(wfac, 4),
+        "bytes_per_launch": (f * 1024.0 * ffac + w * 1024.0 * wfac) / max(1, nf),
+        "read_bytes_per_launch": f * 1024.0 * ffac / max(1, nf),
+        "write_bytes_per_launch": w * 1024.0 * wfac / max(1, nw),
+    }
+    with open(out, "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(json.dumps(rec))
+
+
+def measured_traffic(label: str):
+    """Bytes per sweep launch from the committed counter summary, if it was
+    taken on the current kernel source and the same workload/schedule."""
+    path = os.path.join(TRAFFIC_DIR, f"sweep_traffic_{label}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def workload(name: str, kn: float):
+    from paper_1810_00348_amd import cases
+    if name == "c2":
+        return cases.config("c2", kn=kn), "f64"
+    if name == "c3":
+        return cases.config("c3"), "f32"
+    if name == "c4":
+        return cases.config("c4"), "f32"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, budget_s: float = 25.0):
+    """The FP64 oracle, as it stands, for one outer iteration on a bounded
+    sample of the workload: the same spatial grid with a reduced velocity grid
+    (the oracle's cost is linear in the number of phase-space points)."""
+    from oracle import oracle as O
+    from paper_1810_00348_amd import cases
+    import dataclasses
+    O.build(force=False)
+    m = 16
+    sample = dataclasses.replace(case, m=(m, m, m), name=case.name + f"_sample_v{m}")
+    o = O.Oracle(sample)
+    o.init_uniform()
+    t0 = time.perf_counter()
+    o.iterate(1)
+    dt = time.perf_counter() - t0
+    pts = sample.points
+    return {
+        "value": pts / dt / 1e9,
+        "unit": "GPt/s",
+        "cores": o.threads,
+        "kind": "oracle",
+        "sample": f"one FP64 oracle iteration on {sample.n[0]}x{sample.n[1]}x{sample.n[2]} cells x "
+                  f"{m}^3 velocities ({pts:.3g} points, {dt:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--kn", type=float, default=1.0)
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic", default=None)
+    ap.add_argument("--copy-calib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=6, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "COPY_BYTES", "LABEL"),
+                    help="write profiles/sweep_traffic_LABEL.json from rocprofv3 --pmc CSVs")
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        a = args.summarize_pmc
+        summarize_pmc(a[0], a[1], a[2], a[3], float(a[4]),
+                      os.path.join(TRAFFIC_DIR, f"sweep_traffic_{a[5]}.json"), a[5])
+        return
+    if args.copy_calib > 0:
+        import torch
+        n = int(args.copy_calib * 2 ** 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8}))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the sweep shards by velocity across "
+              "GPUs by design, but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1810_00348_amd.solver import Solver
+
+    case, prec = workload(args.workload, args.kn)
+    if args.precision:
+        prec = args.precision
+    s = Solver(case, precision=prec)
+    s.init_uniform()
+    info = s.info()
+    if args.warmup:
+        s.iterate(args.warmup)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = s.timings()
+    s.set_timing(False)
+
+    ms = dt * 1e3 / args.steps
+    pts = case.points
+    value = pts / (ms / 1e3) / 1e9
+    iters = max(1, tm["iterations"])
+    sweep_ms = tm["sweep_ms"] / iters
+    launches = info["sweep_launches"]
+    sbytes = 8 if prec == "f64" else 4
+    # dominant kernel: the sweep.  Algorithmic bytes per launch = points per
+    # launch x 2 s; averaged over the launches of an iteration this is
+    # (points x 2 s) / (sweep time of one iteration).
+    achieved_gbs = pts * 2 * sbytes / (sweep_ms / 1e3) / 1e9
+    label = f"{args.workload}_{prec}_vl{info['vel_per_lane']}_b{info['brick'][0]}x{info['brick'][1]}x{info['brick'][2]}"
+    line = {
+        "metric": "phase-space GPoint-updates/s per iteration",
+        "value": round(value, 3),
+        "unit": "GPt/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{case.name}: lid-driven cavity {case.n[0]}x{case.n[1]}x{case.n[2]} cells x "
+                         f"{case.m[0]}^3 velocities on [-{case.vmax[0]:g},{case.vmax[0]:g}]^3, "
+                         f"Kn={case.kn:g}, lid {case.faces[3].u[0]:g}"
+                         if args.workload != "c4" else
+                         f"{case.name}: cube half-domain {case.n[0]}x{case.n[1]}x{case.n[2]} cells x "
+                         f"{case.m[0]}^3 velocities on [-{case.vmax[0]:g},{case.vmax[0]:g}]^3, Ma 5, Kn 0.1"),
+            "points_per_iteration": pts,
+            "brick": info["brick"],
+            "vel_per_lane": info["vel_per_lane"],
+            "sweep_launches_per_iteration": launches,
+            "phase_ms": {"params": round(tm["params_ms"] / iters, 4),
+                         "sweep": round(sweep_ms, 4),
+                         "finalize": round(tm["finalize_ms"] / iters, 4)},
+            "residual_after": s.residual(),
+            "paper_context": "K40, FP32, 64^3 x 32^3 cavity: 4.33 s/iteration = 1.98 GPt/s "
+                             "(Table iteration_time); 190x over one Xeon core",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved_gbs, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved_gbs / PEAK_HBM_GBS, 4),
+            "traffic": measured_traffic(label),
+            "kernel": "sweep_kernel",
+            "bytes_per_point": 2 * sbytes,
+            "launches_per_step": launches,
+            "avg_launch_ms": round(sweep_ms / max(1, launches), 5),
+            "alu_view": {"flops_per_point": FLOPS_PER_POINT,
+                         "achieved_tflops": round(pts * FLOPS_PER_POINT / (sweep_ms / 1e3) / 1e12, 3),
+                         "peak_tflops_fp64": PEAK_FP64_TFLOPS},
+            "traffic_label": label,
+        },
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -9,7 +9,7 @@
 namespace dvm {
 
 constexpr int NMOM = 13;     // raw velocity moments accumulated per cell
-constexpr int PSTRIDE = 16;  // per-cell equilibrium parameter slots
+constexpr int PSTRIDE = 24;  // per-cell parameter slots
 constexpr int MAXM = 512;    // velocity nodes per axis (upper bound)
 constexpr int NKIND = 7;     // emission kinds: 6 box faces + the solid body
 
@@ -21,7 +21,9 @@ enum {
     P_L1, P_L2, P_L3, P_L4,
     P_QX, P_QY, P_QZ,  // sigma * q
     P_TWO_T,    // 2 / T
-    P_NPARAM
+    P_INFO,     // the cell info word (bit pattern in the slot's low 32 bits)
+    P_NPARAM,
+    P_RHO_SIDE = 16  // 6 slots: inflow density of each side (wall rho_w or free-stream rho)
 };
 
 // cell info word: 4 bits per side (side s = 2 d + (upper ? 1 : 0)):
@@ -63,7 +65,6 @@ struct SweepArgs {
     const S* params;      // [N][PSTRIDE]
     const S* etab;        // [N][MT]: exp tables x | y | z (z scaled by nu * prefactor)
     const uint32_t* cellinfo;
-    const double* rho_w;  // [6][N] wall densities of iteration n
     const S* ghat;        // [NKIND][NV] unit-density emission shapes
     const double* lanetab;
     const int* bricks;
@@ -78,14 +79,14 @@ struct SweepArgs {
     int brick_off, brick_cnt;
     int oct_base, noct;
     int spec_on;
+    int has_solid;
     int nblocks;
-    double kind_rho[8];
-    int kind_wall[8];
 };
 
 // kernel launchers (dvm_kernels.hip)
 hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, const double* q,
-                         void* params, void* etab, int prec, int* flag, hipStream_t st);
+                         const double* rho_w, void* params, void* etab, int prec, int* flag,
+                         hipStream_t st);
 hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind_state /*[NKIND][4]*/,
                            int nkind, void* ghat, double* ghat64, double* gout, int prec,
                            hipStream_t st);

@@ -26,7 +26,23 @@ namespace dvm {
 // small helpers
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ double ldpar(const double* p) { return *p; }
+// Reciprocal of a positive normal number: hardware estimate refined by Newton
+// steps (each squares the relative error: two for FP64, one for FP32).
+__device__ __forceinline__ double fast_rcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ float fast_rcp(float d)
+{
+    float r = __builtin_amdgcn_rcpf(d);
+    const float e = fmaf(-d, r, 1.0f);
+    return fmaf(r, e, r);
+}
 
 // 5x5 symmetric positive definite solve by Cholesky (FP64).
 __device__ bool chol5_solve(double A[5][5], const double b[5], double x[5])
@@ -130,12 +146,27 @@ __device__ bool correction_lambda(const double Mx[6], const double My[6], const 
 
 template <typename S>
 __global__ __launch_bounds__(128) void params_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
-                                                     const double* __restrict__ q, S* __restrict__ params,
+                                                     const double* __restrict__ q,
+                                                     const double* __restrict__ rho_w, S* __restrict__ params,
                                                      S* __restrict__ etab, int* __restrict__ flag)
 {
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= C.N) return;
-    if (D.cellinfo[cell] & SOLID_BIT) return;
+    const uint32_t info = D.cellinfo[cell];
+    reinterpret_cast<uint32_t*>(params + (size_t)cell * PSTRIDE + P_INFO)[0] = info;
+    if (info & SOLID_BIT) return;
+    {
+        // inflow density of each side: the wall density of iteration n at a
+        // diffuse wall, the free-stream density at a free-stream face
+        S* P = params + (size_t)cell * PSTRIDE;
+        for (int s = 0; s < 6; ++s) {
+            const uint32_t code = (info >> (4 * s)) & 15u;
+            double rf = 0.0;
+            if (code != 0 && code != CODE_SPECULAR)
+                rf = C.kind_wall[code - 1] ? rho_w[(size_t)s * C.N + cell] : C.kind_rho[code - 1];
+            P[P_RHO_SIDE + s] = (S)rf;
+        }
+    }
     const int N = C.N;
     const double rho = W[cell];
     const double Ux = W[N + cell] / rho, Uy = W[2 * N + cell] / rho, Uz = W[3 * N + cell] / rho;
@@ -200,14 +231,15 @@ __global__ __launch_bounds__(128) void params_kernel(Consts C, DevPtrs D, const 
 }
 
 hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, const double* q,
-                         void* params, void* etab, int prec, int* flag, hipStream_t st)
+                         const double* rho_w, void* params, void* etab, int prec, int* flag,
+                         hipStream_t st)
 {
     const int tpb = 128;
     const int nb = (C.N + tpb - 1) / tpb;
     if (prec == 0)
-        params_kernel<double><<<nb, tpb, 0, st>>>(C, D, W, q, (double*)params, (double*)etab, flag);
+        params_kernel<double><<<nb, tpb, 0, st>>>(C, D, W, q, rho_w, (double*)params, (double*)etab, flag);
     else
-        params_kernel<float><<<nb, tpb, 0, st>>>(C, D, W, q, (float*)params, (float*)etab, flag);
+        params_kernel<float><<<nb, tpb, 0, st>>>(C, D, W, q, rho_w, (float*)params, (float*)etab, flag);
     return hipGetLastError();
 }
 
@@ -455,9 +487,10 @@ __device__ __forceinline__ double wave_reduce13(const double v[13])
 __device__ __forceinline__ int reduce13_index(int lane)
 {
     const int r = lane >> 4, b = (lane >> 2) & 3;
-    const int base[4] = {0, 8, 4, 12};
-    const int rowm[4] = {0, 2, 1, 3};
-    return base[b] + rowm[r];
+    // base {0, 8, 4, 12}[b] = 4 * bitreverse2(b); row {0, 2, 1, 3}[r] = bitreverse2(r)
+    const int rb = ((b & 1) << 1) | (b >> 1);
+    const int rr = ((r & 1) << 1) | (r >> 1);
+    return 4 * rb + rr;
 }
 
 __global__ __launch_bounds__(64) void selftest_reduce_kernel(const double* in, double* out)
@@ -498,8 +531,25 @@ hipError_t launch_selftest_reduce(const double* in, double* out, hipStream_t st)
 // deterministic slot partial[o*ntiles + tile][cell].
 // --------------------------------------------------------------------------
 
+// byte-offset load/store: a wave-uniform base pointer plus a 32-bit per-lane
+// byte offset, so that the address is one SGPR pair plus one VGPR
+template <typename T>
+__device__ __forceinline__ T ldb(const T* base, unsigned off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void stb(T* base, unsigned off, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
 template <typename S, int VL, int BX, int BY>
-__global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
+__device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __restrict__ params,
+                                           const S* __restrict__ etab, const S* __restrict__ ghat,
+                                           const double* __restrict__ lanetab, const int* __restrict__ bricks,
+                                           S* __restrict__ xface, S* __restrict__ yface, S* __restrict__ zface,
+                                           S* __restrict__ spec, double* __restrict__ partial, S* __restrict__ plane)
 {
     const int lane = threadIdx.x;
     int bid = blockIdx.x;
@@ -511,146 +561,161 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
         const int per = nb / 8, rem = nb % 8;
         const int xcd = bid % 8, k = bid / 8;
         const int start = xcd * per + (xcd < rem ? xcd : rem);
-        const int len = per + (xcd < rem ? 1 : 0);
-        if (k < len) bid = start + k;   // always true for a consistent mapping
+        bid = start + k;
     }
     const int tile = bid % A.ntiles;
     bid /= A.ntiles;
     const int bi = bid % A.brick_cnt;
     const int o = A.oct_base + bid / A.brick_cnt;
-    const int* br = A.bricks + 4 * (A.brick_off + bi);
-    const int I = br[0], J = br[1], K = br[2];
+    const int I = bricks[4 * (A.brick_off + bi) + 0];
+    const int J = bricks[4 * (A.brick_off + bi) + 1];
+    const int K = bricks[4 * (A.brick_off + bi) + 2];
     const bool px = (o & 1) != 0, py = (o & 2) != 0, pz = (o & 4) != 0;
     const int slot = tile * 64 + lane;
-    const int N = A.N;
+    const int nx = A.nx, ny = A.ny, nz = A.nz, MT = A.MT;
+    constexpr unsigned SB = sizeof(S);
+    const size_t fstride = (size_t)A.slots * VL;
+    const unsigned lofs = (unsigned)slot * VL * SB;
 
-    // lane constants
-    const double* lt = A.lanetab + ((size_t)o * A.slots + slot) * A.lstride;
+    const int iend = min(BX, nx - I * BX), jend = min(BY, ny - J * BY);
+    const int kend = min(A.bz, nz - K * A.bz);
+    const bool wx = I < A.nbx - 1, wy = J < A.nby - 1, wz = K < A.nbz - 1;
+    const int ir0 = I * BX, jr0 = J * BY, kr0 = K * A.bz;
+    // cell index steps along the octant's sweep directions
+    const int si = px ? 1 : -1, sj = py ? nx : -nx, sk = pz ? nx * ny : -nx * ny;
+    const int cell0 = (px ? ir0 : nx - 1 - ir0) + nx * ((py ? jr0 : ny - 1 - jr0) + ny * (pz ? kr0 : nz - 1 - kr0));
+
+    // face rows: (x) one slot row per (kr, jr), (y) per (kr, ir), (z) per (jr, ir)
+    const S* xin = xface + ((size_t)(o * 2 + ((I - 1) & 1)) * nz * ny + (size_t)kr0 * ny + jr0) * fstride;
+    S* xout = xface + ((size_t)(o * 2 + (I & 1)) * nz * ny + (size_t)kr0 * ny + jr0) * fstride;
+    const S* yin = yface + ((size_t)(o * 2 + ((J - 1) & 1)) * nz * nx + (size_t)kr0 * nx + ir0) * fstride;
+    S* yout = yface + ((size_t)(o * 2 + (J & 1)) * nz * nx + (size_t)kr0 * nx + ir0) * fstride;
+    const S* zin = zface + ((size_t)(o * 2 + ((K - 1) & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
+    S* zout = zface + ((size_t)(o * 2 + (K & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
+    S* sbuf = A.spec_on ? spec + (size_t)(o & 3) * ny * nx * fstride : nullptr;
+
+    // the brick's newest plane of f: lds(jj, ii, v) = plane[((jj*BX + ii)*VL + v)*64 + lane]
+    auto lds = [&](int jj, int ii, int v) -> S& { return plane[((jj * BX + ii) * VL + v) * 64 + lane]; };
+
+    // ---- lane constants
+    const double* lt = lanetab + ((size_t)o * A.slots + slot) * A.lstride;
     const double xiy_d = lt[0], xiz_d = lt[1];
     const S xiy = (S)xiy_d, xiz = (S)xiz_d;
     const S ay = (S)lt[2], az = (S)lt[3];
     const int vb = (int)lt[4], vc = (int)lt[5];
     S xix[VL], ax[VL], asum[VL];
     double wm0[VL], wm1[VL], wm2[VL], wm3[VL];
-    int va[VL], alpha[VL];
+    unsigned oa[VL], oal[VL];
 #pragma unroll
     for (int v = 0; v < VL; ++v) {
         const double x = lt[LT_SHARED + LT_PER_V * v + 0];
         const double w = lt[LT_SHARED + LT_PER_V * v + 2];
+        const int a = (int)lt[LT_SHARED + LT_PER_V * v + 3];
         xix[v] = (S)x;
         ax[v] = (S)lt[LT_SHARED + LT_PER_V * v + 1];
         asum[v] = ax[v] + ay + az;
-        va[v] = (int)lt[LT_SHARED + LT_PER_V * v + 3];
-        alpha[v] = va[v] + A.mx * (vb + A.my * vc);
+        oa[v] = (unsigned)a * SB;
+        oal[v] = (unsigned)(a + A.mx * (vb + A.my * vc)) * SB;
         wm0[v] = w;
         wm1[v] = w * x;
         wm2[v] = w * x * x;
         wm3[v] = w * x * x * x;
     }
+    const unsigned ob = (unsigned)(A.mx + vb) * SB, oc = (unsigned)(A.mx + A.my + vc) * SB;
     const double yz2 = xiy_d * xiy_d + xiz_d * xiz_d;
     const double xiyy = xiy_d * xiy_d, xizz = xiz_d * xiz_d, xiyz = xiy_d * xiz_d;
-
     const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
-    const size_t fstride = (size_t)A.slots * VL;
-    const size_t lofs = (size_t)slot * VL;
+    const int shX = 4 * sideX, shY = 4 * sideY, shZ = 4 * sideZ;
     const int ridx = reduce13_index(lane);
     const bool writer = ((lane & 3) == 0) && ridx < NMOM;
-    double* part = A.partial + ((size_t)(o * A.ntiles + tile) * N) * NMOM;
+    const unsigned oridx = (unsigned)ridx * 8u;
+    double* part = partial + ((size_t)(o * A.ntiles + tile) * A.N) * NMOM;
 
-    S plane[VL][BY][BX];
-#pragma unroll
-    for (int v = 0; v < VL; ++v)
-#pragma unroll
-        for (int jj = 0; jj < BY; ++jj)
-#pragma unroll
-            for (int ii = 0; ii < BX; ++ii) plane[v][jj][ii] = (S)0;
-
-    for (int kk = 0; kk < A.bz; ++kk) {
-        const int kr = K * A.bz + kk;
-        if (kr >= A.nz) break;
-        const int k = pz ? kr : A.nz - 1 - kr;
-#pragma unroll
-        for (int jj = 0; jj < BY; ++jj) {
-            const int jr = J * BY + jj;
-            if (jr >= A.ny) break;
-            const int j = py ? jr : A.ny - 1 - jr;
-#pragma unroll
-            for (int ii = 0; ii < BX; ++ii) {
-                const int ir = I * BX + ii;
-                if (ir >= A.nx) break;
-                const int i = px ? ir : A.nx - 1 - ir;
-                const int cell = i + A.nx * (j + A.ny * k);
-                const uint32_t info = A.cellinfo[cell];
+    for (int kk = 0; kk < kend; ++kk) {
+        const int kcell = cell0 + kk * sk;
+        for (int jj = 0; jj < jend; ++jj) {
+            const int rcell = kcell + jj * sj;
+            const S* xrow_in = xin + ((size_t)kk * ny + jj) * fstride;
+            S* xrow_out = xout + ((size_t)kk * ny + jj) * fstride;
+            S prev[VL];
+            for (int ii = 0; ii < iend; ++ii) {
+                const int cell = rcell + ii * si;
+                const S* P = params + (size_t)cell * PSTRIDE;
+                const uint32_t info = reinterpret_cast<const uint32_t*>(P + P_INFO)[0];
                 if (info & SOLID_BIT) continue;
+                const S* E = etab + (size_t)cell * MT;
 
-                // ---- upwind operands
+                // ---- upwind operands: 0 = interior neighbour (in the plane,
+                //      the previous cell, or the upwind brick's face), 8 =
+                //      symmetry plane, 7 = solid body, else the box face
                 S fx[VL], fy[VL], fz[VL];
                 {
-                    const uint32_t code = (info >> (4 * sideX)) & 15u;
+                    const uint32_t code = (info >> shX) & 15u;
                     if (code == 0) {
                         if (ii > 0) {
 #pragma unroll
-                            for (int v = 0; v < VL; ++v) fx[v] = plane[v][jj][ii - 1];
+                            for (int v = 0; v < VL; ++v) fx[v] = prev[v];
                         } else {
-                            const S* src = A.xface + ((size_t)((o * 2 + ((I - 1) & 1)) * A.nz + kr) * A.ny + jr) * fstride + lofs;
 #pragma unroll
-                            for (int v = 0; v < VL; ++v) fx[v] = src[v];
+                            for (int v = 0; v < VL; ++v) fx[v] = ldb(xrow_in, lofs + v * SB);
                         }
                     } else {
-                        const int kind = (int)code - 1;
-                        const S rf = (S)(A.kind_wall[kind] ? A.rho_w[(size_t)sideX * N + cell] : A.kind_rho[kind]);
+                        const S rf = P[P_RHO_SIDE + sideX];
+                        const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                        for (int v = 0; v < VL; ++v) fx[v] = rf * A.ghat[(size_t)kind * A.NV + alpha[v]];
+                        for (int v = 0; v < VL; ++v) fx[v] = rf * ldb(g, oal[v]);
                     }
                 }
                 {
-                    const uint32_t code = (info >> (4 * sideY)) & 15u;
+                    const uint32_t code = (info >> shY) & 15u;
                     if (code == 0) {
                         if (jj > 0) {
 #pragma unroll
-                            for (int v = 0; v < VL; ++v) fy[v] = plane[v][jj - 1][ii];
+                            for (int v = 0; v < VL; ++v) fy[v] = lds(jj - 1, ii, v);
                         } else {
-                            const S* src = A.yface + ((size_t)((o * 2 + ((J - 1) & 1)) * A.nz + kr) * A.nx + ir) * fstride + lofs;
+                            const S* src = yin + ((size_t)kk * nx + ii) * fstride;
 #pragma unroll
-                            for (int v = 0; v < VL; ++v) fy[v] = src[v];
+                            for (int v = 0; v < VL; ++v) fy[v] = ldb(src, lofs + v * SB);
                         }
                     } else {
-                        const int kind = (int)code - 1;
-                        const S rf = (S)(A.kind_wall[kind] ? A.rho_w[(size_t)sideY * N + cell] : A.kind_rho[kind]);
+                        const S rf = P[P_RHO_SIDE + sideY];
+                        const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                        for (int v = 0; v < VL; ++v) fy[v] = rf * A.ghat[(size_t)kind * A.NV + alpha[v]];
+                        for (int v = 0; v < VL; ++v) fy[v] = rf * ldb(g, oal[v]);
                     }
                 }
                 {
-                    const uint32_t code = (info >> (4 * sideZ)) & 15u;
+                    const uint32_t code = (info >> shZ) & 15u;
                     if (code == 0) {
                         if (kk > 0) {
 #pragma unroll
-                            for (int v = 0; v < VL; ++v) fz[v] = plane[v][jj][ii];
+                            for (int v = 0; v < VL; ++v) fz[v] = lds(jj, ii, v);
                         } else {
-                            const S* src = A.zface + ((size_t)((o * 2 + ((K - 1) & 1)) * A.ny + jr) * A.nx + ir) * fstride + lofs;
+                            const S* src = zin + ((size_t)jj * nx + ii) * fstride;
 #pragma unroll
-                            for (int v = 0; v < VL; ++v) fz[v] = src[v];
+                            for (int v = 0; v < VL; ++v) fz[v] = ldb(src, lofs + v * SB);
                         }
                     } else if (code == CODE_SPECULAR) {
-                        const S* src = A.spec + ((size_t)((o & 3) * A.ny + j) * A.nx + i) * fstride + lofs;
+                        // inflow of a +z velocity at z = 0: the outflow of its
+                        // mirror image (same lane, same octant-local index)
+                        const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
+                        const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
+                        const S* src = sbuf + ((size_t)j * nx + i) * fstride;
 #pragma unroll
-                        for (int v = 0; v < VL; ++v) fz[v] = src[v];
+                        for (int v = 0; v < VL; ++v) fz[v] = ldb(src, lofs + v * SB);
                     } else {
-                        const int kind = (int)code - 1;
-                        const S rf = (S)(A.kind_wall[kind] ? A.rho_w[(size_t)sideZ * N + cell] : A.kind_rho[kind]);
+                        const S rf = P[P_RHO_SIDE + sideZ];
+                        const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                        for (int v = 0; v < VL; ++v) fz[v] = rf * A.ghat[(size_t)kind * A.NV + alpha[v]];
+                        for (int v = 0; v < VL; ++v) fz[v] = rf * ldb(g, oal[v]);
                     }
                 }
 
                 // ---- equilibrium (wave-uniform cell parameters) and update
-                const S* P = A.params + (size_t)cell * PSTRIDE;
                 const S nu = P[P_NU], Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
                 const S L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
                 const S qx = P[P_QX], qy = P[P_QY], qz = P[P_QZ], tT = P[P_TWO_T];
-                const S* E = A.etab + (size_t)cell * A.MT;
-                const S gyz = E[A.mx + vb] * E[A.mx + A.my + vc];
+                const S gyz = ldb(E, ob) * ldb(E, oc);
                 const S cy = xiy - Uy, cz = xiz - Uz;
                 const S cyz2 = cy * cy + cz * cz;
                 const S Lyz = L0 + L2 * cy + L3 * cz;
@@ -661,10 +726,11 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
                     const S cx = xix[v] - Ux;
                     const S c2 = cx * cx + cyz2;
                     const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
-                    const S nfs = gyz * E[va[v]] * poly;
+                    const S nfs = gyz * ldb(E, oa[v]) * poly;
                     const S num = ax[v] * fx[v] + ay * fy[v] + az * fz[v] + nfs;
-                    const S f = num / (asum[v] + nu);
-                    plane[v][jj][ii] = f;
+                    const S f = num * fast_rcp(asum[v] + nu);
+                    prev[v] = f;
+                    lds(jj, ii, v) = f;
                     const double fd = (double)f;
                     u0 += wm0[v] * fd;
                     u1 += wm1[v] * fd;
@@ -673,25 +739,24 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
                 }
 
                 // ---- outflow faces for the downstream bricks
-                if (ii == BX - 1 && I < A.nbx - 1) {
-                    S* dst = A.xface + ((size_t)((o * 2 + (I & 1)) * A.nz + kr) * A.ny + jr) * fstride + lofs;
+                if (ii == BX - 1 && wx) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                    for (int v = 0; v < VL; ++v) stb(xrow_out, lofs + v * SB, prev[v]);
                 }
-                if (jj == BY - 1 && J < A.nby - 1) {
-                    S* dst = A.yface + ((size_t)((o * 2 + (J & 1)) * A.nz + kr) * A.nx + ir) * fstride + lofs;
+                if (jj == BY - 1 && wy) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                    for (int v = 0; v < VL; ++v) stb(yout + ((size_t)kk * nx + ii) * fstride, lofs + v * SB, prev[v]);
                 }
-                if (kk == A.bz - 1 && K < A.nbz - 1) {
-                    S* dst = A.zface + ((size_t)((o * 2 + (K & 1)) * A.ny + jr) * A.nx + ir) * fstride + lofs;
+                if (kk == A.bz - 1 && wz) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                    for (int v = 0; v < VL; ++v) stb(zout + ((size_t)jj * nx + ii) * fstride, lofs + v * SB, prev[v]);
                 }
-                if (A.spec_on && !pz && k == 0) {
-                    S* dst = A.spec + ((size_t)((o & 3) * A.ny + j) * A.nx + i) * fstride + lofs;
+                if (sbuf != nullptr && !pz && kr0 + kk == nz - 1) {
+                    const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
+                    const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
+                    S* dst = sbuf + ((size_t)j * nx + i) * fstride;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) dst[v] = plane[v][jj][ii];
+                    for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
                 }
 
                 // ---- 13 raw moments of this tile at this cell
@@ -711,18 +776,24 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
                 m[11] = xiy_d * t2;
                 m[12] = xiz_d * t2;
                 const double tot = wave_reduce13(m);
-                if (writer) part[(size_t)cell * NMOM + ridx] = tot;
+                if (writer) stb(part + (size_t)cell * NMOM, oridx, tot);
             }
         }
     }
 }
 
+template <typename S, int VL, int BX, int BY>
+__global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
+{
+    __shared__ S plane[BY * BX * VL * 64];
+    sweep_body<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
+                              A.spec, A.partial, plane);
+}
+
 // instantiated variants: (precision, VL, BX, BY)
 #define DVM_SWEEP_VARIANTS(X) \
-    X(double, 1, 4, 4) X(double, 2, 4, 4) X(double, 4, 4, 4) \
-    X(double, 1, 8, 8) X(double, 2, 8, 4) X(double, 1, 8, 4) \
-    X(float, 1, 4, 4) X(float, 2, 4, 4) X(float, 4, 4, 4) \
-    X(float, 1, 8, 8) X(float, 2, 8, 4) X(float, 2, 8, 8)
+    X(double, 1, 4, 4) X(double, 2, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) X(double, 4, 4, 4) \
+    X(float, 1, 4, 4) X(float, 2, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2) X(float, 4, 4, 4)
 
 bool sweep_variant_available(int prec, int vl, int bx, int by)
 {

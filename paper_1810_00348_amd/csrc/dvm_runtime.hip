@@ -366,7 +366,7 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
 
     HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[0], st));
-    HIPCHK(launch_params(C, D, W + cur * 5 * N, q + cur * 3 * N, c->ws + c->off.params,
+    HIPCHK(launch_params(C, D, W + cur * 5 * N, q + cur * 3 * N, rw + cur * 6 * N, c->ws + c->off.params,
                          c->ws + c->off.etab, c->prec, flag, st));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[1], st));
 
@@ -383,7 +383,6 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.params = c->P<S>(c->off.params);
                 a.etab = c->P<S>(c->off.etab);
                 a.cellinfo = c->P<uint32_t>(c->off.cellinfo);
-                a.rho_w = rw + cur * 6 * N;
                 a.ghat = c->P<S>(c->off.ghat);
                 a.lanetab = c->P<double>(c->off.lanetab);
                 a.bricks = c->P<int>(c->off.bricks);
@@ -400,8 +399,8 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.oct_base = c->spec_on ? 4 * ph : 0;
                 a.noct = c->spec_on ? 4 : 8;
                 a.spec_on = c->spec_on ? 1 : 0;
+                a.has_solid = c->nfluid < c->N ? 1 : 0;
                 a.nblocks = a.noct * cnt * c->ntiles;
-                for (int k = 0; k < 8; ++k) { a.kind_rho[k] = c->kind_rho[k]; a.kind_wall[k] = c->kind_wall[k]; }
             };
             hipError_t e;
             if (c->prec == DVM_F64) {
@@ -457,7 +456,8 @@ dvm_status upload_initial(dvm_ctx* c, const std::vector<double>& Wh)
     HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
     const Consts C = make_consts(c);
     const DevPtrs D = make_ptrs(c);
-    HIPCHK(launch_params(C, D, W, q, c->ws + c->off.params, c->ws + c->off.etab, c->prec, flag, st));
+    HIPCHK(hipMemsetAsync(rw, 0, sizeof(double) * 6 * N, st));
+    HIPCHK(launch_params(C, D, W, q, rw, c->ws + c->off.params, c->ws + c->off.etab, c->prec, flag, st));
     HIPCHK(launch_wall_init(C, D, c->ws + c->off.params, c->ws + c->off.etab, c->P<double>(c->off.ghat64),
                             c->P<double>(c->off.gout), rw, c->prec, st));
     int hflag = 0;
