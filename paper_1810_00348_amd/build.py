@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdvm_hip.so")
-SOURCES = ["dvm_kernels.hip", "dvm_runtime.hip"]
+SOURCES = ["dvm_kernels.hip", "dvm_runtime.hip", "wsn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

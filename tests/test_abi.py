@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point include/dvm.h
+"""The C-ABI library loads and exports every entry point that include/*.h
 declares; host-only calls (no GPU work) behave as documented."""
 import ctypes as C
 import os
@@ -9,9 +9,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    src = open(os.path.join(ROOT, "include", "dvm.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:dvm_status|const char\*|void)\s+(dvm_\w+)\s*\(", src, re.M)))
+def declared_symbols(header="dvm.h", prefix="dvm_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    pat = r"^\s*(?:dvm_status|int|size_t|const char\*|void)\s+(" + prefix + r"\w+)\s*\("
+    return sorted(set(re.findall(pat, src, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -30,6 +31,31 @@ def test_every_declared_symbol_is_exported(L):
     for s in syms:
         assert hasattr(lib, s), s
     assert set(syms) <= set(L.EXPORTS), set(syms) - set(L.EXPORTS)
+
+
+def test_every_warm_start_symbol_is_exported(L):
+    lib = L.lib()
+    syms = declared_symbols("wsn.h", "wsn_")
+    assert len(syms) == 13, syms
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["dvm.h", "wsn.h"]
+
+
+def test_warm_start_argument_errors(L):
+    from paper_1810_00348_amd import warmstart as W
+    lib = W.wsn_lib()
+    h = C.c_void_p()
+    # rejected before any device call
+    assert lib.wsn_create(3, 5, 12, 16, 16, 16, None, C.byref(h)) == -1
+    assert b"multiple of 8" in lib.wsn_last_error()
+    assert lib.wsn_create(3, 5, 32, 18, 16, 16, None, C.byref(h)) == -1
+    assert lib.wsn_create(3, 5, 128, 16, 16, 16, None, C.byref(h)) == -1
+    assert lib.wsn_create(3, 5, 32, 16, 16, 16, None, None) == -1
+    assert not h.value
+    assert lib.wsn_num_params(None) == 0
+    assert lib.wsn_forward(None, None, 4, 4, 4, None) == -1
+    assert lib.wsn_test_conv(4, 4, 4, 3, 5, 9, None, None, None, None, None, None, None, None) == -1
 
 
 def _ctx(L, case, prec=0):

@@ -1,0 +1,184 @@
+"""The warm-start network's HIP/MFMA kernels against the FP64 numpy
+reference (oracle/unet_oracle.py) on identical BF16-rounded operands."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from oracle import unet_oracle as U
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _ws():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_00348_amd import warmstart
+    return warmstart
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def test_mfma_tile_layout():
+    ws = _ws()
+    rng = np.random.default_rng(0)
+    a = U.bf16_round(rng.standard_normal((16, 32))).astype(np.float32)
+    b = U.bf16_round(rng.standard_normal((32, 16))).astype(np.float32)
+    c = np.zeros((16, 16), dtype=np.float32)
+    assert ws.wsn_lib().wsn_selftest_mfma(_p(a), _p(b), _p(c)) == 0
+    ref = a.astype(np.float64) @ b.astype(np.float64)
+    assert np.abs(c - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape,ci,co,taps", [((4, 6, 5), 3, 5, 27), ((8, 4, 4), 16, 32, 27),
+                                              ((5, 5, 5), 32, 5, 1), ((4, 4, 8), 96, 32, 27)])
+def test_conv_kernels_match_reference(shape, ci, co, taps):
+    ws = _ws()
+    D, H, W = shape
+    rng = np.random.default_rng(ci * 100 + co)
+    x = U.bf16_round(rng.standard_normal((D, H, W, ci))).astype(np.float32)
+    w = U.bf16_round(rng.standard_normal((taps, co, ci)) / np.sqrt(taps * ci)).astype(np.float32)
+    b = rng.standard_normal(co).astype(np.float32)
+    gy = U.bf16_round(rng.standard_normal((D, H, W, co))).astype(np.float32)
+    y = np.zeros((D, H, W, co), np.float32)
+    gx = np.zeros((D, H, W, ci), np.float32)
+    gw = np.zeros((taps, co, ci), np.float32)
+    gb = np.zeros(co, np.float32)
+    rc = ws.wsn_lib().wsn_test_conv(D, H, W, ci, co, taps, _p(x), _p(w), _p(b), _p(gy), _p(y), _p(gx), _p(gw), _p(gb))
+    assert rc == 0, ws.wsn_lib().wsn_last_error()
+    X, Wt, G = x.astype(np.float64), w.astype(np.float64), gy.astype(np.float64)
+    ry = U.conv3d(X, Wt, b.astype(np.float64))
+    rgx, rgw, rgb = U.conv3d_backward(X, Wt, G)
+    for name, got, ref in (("y", y, ry), ("gx", gx, rgx), ("gw", gw, rgw), ("gb", gb, rgb)):
+        err = np.abs(got - ref).max() / max(1e-30, np.abs(ref).max())
+        # FP32 accumulation over K terms (K = taps * channels or voxels)
+        assert err < 2e-5, (name, err)
+
+
+def _bf16_network_reference(theta, x, t, mask, specs):
+    """FP64 forward/backward with the HIP path's BF16 rounding points:
+    weights, the network input, every stored activation (conv outputs and
+    pooled/upsampled tensors) and every pre-activation gradient."""
+    P = U.unpack(theta, specs)
+    P = [(U.bf16_round(W), b) for W, b in P]
+    tape = {}
+
+    def conv(i, inp):
+        W, b = P[i]
+        pre = U.conv3d(inp, W, b)
+        out = U.relu(pre) if specs[i][4] else pre
+        tape[i] = inp
+        return U.bf16_round(out) if specs[i][4] else out
+
+    a = conv(0, U.bf16_round(x))
+    s1 = conv(1, a)
+    a = conv(2, U.bf16_round(U.avgpool2(s1)))
+    s2 = conv(3, a)
+    a = conv(4, U.bf16_round(U.avgpool2(s2)))
+    a = conv(5, a)
+    a = conv(6, np.concatenate([U.upsample2(a), s2], axis=-1))
+    a = conv(7, a)
+    a = conv(8, np.concatenate([U.upsample2(a), s1], axis=-1))
+    a = conv(9, a)
+    y = conv(10, a)
+    L, gy = U.mse(y, t, mask)
+    grads = [None] * len(specs)
+
+    def bconv(i, g, act):
+        if specs[i][4]:
+            g = g * (act > 0)
+        g = U.bf16_round(g)
+        gx, gW, gb = U.conv3d_backward(tape[i], P[i][0], g)
+        grads[i] = (gW, gb)
+        return gx
+
+    acts = {}
+    # recompute the stored activations for the masks
+    a0 = conv(0, U.bf16_round(x)); acts[0] = a0
+    acts[1] = s1
+    acts[2] = tape[3]
+    acts[3] = s2
+    acts[4] = tape[5]
+    acts[5] = U.bf16_round(U.relu(U.conv3d(tape[5], *P[5])))
+    acts[6] = tape[7]
+    acts[7] = U.bf16_round(U.relu(U.conv3d(tape[7], *P[7])))
+    acts[8] = tape[9]
+    acts[9] = tape[10]
+    b1, b2, b3 = specs[1][2], specs[3][2], specs[5][2]
+    g = bconv(10, gy, None)
+    g = bconv(9, g, acts[9])
+    g = bconv(8, g, acts[8])
+    g_up, g_s1 = g[..., :b2], g[..., b2:]
+    g = bconv(7, U.upsample2_backward(g_up), acts[7])
+    g = bconv(6, g, acts[6])
+    g_up, g_s2 = g[..., :b3], g[..., b3:]
+    g = bconv(5, U.upsample2_backward(g_up), acts[5])
+    g = bconv(4, g, acts[4])
+    g = bconv(3, U.avgpool2_backward(g) + g_s2, acts[3])
+    g = bconv(2, g, acts[2])
+    g = bconv(1, U.avgpool2_backward(g) + g_s1, acts[1])
+    bconv(0, g, acts[0])
+    grad = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+    return y, L, grad
+
+
+def test_network_forward_and_gradient_match_reference():
+    ws = _ws()
+    import torch
+    specs = U.layer_specs(3, 5, 8)
+    theta = U.init_params(specs, seed=11)
+    theta[-5:] = 0.1
+    rng = np.random.default_rng(12)
+    D = H = W = 8
+    x = rng.standard_normal((D, H, W, 3)).astype(np.float32)
+    t = rng.standard_normal((D, H, W, 5)).astype(np.float32)
+    mask = (rng.random((D, H, W)) > 0.1).astype(np.float32)
+    net = ws.WarmStartNet(max_grid=(8, 8, 8), base=8)
+    assert net.num_params == theta.size
+    net.set_params(theta.astype(np.float32))
+    dev = net.device
+    xt = torch.from_numpy(x).to(dev)
+    y = net.forward(xt).cpu().numpy()
+    net.zero_grad()
+    loss = net.backward_mse(torch.from_numpy(t).to(dev), torch.from_numpy(mask).to(dev))
+    g = net.grads()
+    ry, rL, rg = _bf16_network_reference(theta.astype(np.float32).astype(np.float64), x.astype(np.float64),
+                                         t.astype(np.float64), mask.astype(np.float64), specs)
+    assert np.abs(y - ry).max() < 2e-2 * np.abs(ry).max()
+    assert abs(loss - rL) < 1e-2 * rL
+    # relative L2 error of the whole gradient, and per layer
+    assert np.linalg.norm(g - rg) < 3e-2 * np.linalg.norm(rg)
+    cos = g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg))
+    assert cos > 0.999
+
+
+def test_training_reduces_the_loss():
+    ws = _ws()
+    import torch
+    specs = U.layer_specs(3, 5, 8)
+    net = ws.WarmStartNet(max_grid=(8, 8, 8), base=8)
+    net.set_params(U.init_params(specs, seed=5).astype(np.float32))
+    rng = np.random.default_rng(6)
+    dev = net.device
+    z, yy, xx = np.meshgrid(*[np.linspace(-1, 1, 8)] * 3, indexing="ij")
+    data = []
+    for k in range(3):
+        x = np.stack([np.full_like(z, 0.3 * k), np.full_like(z, 0.2), (np.abs(yy) > 0.8) * 1.0], -1)
+        t = np.stack([np.sin(z + k), xx * yy, yy, z * 0.5, xx], -1)
+        data.append((torch.from_numpy(x.astype(np.float32)).to(dev), torch.from_numpy(t.astype(np.float32)).to(dev)))
+    mask = torch.ones((8, 8, 8), dtype=torch.float32, device=dev)
+    losses = []
+    for step in range(60):
+        net.zero_grad()
+        tot = 0.0
+        for x, t in data:
+            net.forward(x)
+            tot += net.backward_mse(t, mask, 1.0 / len(data))
+        net.adam_step(3e-3)
+        losses.append(tot)
+    assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
