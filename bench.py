@@ -15,6 +15,11 @@ Prints ONE JSON line (rank 0).  Options:
   --no-cpu      skip the CPU oracle baseline
   --traffic F   JSON file with measured HBM bytes per sweep launch (from
                 rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, calibrated)
+  --time-to-residual
+                instead of the throughput line: iterations and wall time to
+                residual 1e-6 from the uniform start, FP64 and FP32 storage,
+                and the per-field difference of the two converged solutions
+                (one JSON line per workload)
 """
 from __future__ import annotations
 
@@ -131,6 +136,41 @@ def cpu_baseline(case, budget_s: float = 25.0):
     }
 
 
+def time_to_residual(workloads, tol=1e-6, max_iters=3000):
+    """Wall time to the residual tolerance from the uniform start (the full
+    dvm_iterate loop including its per-iteration residual read-back), FP64
+    and FP32 storage; per-field max |f32 - f64| / max |f64|."""
+    import numpy as np
+    import torch
+    from paper_1810_00348_amd.solver import Solver
+    from paper_1810_00348_amd import cases
+    for name, case in workloads:
+        row = {"workload": name, "case": case.name, "points_per_iteration": case.points, "tol": tol}
+        fields = {}
+        for prec in ("f64", "f32"):
+            s = Solver(case, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.init_uniform()
+            it, r, ok = s.iterate(max_iters, tol=tol)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            fields[prec] = s.fields()
+            row[prec] = {"iters": it, "seconds": round(dt, 3), "converged": ok, "residual": r,
+                         "ms_per_iter": round(dt * 1e3 / max(it, 1), 3)}
+            del s
+            torch.cuda.empty_cache()
+        a, b = fields["f32"], fields["f64"]
+        err = {}
+        for key, x, y in (("rho", a["rho"], b["rho"]), ("ux", a["u"][0], b["u"][0]),
+                          ("uy", a["u"][1], b["u"][1]), ("uz", a["u"][2], b["u"][2]),
+                          ("T", a["T"], b["T"]), ("qx", a["q"][0], b["q"][0])):
+            err[key] = float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+        row["f32_vs_f64_converged"] = err
+        row["f32_speedup_time_to_residual"] = round(row["f64"]["seconds"] / row["f32"]["seconds"], 3)
+        print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +181,7 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic", default=None)
+    ap.add_argument("--time-to-residual", action="store_true")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=6, default=None,
@@ -166,6 +207,13 @@ def main():
         print("bench.py: this build runs on one GPU only (the sweep shards by velocity across "
               "GPUs by design, but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.time_to_residual:
+        from paper_1810_00348_amd import cases
+        wl = [(f"c2_kn{kn:g}", cases.config("c2", kn=kn)) for kn in (10.0, 1.0, 0.1)]
+        wl.append(("c3", cases.config("c3")))
+        time_to_residual(wl)
+        return
 
     import torch
     from paper_1810_00348_amd.solver import Solver

@@ -286,3 +286,181 @@ def train(net: WarmStartNet, data, chan_std, epochs: int, lr: float, batch: int 
         if log:
             log(f"epoch {ep} loss {history[-1]:.5f}")
     return history
+
+
+# ------------------------------------------------------------------ pipeline
+
+def generate(case_list, tol=1e-6, max_iters=4000, precision="f64", log=None):
+    """Converged fields of every case from the plain uniform start."""
+    out = []
+    for k, c in enumerate(case_list):
+        r = solve(c, tol, max_iters, precision=precision)
+        out.append((c, r["fields"], {"iters": r["iters"], "seconds": r["seconds"], "converged": r["converged"]}))
+        if log:
+            log(f"gen {k} {c.name} n={c.n[0]} m={c.m[0]} kn={c.kn:.3f} lid={c.faces[3].u[0]:.3f} "
+                f"iters={r['iters']} conv={r['converged']} {r['seconds']:.2f}s")
+    return out
+
+
+def channel_scale(data) -> np.ndarray:
+    """Per-channel RMS of the lid-normalised deviations over all training cells."""
+    acc = np.zeros(5)
+    n = 0
+    for case, fields in data:
+        t, m = targets(case, fields, np.ones(5))
+        sel = m > 0
+        acc += (t[sel] ** 2).sum(axis=0)
+        n += int(sel.sum())
+    return np.sqrt(acc / max(n, 1)).astype(np.float32) + np.float32(1e-6)
+
+
+def field_difference(a: Dict[str, np.ndarray], b: Dict[str, np.ndarray]) -> Dict[str, float]:
+    """max_c |a - b| / max_c |b| per macroscopic field (normwise relative)."""
+    out = {}
+    for key, x, y in (("rho", a["rho"], b["rho"]), ("ux", a["u"][0], b["u"][0]), ("uy", a["u"][1], b["u"][1]),
+                      ("uz", a["u"][2], b["u"][2]), ("T", a["T"], b["T"])):
+        out[key] = float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+    return out
+
+
+def evaluate(net, case_list, chan_std, tol=1e-6, max_iters=4000, log=None):
+    """Plain and warm-started FP64 solves of every case."""
+    rows = []
+    for k, c in enumerate(case_list):
+        plain = solve(c, tol, max_iters)
+        warm = warm_started_solve(net, c, chan_std, tol, max_iters)
+        rho, u, T = predict(net, c, chan_std)
+        pred = {"rho": rho, "u": u, "T": T}
+        row = {"case": c.name, "n": c.n[0], "m": c.m[0], "kn": c.kn, "lid": c.faces[3].u[0],
+               "plain_iters": plain["iters"], "plain_s": plain["seconds"], "plain_converged": plain["converged"],
+               "warm_iters": warm["iters"], "warm_s": warm["seconds"], "warm_converged": warm["converged"],
+               "predict_s": warm["predict_seconds"], "fallback": warm["fallback"],
+               "final_diff": field_difference(warm["fields"], plain["fields"]),
+               "prediction_error": field_difference(pred, plain["fields"])}
+        rows.append(row)
+        if log:
+            log(f"eval {k} {c.name} kn={c.kn:.3f} lid={row['lid']:.3f} plain {plain['iters']} it "
+                f"{plain['seconds']:.2f}s | warm {warm['iters']} it {warm['seconds']:.2f}s "
+                f"fallback={warm['fallback']} diff={max(row['final_diff'].values()):.1e}")
+    return rows
+
+
+def store_params(theta: np.ndarray, specs) -> np.ndarray:
+    """Weights rounded to BF16 (the precision the kernels use them in; biases
+    stay FP32), so that the stored file compresses to the BF16 size."""
+    out = np.array(theta, dtype=np.float32)
+    off = 0
+    for _, ci, co, taps, _ in specs:
+        nw = taps * co * ci
+        w = out[off:off + nw].view(np.uint32)
+        w += np.uint32(0x7FFF) + ((w >> np.uint32(16)) & np.uint32(1))
+        w &= np.uint32(0xFFFF0000)
+        off += nw + co
+    return out
+
+
+def save_weights(path: str, theta: np.ndarray, chan_std: np.ndarray, meta: dict):
+    import json
+    np.savez_compressed(path, theta=theta, chan_std=chan_std.astype(np.float32),
+                        meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load_weights(path: str):
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        return z["theta"].astype(np.float32), z["chan_std"].astype(np.float32), json.loads(bytes(z["meta"]).decode())
+
+
+def layer_table(base=NET_BASE, cin=NET_IN, cout=NET_OUT):
+    """(name, c_in, c_out, taps, relu) per convolution, the order of the
+    parameter vector of include/wsn.h."""
+    b1, b2, b3 = base, 2 * base, 4 * base
+    return [("e1a", cin, b1, 27, True), ("e1b", b1, b1, 27, True), ("e2a", b1, b2, 27, True),
+            ("e2b", b2, b2, 27, True), ("b1", b2, b3, 27, True), ("b2", b3, b3, 27, True),
+            ("d2a", b3 + b2, b2, 27, True), ("d2b", b2, b2, 27, True), ("d1a", b2 + b1, b1, 27, True),
+            ("d1b", b1, b1, 27, True), ("out", b1, cout, 1, False)]
+
+
+def init_theta(seed: int, base=NET_BASE, cin=NET_IN, cout=NET_OUT) -> np.ndarray:
+    """He-normal weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, ci, co, taps, relu in layer_table(base, cin, cout):
+        std = math.sqrt((2.0 if relu else 1.0) / (taps * ci))
+        parts.append((rng.standard_normal(taps * co * ci) * std).astype(np.float32))
+        parts.append(np.zeros(co, np.float32))
+    return np.concatenate(parts)
+
+
+def pipeline(out_dir: str, n_train=256, n_eval=32, epochs=40, lr=1e-3, batch=4, tol=1e-6, max_iters=4000,
+             time_budget_s=None, log=print):
+    """Generate training solves, train the network on the GPU, evaluate the
+    held-out cases; writes report.json and weights.npz into out_dir."""
+    import json
+    import os
+    os.makedirs(out_dir, exist_ok=True)
+    t_start = time.perf_counter()
+    train_cases = training_cases(n_train)
+    gen = generate(train_cases, tol, max_iters, log=log)
+    t_gen = time.perf_counter() - t_start
+    data = [(c, f) for c, f, s in gen if s["converged"]]
+    chan_std = channel_scale(data)
+    big = max(max(pad4(n) for n in c.n) for c in train_cases + heldout_cases(n_eval))
+    net = WarmStartNet(max_grid=(big, big, big))
+    net.set_params(init_theta(seed=7))
+    t0 = time.perf_counter()
+    sched_epochs = epochs
+    history = []
+    for ep in range(epochs):
+        # cosine decay of the learning rate
+        cur = lr * 0.5 * (1 + math.cos(math.pi * ep / sched_epochs))
+        h = train(net, data, chan_std, 1, cur, batch, seed=1000 + ep)
+        history.append(h[0])
+        log(f"epoch {ep} lr {cur:.2e} loss {h[0]:.5f} ({time.perf_counter() - t0:.0f}s)")
+        if time_budget_s and time.perf_counter() - t_start > time_budget_s:
+            log("time budget reached, stopping training")
+            break
+    t_train = time.perf_counter() - t0
+    theta = store_params(net.params(), layer_table())
+    net.set_params(theta)
+    rows = evaluate(net, heldout_cases(n_eval), chan_std, tol, max_iters, log=log)
+    meta = {"n_train": n_train, "converged_train": len(data), "epochs_run": len(history), "lr": lr,
+            "batch": batch, "tol": tol, "seed_train": 1810_00348, "seed_eval": 1810_00348 + 1}
+    save_weights(os.path.join(out_dir, "weights.npz"), theta, chan_std, meta)
+
+    def tot(key):
+        return float(sum(r[key] for r in rows))
+    summary = {"plain_iters": tot("plain_iters"), "warm_iters": tot("warm_iters"), "plain_s": tot("plain_s"),
+               "warm_s": tot("warm_s"), "fallbacks": int(sum(r["fallback"] for r in rows)),
+               "max_final_diff": max(max(r["final_diff"].values()) for r in rows),
+               "median_iter_ratio": float(np.median([r["warm_iters"] / max(1, r["plain_iters"]) for r in rows]))}
+    report = {"meta": meta, "gen": [{"case": c.name, "n": c.n[0], "m": c.m[0], "kn": c.kn,
+                                     "lid": c.faces[3].u[0], **s} for c, f, s in gen],
+              "gen_seconds": t_gen, "train_seconds": t_train, "loss_history": history,
+              "chan_std": chan_std.tolist(), "eval": rows, "summary": summary}
+    with open(os.path.join(out_dir, "report.json"), "w") as fh:
+        json.dump(report, fh, indent=1)
+    log(json.dumps(summary))
+    return report
+
+
+def main(argv=None):
+    import argparse
+    p = argparse.ArgumentParser(description="learned warm start: generate, train, evaluate")
+    p.add_argument("--out", required=True)
+    p.add_argument("--n-train", type=int, default=256)
+    p.add_argument("--n-eval", type=int, default=32)
+    p.add_argument("--epochs", type=int, default=40)
+    p.add_argument("--lr", type=float, default=1e-3)
+    p.add_argument("--batch", type=int, default=4)
+    p.add_argument("--max-iters", type=int, default=4000)
+    p.add_argument("--time-budget", type=float, default=None)
+    a = p.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+    pipeline(a.out, a.n_train, a.n_eval, a.epochs, a.lr, a.batch, 1e-6, a.max_iters, a.time_budget, log)
+
+
+if __name__ == "__main__":
+    main()
