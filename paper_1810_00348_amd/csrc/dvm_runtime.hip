@@ -127,7 +127,7 @@ void derive_schedule(dvm_ctx* c)
     int vl = c->prec == DVM_F64 ? 2 : 4;
     if (nax % vl) vl = (nax % 2) ? 1 : 2;
     vl = env_int("DVM_VL", vl);
-    int bx = env_int("DVM_BX", 4), by = env_int("DVM_BY", 4);
+    int bx = env_int("DVM_BX", 4), by = env_int("DVM_BY", 2);
     if (!sweep_variant_available(c->prec, vl, bx, by)) { vl = 1; bx = 4; by = 4; }
     c->VL = vl;
     c->BX = bx;

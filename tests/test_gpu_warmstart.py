@@ -182,3 +182,33 @@ def test_training_reduces_the_loss():
         net.adam_step(3e-3)
         losses.append(tot)
     assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
+
+
+WEIGHTS = os.path.join(ROOT, "paper_1810_00348_amd", "data", "warmstart_unet.npz")
+
+
+def test_trained_warm_start_gains_over_uniform_start():
+    """The committed network (trained on the GPU by the warm-start pipeline)
+    seeds held-out cavities it has not seen: the solver reaches the same
+    residual tolerance in fewer iterations, and the converged fields agree
+    with the uniform-start solution."""
+    ws = _ws()
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("no trained weights yet: python -m paper_1810_00348_amd.warmstart --out DIR")
+    theta, chan_std, meta = ws.load_weights(WEIGHTS)
+    held = sorted(ws.heldout_cases(), key=lambda c: c.ncells * c.nvel)[:4]
+    big = max(max(c.n) for c in held)
+    net = ws.WarmStartNet(max_grid=(big, big, big))
+    net.set_params(theta)
+    plain_total = warm_total = 0
+    for c in held:
+        plain = ws.solve(c, tol=1e-6, max_iters=4000)
+        warm = ws.warm_started_solve(net, c, chan_std, tol=1e-6, max_iters=4000)
+        assert plain["converged"] and warm["converged"] and not warm["fallback"], c.name
+        assert warm["residual"] <= 1e-6
+        diff = ws.field_difference(warm["fields"], plain["fields"])
+        print(c.name, c.kn, plain["iters"], warm["iters"], diff)
+        assert max(diff.values()) < 2e-3, (c.name, diff)
+        plain_total += plain["iters"]
+        warm_total += warm["iters"]
+    assert warm_total < 0.8 * plain_total, (warm_total, plain_total)
