@@ -93,7 +93,7 @@ hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind
 hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* params, const void* etab,
                             const double* ghat64, const double* gout, double* rho_w, int prec,
                             hipStream_t st);
-hipError_t launch_sweep(int prec, int vl, int bx, int by, const void* args, hipStream_t st);
+hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, const void* args, hipStream_t st);
 hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
                            const double* gout, double* Wn, double* qn, double* rwn,
                            double* blockmass, int nblocks, int* flag, hipStream_t st);

@@ -782,6 +782,286 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
     }
 }
 
+// Software-pipelined form of the same sweep.  The cells of the brick are
+// visited in the same order through one flat loop; while cell n is computed,
+// the loads of cell n+1 are already in flight: its Gaussian-table gathers and,
+// by position alone, the inflow values it will take from the upwind bricks'
+// x and y faces (when its own boundary code says otherwise, e.g. next to a
+// solid, the prefetched value is simply not used).  The first plane's z inflow
+// is staged into the LDS plane before the loop, so every plane takes its z
+// upwind operand from LDS.  Moments are accumulated from the node weight and
+// abscissa (three more multiplies per velocity instead of four per-velocity
+// weight products held in registers).
+template <typename S, int VL, int BX, int BY>
+__device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __restrict__ params,
+                                              const S* __restrict__ etab, const S* __restrict__ ghat,
+                                              const double* __restrict__ lanetab, const int* __restrict__ bricks,
+                                              S* __restrict__ xface, S* __restrict__ yface, S* __restrict__ zface,
+                                              S* __restrict__ spec, double* __restrict__ partial,
+                                              S* __restrict__ plane)
+{
+    const int lane = threadIdx.x;
+    int bid = blockIdx.x;
+    {
+        const int nb = A.nblocks;
+        const int per = nb / 8, rem = nb % 8;
+        const int xcd = bid % 8, k = bid / 8;
+        const int start = xcd * per + (xcd < rem ? xcd : rem);
+        bid = start + k;
+    }
+    const int tile = bid % A.ntiles;
+    bid /= A.ntiles;
+    const int bi = bid % A.brick_cnt;
+    const int o = A.oct_base + bid / A.brick_cnt;
+    const int I = bricks[4 * (A.brick_off + bi) + 0];
+    const int J = bricks[4 * (A.brick_off + bi) + 1];
+    const int K = bricks[4 * (A.brick_off + bi) + 2];
+    const bool px = (o & 1) != 0, py = (o & 2) != 0, pz = (o & 4) != 0;
+    const int slot = tile * 64 + lane;
+    const int nx = A.nx, ny = A.ny, nz = A.nz, MT = A.MT;
+    constexpr unsigned SB = sizeof(S);
+    const size_t fstride = (size_t)A.slots * VL;
+    const unsigned lofs = (unsigned)slot * VL * SB;
+
+    const int iend = min(BX, nx - I * BX), jend = min(BY, ny - J * BY);
+    const int kend = min(A.bz, nz - K * A.bz);
+    const bool wx = I < A.nbx - 1, wy = J < A.nby - 1, wz = K < A.nbz - 1;
+    const int ir0 = I * BX, jr0 = J * BY, kr0 = K * A.bz;
+    const int si = px ? 1 : -1, sj = py ? nx : -nx, sk = pz ? nx * ny : -nx * ny;
+    const int cell0 = (px ? ir0 : nx - 1 - ir0) + nx * ((py ? jr0 : ny - 1 - jr0) + ny * (pz ? kr0 : nz - 1 - kr0));
+
+    const S* xin = xface + ((size_t)(o * 2 + ((I - 1) & 1)) * nz * ny + (size_t)kr0 * ny + jr0) * fstride;
+    S* xout = xface + ((size_t)(o * 2 + (I & 1)) * nz * ny + (size_t)kr0 * ny + jr0) * fstride;
+    const S* yin = yface + ((size_t)(o * 2 + ((J - 1) & 1)) * nz * nx + (size_t)kr0 * nx + ir0) * fstride;
+    S* yout = yface + ((size_t)(o * 2 + (J & 1)) * nz * nx + (size_t)kr0 * nx + ir0) * fstride;
+    const S* zin = zface + ((size_t)(o * 2 + ((K - 1) & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
+    S* zout = zface + ((size_t)(o * 2 + (K & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
+    S* sbuf = A.spec_on ? spec + (size_t)(o & 3) * ny * nx * fstride : nullptr;
+
+    auto lds = [&](int jj, int ii, int v) -> S& { return plane[((jj * BX + ii) * VL + v) * 64 + lane]; };
+
+    // ---- lane constants
+    const double* lt = lanetab + ((size_t)o * A.slots + slot) * A.lstride;
+    const double xiy_d = lt[0], xiz_d = lt[1];
+    const S xiy = (S)xiy_d, xiz = (S)xiz_d;
+    const S ay = (S)lt[2], az = (S)lt[3];
+    const int vb = (int)lt[4], vc = (int)lt[5];
+    S xix[VL], ax[VL], asum[VL];
+    double xd[VL], wd[VL];
+    unsigned oa[VL], oal[VL];
+#pragma unroll
+    for (int v = 0; v < VL; ++v) {
+        xd[v] = lt[LT_SHARED + LT_PER_V * v + 0];
+        wd[v] = lt[LT_SHARED + LT_PER_V * v + 2];
+        const int a = (int)lt[LT_SHARED + LT_PER_V * v + 3];
+        xix[v] = (S)xd[v];
+        ax[v] = (S)lt[LT_SHARED + LT_PER_V * v + 1];
+        asum[v] = ax[v] + ay + az;
+        oa[v] = (unsigned)a * SB;
+        oal[v] = (unsigned)(a + A.mx * (vb + A.my * vc)) * SB;
+    }
+    const unsigned ob = (unsigned)(A.mx + vb) * SB, oc = (unsigned)(A.mx + A.my + vc) * SB;
+    const double yz2 = xiy_d * xiy_d + xiz_d * xiz_d;
+    const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
+    const int shX = 4 * sideX, shY = 4 * sideY, shZ = 4 * sideZ;
+    const int ridx = reduce13_index(lane);
+    const bool writer = ((lane & 3) == 0) && ridx < NMOM;
+    const unsigned oridx = (unsigned)ridx * 8u;
+    double* part = partial + ((size_t)(o * A.ntiles + tile) * A.N) * NMOM;
+
+    // ---- the first plane's z inflow: the upwind brick's outflow face
+    if (kr0 > 0) {
+        for (int jj = 0; jj < jend; ++jj)
+            for (int ii = 0; ii < iend; ++ii) {
+                const S* src = zin + ((size_t)jj * nx + ii) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) lds(jj, ii, v) = ldb(src, lofs + v * SB);
+            }
+    }
+
+    // ---- loads of the next cell, issued one cell ahead
+    S eb_n = (S)0, ec_n = (S)0, ex_n[VL], fx_n[VL], fy_n[VL];
+#pragma unroll
+    for (int v = 0; v < VL; ++v) ex_n[v] = fx_n[v] = fy_n[v] = (S)0;
+    auto prefetch = [&](int ii, int jj, int kk) {
+        const S* E = etab + (size_t)(cell0 + ii * si + jj * sj + kk * sk) * MT;
+        eb_n = ldb(E, ob);
+        ec_n = ldb(E, oc);
+#pragma unroll
+        for (int v = 0; v < VL; ++v) ex_n[v] = ldb(E, oa[v]);
+        if (ii == 0 && ir0 > 0) {
+            const S* src = xin + ((size_t)kk * ny + jj) * fstride;
+#pragma unroll
+            for (int v = 0; v < VL; ++v) fx_n[v] = ldb(src, lofs + v * SB);
+        }
+        if (jj == 0 && jr0 > 0) {
+            const S* src = yin + ((size_t)kk * nx + ii) * fstride;
+#pragma unroll
+            for (int v = 0; v < VL; ++v) fy_n[v] = ldb(src, lofs + v * SB);
+        }
+    };
+
+    const int ncell = iend * jend * kend;
+    int ii = 0, jj = 0, kk = 0;
+    prefetch(0, 0, 0);
+    S prev[VL];
+#pragma unroll
+    for (int v = 0; v < VL; ++v) prev[v] = (S)0;
+    for (int n = 0; n < ncell; ++n) {
+        const S eb = eb_n, ec = ec_n;
+        S ex[VL], fxp[VL], fyp[VL];
+#pragma unroll
+        for (int v = 0; v < VL; ++v) {
+            ex[v] = ex_n[v];
+            fxp[v] = fx_n[v];
+            fyp[v] = fy_n[v];
+        }
+        int ni = ii + 1, nj = jj, nk = kk;
+        if (ni == iend) {
+            ni = 0;
+            if (++nj == jend) {
+                nj = 0;
+                ++nk;
+            }
+        }
+        if (n + 1 < ncell) prefetch(ni, nj, nk);
+
+        const int cell = cell0 + ii * si + jj * sj + kk * sk;
+        const S* P = params + (size_t)cell * PSTRIDE;
+        const uint32_t info = reinterpret_cast<const uint32_t*>(P + P_INFO)[0];
+        if (!(info & SOLID_BIT)) {
+            S fx[VL], fy[VL], fz[VL];
+            {
+                const uint32_t code = (info >> shX) & 15u;
+                if (code == 0) {
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) fx[v] = ii > 0 ? prev[v] : fxp[v];
+                } else {
+                    const S rf = P[P_RHO_SIDE + sideX];
+                    const S* g = ghat + (size_t)(code - 1) * A.NV;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) fx[v] = rf * ldb(g, oal[v]);
+                }
+            }
+            {
+                const uint32_t code = (info >> shY) & 15u;
+                if (code == 0) {
+                    if (jj > 0) {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) fy[v] = lds(jj - 1, ii, v);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) fy[v] = fyp[v];
+                    }
+                } else {
+                    const S rf = P[P_RHO_SIDE + sideY];
+                    const S* g = ghat + (size_t)(code - 1) * A.NV;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) fy[v] = rf * ldb(g, oal[v]);
+                }
+            }
+            {
+                const uint32_t code = (info >> shZ) & 15u;
+                if (code == 0) {
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) fz[v] = lds(jj, ii, v);
+                } else if (code == CODE_SPECULAR) {
+                    const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
+                    const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
+                    const S* src = sbuf + ((size_t)j * nx + i) * fstride;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) fz[v] = ldb(src, lofs + v * SB);
+                } else {
+                    const S rf = P[P_RHO_SIDE + sideZ];
+                    const S* g = ghat + (size_t)(code - 1) * A.NV;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) fz[v] = rf * ldb(g, oal[v]);
+                }
+            }
+
+            const S nu = P[P_NU], Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
+            const S L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
+            const S qx = P[P_QX], qy = P[P_QY], qz = P[P_QZ], tT = P[P_TWO_T];
+            const S gyz = eb * ec;
+            const S cy = xiy - Uy, cz = xiz - Uz;
+            const S cyz2 = cy * cy + cz * cz;
+            const S Lyz = L0 + L2 * cy + L3 * cz;
+            const S Qyz = qy * cy + qz * cz;
+            double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+#pragma unroll
+            for (int v = 0; v < VL; ++v) {
+                const S cx = xix[v] - Ux;
+                const S c2 = cx * cx + cyz2;
+                const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
+                const S nfs = gyz * ex[v] * poly;
+                const S num = ax[v] * fx[v] + ay * fy[v] + az * fz[v] + nfs;
+                const S f = num * fast_rcp(asum[v] + nu);
+                prev[v] = f;
+                lds(jj, ii, v) = f;
+                const double t0 = wd[v] * (double)f;
+                const double t1 = t0 * xd[v];
+                const double t2 = t1 * xd[v];
+                u0 += t0;
+                u1 += t1;
+                u2 += t2;
+                u3 += t2 * xd[v];
+            }
+
+            if (ii == BX - 1 && wx) {
+                S* dst = xout + ((size_t)kk * ny + jj) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+            }
+            if (jj == BY - 1 && wy) {
+                S* dst = yout + ((size_t)kk * nx + ii) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+            }
+            if (kk == A.bz - 1 && wz) {
+                S* dst = zout + ((size_t)jj * nx + ii) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+            }
+            if (sbuf != nullptr && !pz && kr0 + kk == nz - 1) {
+                const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
+                const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
+                S* dst = sbuf + ((size_t)j * nx + i) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+            }
+
+            double m[13];
+            m[0] = u0;
+            m[1] = u1;
+            m[2] = xiy_d * u0;
+            m[3] = xiz_d * u0;
+            m[4] = u2;
+            m[5] = xiy_d * m[2];
+            m[6] = xiz_d * m[3];
+            m[7] = xiy_d * u1;
+            m[8] = xiz_d * u1;
+            m[9] = xiz_d * m[2];
+            m[10] = u3 + yz2 * u1;
+            const double t2 = u2 + yz2 * u0;
+            m[11] = xiy_d * t2;
+            m[12] = xiz_d * t2;
+            const double tot = wave_reduce13(m);
+            if (writer) stb(part + (size_t)cell * NMOM, oridx, tot);
+        }
+        ii = ni;
+        jj = nj;
+        kk = nk;
+    }
+}
+
+template <typename S, int VL, int BX, int BY>
+__global__ __launch_bounds__(64) void sweep_kernel_pf(const SweepArgs<S> A)
+{
+    __shared__ S plane[BY * BX * VL * 64];
+    sweep_body_pf<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
+                                 A.spec, A.partial, plane);
+}
+
 template <typename S, int VL, int BX, int BY>
 __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 {
@@ -804,12 +1084,15 @@ bool sweep_variant_available(int prec, int vl, int bx, int by)
     return false;
 }
 
-hipError_t launch_sweep(int prec, int vl, int bx, int by, const void* args, hipStream_t st)
+hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, const void* args, hipStream_t st)
 {
 #define X(T, V, BXX, BYY)                                                                  \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) {            \
         const SweepArgs<T>& a = *(const SweepArgs<T>*)args;                                \
-        sweep_kernel<T, V, BXX, BYY><<<a.nblocks, 64, 0, st>>>(a);                          \
+        if (pipelined)                                                                     \
+            sweep_kernel_pf<T, V, BXX, BYY><<<a.nblocks, 64, 0, st>>>(a);                   \
+        else                                                                               \
+            sweep_kernel<T, V, BXX, BYY><<<a.nblocks, 64, 0, st>>>(a);                      \
         return hipGetLastError();                                                          \
     }
     DVM_SWEEP_VARIANTS(X)

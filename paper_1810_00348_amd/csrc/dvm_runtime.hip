@@ -73,6 +73,7 @@ struct dvm_ctx {
     double dx[3];
     int hsplit[3];  // number of nodes with xi < 0 along each axis
     int VL = 2, BX = 4, BY = 4, BZ = 8;
+    int PF = 1;  // software-pipelined sweep body
     int nbx = 0, nby = 0, nbz = 0;
     int ntiles = 0, slots = 0, lstride = 0;
     std::vector<int> bricks;           // I, J, K, 0 per brick, grouped by diagonal
@@ -123,9 +124,11 @@ void derive_schedule(dvm_ctx* c)
     c->Ssz = c->prec == DVM_F64 ? 8 : 4;
 
     // velocities per lane, brick shape (overridable for tuning)
+    // VL: 2 (FP64) or 4 (FP32) velocities per lane, halved while more than
+    // 1/8 of the lanes' velocity slots of the larger x half would be empty
     const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
     int vl = c->prec == DVM_F64 ? 2 : 4;
-    if (nax % vl) vl = (nax % 2) ? 1 : 2;
+    while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
     vl = env_int("DVM_VL", vl);
     int bx = env_int("DVM_BX", 4), by = env_int("DVM_BY", 2);
     if (!sweep_variant_available(c->prec, vl, bx, by)) { vl = 1; bx = 4; by = 4; }
@@ -133,6 +136,9 @@ void derive_schedule(dvm_ctx* c)
     c->BX = bx;
     c->BY = by;
     c->BZ = env_int("DVM_BZ", 8);
+    // the software-pipelined sweep is faster with FP32 storage, the plain
+    // one with FP64 (measured on the cavity and cube workloads)
+    c->PF = env_int("DVM_PF", c->prec == DVM_F32 ? 1 : 0) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
     c->nby = (c->g.ny + c->BY - 1) / c->BY;
@@ -406,11 +412,11 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
             if (c->prec == DVM_F64) {
                 SweepArgs<double> a;
                 fill(a);
-                e = launch_sweep(0, c->VL, c->BX, c->BY, &a, st);
+                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, &a, st);
             } else {
                 SweepArgs<float> a;
                 fill(a);
-                e = launch_sweep(1, c->VL, c->BX, c->BY, &a, st);
+                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, &a, st);
             }
             if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
         }

@@ -259,32 +259,49 @@ def warm_started_solve(net: WarmStartNet, case: cases.Case, chan_std: np.ndarray
     return res
 
 
-def train(net: WarmStartNet, data, chan_std, epochs: int, lr: float, batch: int = 4, seed: int = 0,
-          log=None):
+def train(net: WarmStartNet, data, chan_std, epochs: int, lr, batch: int = 4, seed: int = 0,
+          log=None, pad_jitter: int = 3, stop=None):
     """Adam on the masked MSE of normalised targets, minibatches of whole
-    grids (gradients accumulated over the batch)."""
+    grids (gradients accumulated over the batch).  Each grid is zero-padded
+    on its high side by 0..pad_jitter extra cells per axis (then to a
+    multiple of 4), drawn afresh every epoch, so that the network sees the
+    padding that odd-sized grids get at inference.  lr: a number or a
+    function of the epoch; stop(): optional early-stop test after an epoch."""
     rng = np.random.default_rng(seed)
     dev = net.device
     prepared = []
     for case, fields in data:
-        x = torch.from_numpy(features(case)).to(dev).contiguous()
-        t, m = targets(case, fields, chan_std)
-        prepared.append((x, torch.from_numpy(t).to(dev).contiguous(), torch.from_numpy(m).to(dev).contiguous()))
+        nx, ny, nz = case.n
+        x = torch.from_numpy(features(case)[:nz, :ny, :nx]).to(dev)
+        t, _ = targets(case, fields, chan_std)
+        prepared.append((case.n, x, torch.from_numpy(t[:nz, :ny, :nx]).to(dev)))
     history = []
     for ep in range(epochs):
+        cur = lr(ep) if callable(lr) else lr
         order = rng.permutation(len(prepared))
         tot = 0.0
         for b0 in range(0, len(order), batch):
             idx = order[b0:b0 + batch]
             net.zero_grad()
             for k in idx:
-                x, t, m = prepared[k]
+                (nx, ny, nz), x0, t0 = prepared[k]
+                D, H, W = (pad4(n + int(rng.integers(0, pad_jitter + 1))) for n in (nz, ny, nx))
+                x = torch.zeros((D, H, W, x0.shape[-1]), dtype=torch.float32, device=dev)
+                t = torch.zeros((D, H, W, t0.shape[-1]), dtype=torch.float32, device=dev)
+                m = torch.zeros((D, H, W), dtype=torch.float32, device=dev)
+                x[:nz, :ny, :nx] = x0
+                t[:nz, :ny, :nx] = t0
+                m[:nz, :ny, :nx] = 1.0
                 net.forward(x)
                 tot += net.backward_mse(t, m, 1.0 / len(idx))
-            net.adam_step(lr)
+            net.adam_step(cur)
         history.append(tot / max(1, math.ceil(len(order) / batch)))
         if log:
-            log(f"epoch {ep} loss {history[-1]:.5f}")
+            log(f"epoch {ep} lr {cur:.2e} loss {history[-1]:.5f}")
+        if stop is not None and stop():
+            if log:
+                log("stopping training early")
+            break
     return history
 
 
@@ -303,7 +320,9 @@ def generate(case_list, tol=1e-6, max_iters=4000, precision="f64", log=None):
 
 
 def channel_scale(data) -> np.ndarray:
-    """Per-channel RMS of the lid-normalised deviations over all training cells."""
+    """RMS of the lid-normalised deviations over all training cells: one scale
+    for rho, one shared by the three velocity components (so that the small
+    spanwise component keeps its small weight in the loss), one for T."""
     acc = np.zeros(5)
     n = 0
     for case, fields in data:
@@ -311,37 +330,53 @@ def channel_scale(data) -> np.ndarray:
         sel = m > 0
         acc += (t[sel] ** 2).sum(axis=0)
         n += int(sel.sum())
-    return np.sqrt(acc / max(n, 1)).astype(np.float32) + np.float32(1e-6)
+    acc /= max(n, 1)
+    acc[1:4] = acc[1:4].mean()
+    return (np.sqrt(acc) + 1e-6).astype(np.float32)
 
 
-def field_difference(a: Dict[str, np.ndarray], b: Dict[str, np.ndarray]) -> Dict[str, float]:
-    """max_c |a - b| / max_c |b| per macroscopic field (normwise relative)."""
+def field_difference(a: Dict[str, np.ndarray], b: Dict[str, np.ndarray], norm: str = "max") -> Dict[str, float]:
+    """Per macroscopic field: max_c |a - b| / max_c |b| (norm "max"), or for
+    norm "dev" the L2 norm of a - b over the L2 norm of b's deviation from the
+    rest state (rho - 1, u, T - 1): the error relative to what a solve has to
+    build from the uniform start."""
     out = {}
-    for key, x, y in (("rho", a["rho"], b["rho"]), ("ux", a["u"][0], b["u"][0]), ("uy", a["u"][1], b["u"][1]),
-                      ("uz", a["u"][2], b["u"][2]), ("T", a["T"], b["T"])):
-        out[key] = float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+    for key, x, y, ref in (("rho", a["rho"], b["rho"], 1.0), ("ux", a["u"][0], b["u"][0], 0.0),
+                           ("uy", a["u"][1], b["u"][1], 0.0), ("uz", a["u"][2], b["u"][2], 0.0),
+                           ("T", a["T"], b["T"], 1.0)):
+        if norm == "max":
+            out[key] = float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+        else:
+            out[key] = float(np.linalg.norm(x - y) / max(np.linalg.norm(y - ref), 1e-300))
     return out
 
 
 def evaluate(net, case_list, chan_std, tol=1e-6, max_iters=4000, log=None):
-    """Plain and warm-started FP64 solves of every case."""
+    """Plain and warm-started FP64 solves of every case, and (as the bound a
+    perfect prediction could reach) a solve seeded with the plain solve's own
+    converged rho, U, T."""
     rows = []
     for k, c in enumerate(case_list):
         plain = solve(c, tol, max_iters)
         warm = warm_started_solve(net, c, chan_std, tol, max_iters)
+        exact = solve(c, tol, max_iters, init=(plain["fields"]["rho"], plain["fields"]["u"], plain["fields"]["T"]))
         rho, u, T = predict(net, c, chan_std)
         pred = {"rho": rho, "u": u, "T": T}
         row = {"case": c.name, "n": c.n[0], "m": c.m[0], "kn": c.kn, "lid": c.faces[3].u[0],
                "plain_iters": plain["iters"], "plain_s": plain["seconds"], "plain_converged": plain["converged"],
                "warm_iters": warm["iters"], "warm_s": warm["seconds"], "warm_converged": warm["converged"],
                "predict_s": warm["predict_seconds"], "fallback": warm["fallback"],
+               "exact_seed_iters": exact["iters"],
                "final_diff": field_difference(warm["fields"], plain["fields"]),
-               "prediction_error": field_difference(pred, plain["fields"])}
+               "prediction_error": field_difference(pred, plain["fields"]),
+               "prediction_error_dev": field_difference(pred, plain["fields"], "dev")}
         rows.append(row)
         if log:
             log(f"eval {k} {c.name} kn={c.kn:.3f} lid={row['lid']:.3f} plain {plain['iters']} it "
                 f"{plain['seconds']:.2f}s | warm {warm['iters']} it {warm['seconds']:.2f}s "
-                f"fallback={warm['fallback']} diff={max(row['final_diff'].values()):.1e}")
+                f"fallback={warm['fallback']} | exact seed {exact['iters']} it | "
+                f"pred err {max(row['prediction_error_dev'].values()):.2e} "
+                f"diff={max(row['final_diff'].values()):.1e}")
     return rows
 
 
@@ -405,21 +440,20 @@ def pipeline(out_dir: str, n_train=256, n_eval=32, epochs=40, lr=1e-3, batch=4, 
     t_gen = time.perf_counter() - t_start
     data = [(c, f) for c, f, s in gen if s["converged"]]
     chan_std = channel_scale(data)
-    big = max(max(pad4(n) for n in c.n) for c in train_cases + heldout_cases(n_eval))
+    big = max(max(pad4(n + 3) for n in c.n) for c in train_cases + heldout_cases(n_eval))
     net = WarmStartNet(max_grid=(big, big, big))
     net.set_params(init_theta(seed=7))
     t0 = time.perf_counter()
-    sched_epochs = epochs
-    history = []
-    for ep in range(epochs):
+
+    def lr_at(ep):
         # cosine decay of the learning rate
-        cur = lr * 0.5 * (1 + math.cos(math.pi * ep / sched_epochs))
-        h = train(net, data, chan_std, 1, cur, batch, seed=1000 + ep)
-        history.append(h[0])
-        log(f"epoch {ep} lr {cur:.2e} loss {h[0]:.5f} ({time.perf_counter() - t0:.0f}s)")
-        if time_budget_s and time.perf_counter() - t_start > time_budget_s:
-            log("time budget reached, stopping training")
-            break
+        return lr * 0.5 * (1 + math.cos(math.pi * ep / epochs))
+
+    def over_budget():
+        return bool(time_budget_s) and time.perf_counter() - t_start > time_budget_s
+
+    history = train(net, data, chan_std, epochs, lr_at, batch, seed=1000,
+                    log=lambda m: log(f"{m} ({time.perf_counter() - t0:.0f}s)"), stop=over_budget)
     t_train = time.perf_counter() - t0
     theta = store_params(net.params(), layer_table())
     net.set_params(theta)
@@ -430,7 +464,8 @@ def pipeline(out_dir: str, n_train=256, n_eval=32, epochs=40, lr=1e-3, batch=4, 
 
     def tot(key):
         return float(sum(r[key] for r in rows))
-    summary = {"plain_iters": tot("plain_iters"), "warm_iters": tot("warm_iters"), "plain_s": tot("plain_s"),
+    summary = {"plain_iters": tot("plain_iters"), "warm_iters": tot("warm_iters"),
+               "exact_seed_iters": tot("exact_seed_iters"), "plain_s": tot("plain_s"),
                "warm_s": tot("warm_s"), "fallbacks": int(sum(r["fallback"] for r in rows)),
                "max_final_diff": max(max(r["final_diff"].values()) for r in rows),
                "median_iter_ratio": float(np.median([r["warm_iters"] / max(1, r["plain_iters"]) for r in rows]))}
