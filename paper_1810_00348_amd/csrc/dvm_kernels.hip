@@ -551,7 +551,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                                            S* __restrict__ xface, S* __restrict__ yface, S* __restrict__ zface,
                                            S* __restrict__ spec, double* __restrict__ partial, S* __restrict__ plane)
 {
-    const int lane = threadIdx.x;
+    // one wave per tile; a block holds A.tpb tiles of the same (octant,
+    // brick), so that they share the cell records in the CU's caches
+    const int lane = threadIdx.x & 63;
     int bid = blockIdx.x;
     // XCD-aware order: consecutive block ids go round-robin over the 8 XCDs,
     // so regroup them to give each XCD a contiguous range of work units
@@ -563,8 +565,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
         const int start = xcd * per + (xcd < rem ? xcd : rem);
         bid = start + k;
     }
-    const int tile = bid % A.ntiles;
-    bid /= A.ntiles;
+    const int ntg = (A.ntiles + A.tpb - 1) / A.tpb;
+    const int tile = (bid % ntg) * A.tpb + (int)(threadIdx.x >> 6);
+    if (tile >= A.ntiles) return;
+    bid /= ntg;
     const int bi = bid % A.brick_cnt;
     const int o = A.oct_base + bid / A.brick_cnt;
     const int I = bricks[4 * (A.brick_off + bi) + 0];
@@ -782,6 +786,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
     }
 }
 
+// the LDS planes of the block's waves (dynamic size: A.tpb planes)
+extern __shared__ __align__(16) unsigned char dvm_sweep_lds[];
+
 // Software-pipelined form of the same sweep.  The cells of the brick are
 // visited in the same order through one flat loop; while cell n is computed,
 // the loads of cell n+1 are already in flight: its Gaussian-table gathers and,
@@ -800,7 +807,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                                               S* __restrict__ spec, double* __restrict__ partial,
                                               S* __restrict__ plane)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     int bid = blockIdx.x;
     {
         const int nb = A.nblocks;
@@ -809,8 +816,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         const int start = xcd * per + (xcd < rem ? xcd : rem);
         bid = start + k;
     }
-    const int tile = bid % A.ntiles;
-    bid /= A.ntiles;
+    const int ntg = (A.ntiles + A.tpb - 1) / A.tpb;
+    const int tile = (bid % ntg) * A.tpb + (int)(threadIdx.x >> 6);
+    if (tile >= A.ntiles) return;
+    bid /= ntg;
     const int bi = bid % A.brick_cnt;
     const int o = A.oct_base + bid / A.brick_cnt;
     const int I = bricks[4 * (A.brick_off + bi) + 0];
@@ -1054,18 +1063,22 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     }
 }
 
-template <typename S, int VL, int BX, int BY>
-__global__ __launch_bounds__(64) void sweep_kernel_pf(const SweepArgs<S> A)
+// WPE: minimum waves per SIMD the register allocation is held to (1 = the
+// compiler's own choice)
+template <typename S, int VL, int BX, int BY, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void sweep_kernel_pf(
+    const SweepArgs<S> A)
 {
-    __shared__ S plane[BY * BX * VL * 64];
+    S* plane = reinterpret_cast<S*>(dvm_sweep_lds) + (threadIdx.x >> 6) * (BY * BX * VL * 64);
     sweep_body_pf<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
                                  A.spec, A.partial, plane);
 }
 
-template <typename S, int VL, int BX, int BY>
-__global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
+template <typename S, int VL, int BX, int BY, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void sweep_kernel(
+    const SweepArgs<S> A)
 {
-    __shared__ S plane[BY * BX * VL * 64];
+    S* plane = reinterpret_cast<S*>(dvm_sweep_lds) + (threadIdx.x >> 6) * (BY * BX * VL * 64);
     sweep_body<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
                               A.spec, A.partial, plane);
 }
@@ -1089,10 +1102,16 @@ hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, const v
 #define X(T, V, BXX, BYY)                                                                  \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) {            \
         const SweepArgs<T>& a = *(const SweepArgs<T>*)args;                                \
-        if (pipelined)                                                                     \
-            sweep_kernel_pf<T, V, BXX, BYY><<<a.nblocks, 64, 0, st>>>(a);                   \
+        const size_t lds = (size_t)a.tpb * BYY * BXX * V * 64 * sizeof(T);                 \
+        const dim3 g(a.nblocks), b(64 * a.tpb);                                             \
+        if (pipelined && a.wpe == 5)                                                       \
+            sweep_kernel_pf<T, V, BXX, BYY, 5><<<g, b, lds, st>>>(a);                       \
+        else if (pipelined)                                                                \
+            sweep_kernel_pf<T, V, BXX, BYY, 1><<<g, b, lds, st>>>(a);                       \
+        else if (a.wpe == 5)                                                               \
+            sweep_kernel<T, V, BXX, BYY, 5><<<g, b, lds, st>>>(a);                          \
         else                                                                               \
-            sweep_kernel<T, V, BXX, BYY><<<a.nblocks, 64, 0, st>>>(a);                      \
+            sweep_kernel<T, V, BXX, BYY, 1><<<g, b, lds, st>>>(a);                          \
         return hipGetLastError();                                                          \
     }
     DVM_SWEEP_VARIANTS(X)
