@@ -1,10 +1,10 @@
 /*
  * wsn.h -- C ABI of the learned warm start of the iterative DVM solver
- * (libdvm_hip.so).  A small 3D U-Net maps (log10 Kn, lid speed, wall mask)
- * on the cell grid to the macroscopic fields (rho, U, T) of the converged
+ * (libdvm_hip.so).  A small 3D U-Net maps (log10 Kn, lid speed, wall mask,
+ * cell position) on the cell grid to the macroscopic fields (rho, U, T) of the converged
  * solution; its output seeds the solver's initial equilibrium, which the
- * paper sets from the initial macroscopic fields (Sec. 2.2, "At the
- * beginning of the iteration ...").  The network is not part of the paper;
+ * paper builds from the initial macroscopic fields (Sec. 2.2).  The network
+ * is not part of the paper;
  * it is the learned warm start of this implementation.
  *
  * Network: 3 levels, base width B (32): per level two 3x3x3 convolutions
@@ -39,7 +39,8 @@ extern "C" {
 
 typedef struct wsn_ctx wsn_ctx;
 
-/* cin input channels (3), cout outputs (5), base width (32), largest grid. */
+/* cin input channels (6 for the cavity warm start), cout outputs (5), base
+   width (32), largest grid. */
 int wsn_create(int cin, int cout, int base, int max_d, int max_h, int max_w, void* hip_stream,
                wsn_ctx** out);
 size_t wsn_num_params(const wsn_ctx* ctx);

@@ -80,8 +80,6 @@ struct SweepArgs {
     int oct_base, noct;
     int spec_on;
     int has_solid;
-    int tpb;       // tiles (waves) per block
-    int wpe;       // register budget: minimum waves per SIMD (1 or 5)
     int nblocks;
 };
 

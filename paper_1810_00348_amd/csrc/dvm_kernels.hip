@@ -327,20 +327,24 @@ hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind
 // equilibrium at every wall face, divided by the emitted-flux normaliser.
 // --------------------------------------------------------------------------
 
+// initial wall densities: rho_w = (flux of the initial equilibrium into the
+// wall) / (flux of the unit emission shape out of it).  One wave per cell;
+// lanes stride over the velocities, then a shuffle tree (fixed order).
 template <typename S>
-__global__ __launch_bounds__(128) void wall_init_kernel(Consts C, DevPtrs D, const S* __restrict__ params,
-                                                        const S* __restrict__ etab,
-                                                        const double* __restrict__ gout,
-                                                        double* __restrict__ rho_w)
+__global__ __launch_bounds__(64) void wall_init_kernel(Consts C, DevPtrs D, const S* __restrict__ params,
+                                                       const S* __restrict__ etab,
+                                                       const double* __restrict__ gout,
+                                                       double* __restrict__ rho_w)
 {
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= C.N) return;
+    const int cell = blockIdx.x;
+    const int lane = threadIdx.x;
     const uint32_t info = D.cellinfo[cell];
-    for (int s = 0; s < 6; ++s) rho_w[(size_t)s * C.N + cell] = 0.0;
+    if (lane < 6) rho_w[(size_t)lane * C.N + cell] = 0.0;
     if (info & SOLID_BIT) return;
     const S* P = params + (size_t)cell * PSTRIDE;
     const S* E = etab + (size_t)cell * C.MT;
     const double nu = (double)P[P_NU];
+    const double Ux = (double)P[P_UX], Uy = (double)P[P_UY], Uz = (double)P[P_UZ];
     for (int s = 0; s < 6; ++s) {
         const uint32_t code = (info >> (4 * s)) & 15u;
         if (code == 0 || code == CODE_SPECULAR) continue;
@@ -348,25 +352,23 @@ __global__ __launch_bounds__(128) void wall_init_kernel(Consts C, DevPtrs D, con
         if (!C.kind_wall[kind]) continue;
         const int d = s >> 1;
         double flux = 0.0;
-        for (int c = 0; c < C.mz; ++c)
-            for (int b = 0; b < C.my; ++b)
-                for (int a = 0; a < C.mx; ++a) {
-                    const double xv[3] = {D.xi[a], D.xi[MAXM + b], D.xi[2 * MAXM + c]};
-                    const double xn = (s & 1) ? -xv[d] : xv[d];  // xi . n, n into the gas
-                    if (!(xn < 0)) continue;
-                    const double cx = xv[0] - (double)P[P_UX];
-                    const double cy = xv[1] - (double)P[P_UY];
-                    const double cz = xv[2] - (double)P[P_UZ];
-                    const double c2 = cx * cx + cy * cy + cz * cz;
-                    const double poly = (double)P[P_L0] + (double)P[P_L1] * cx + (double)P[P_L2] * cy +
-                                        (double)P[P_L3] * cz + (double)P[P_L4] * c2 +
-                                        ((double)P[P_QX] * cx + (double)P[P_QY] * cy + (double)P[P_QZ] * cz) *
-                                            (c2 * (double)P[P_TWO_T] - 5.0);
-                    const double nfs = (double)E[a] * (double)E[C.mx + b] * (double)E[C.mx + C.my + c] * poly;
-                    const double w = D.wt[a] * D.wt[MAXM + b] * D.wt[2 * MAXM + c];
-                    flux += w * (-xn) * nfs / nu;
-                }
-        rho_w[(size_t)s * C.N + cell] = flux / gout[kind * 6 + s];
+        for (int v = lane; v < C.mx * C.my * C.mz; v += 64) {
+            const int a = v % C.mx, b = (v / C.mx) % C.my, c = v / (C.mx * C.my);
+            const double xv[3] = {D.xi[a], D.xi[MAXM + b], D.xi[2 * MAXM + c]};
+            const double xn = (s & 1) ? -xv[d] : xv[d];  // xi . n, n into the gas
+            if (!(xn < 0)) continue;
+            const double cx = xv[0] - Ux, cy = xv[1] - Uy, cz = xv[2] - Uz;
+            const double c2 = cx * cx + cy * cy + cz * cz;
+            const double poly = (double)P[P_L0] + (double)P[P_L1] * cx + (double)P[P_L2] * cy +
+                                (double)P[P_L3] * cz + (double)P[P_L4] * c2 +
+                                ((double)P[P_QX] * cx + (double)P[P_QY] * cy + (double)P[P_QZ] * cz) *
+                                    (c2 * (double)P[P_TWO_T] - 5.0);
+            const double nfs = (double)E[a] * (double)E[C.mx + b] * (double)E[C.mx + C.my + c] * poly;
+            const double w = D.wt[a] * D.wt[MAXM + b] * D.wt[2 * MAXM + c];
+            flux += w * (-xn) * nfs / nu;
+        }
+        for (int off = 32; off > 0; off >>= 1) flux += __shfl_xor(flux, off, 64);
+        if (lane == 0) rho_w[(size_t)s * C.N + cell] = flux / gout[kind * 6 + s];
     }
 }
 
@@ -375,12 +377,10 @@ hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* param
                             hipStream_t st)
 {
     (void)ghat64;
-    const int tpb = 128;
-    const int nb = (C.N + tpb - 1) / tpb;
     if (prec == 0)
-        wall_init_kernel<double><<<nb, tpb, 0, st>>>(C, D, (const double*)params, (const double*)etab, gout, rho_w);
+        wall_init_kernel<double><<<C.N, 64, 0, st>>>(C, D, (const double*)params, (const double*)etab, gout, rho_w);
     else
-        wall_init_kernel<float><<<nb, tpb, 0, st>>>(C, D, (const float*)params, (const float*)etab, gout, rho_w);
+        wall_init_kernel<float><<<C.N, 64, 0, st>>>(C, D, (const float*)params, (const float*)etab, gout, rho_w);
     return hipGetLastError();
 }
 
@@ -551,9 +551,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                                            S* __restrict__ xface, S* __restrict__ yface, S* __restrict__ zface,
                                            S* __restrict__ spec, double* __restrict__ partial, S* __restrict__ plane)
 {
-    // one wave per tile; a block holds A.tpb tiles of the same (octant,
-    // brick), so that they share the cell records in the CU's caches
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     int bid = blockIdx.x;
     // XCD-aware order: consecutive block ids go round-robin over the 8 XCDs,
     // so regroup them to give each XCD a contiguous range of work units
@@ -565,10 +563,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
         const int start = xcd * per + (xcd < rem ? xcd : rem);
         bid = start + k;
     }
-    const int ntg = (A.ntiles + A.tpb - 1) / A.tpb;
-    const int tile = (bid % ntg) * A.tpb + (int)(threadIdx.x >> 6);
-    if (tile >= A.ntiles) return;
-    bid /= ntg;
+    const int tile = bid % A.ntiles;
+    bid /= A.ntiles;
     const int bi = bid % A.brick_cnt;
     const int o = A.oct_base + bid / A.brick_cnt;
     const int I = bricks[4 * (A.brick_off + bi) + 0];
@@ -786,7 +782,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
     }
 }
 
-// the LDS planes of the block's waves (dynamic size: A.tpb planes)
+// the LDS plane of the block's wave (dynamic size)
 extern __shared__ __align__(16) unsigned char dvm_sweep_lds[];
 
 // Software-pipelined form of the same sweep.  The cells of the brick are
@@ -807,7 +803,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                                               S* __restrict__ spec, double* __restrict__ partial,
                                               S* __restrict__ plane)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     int bid = blockIdx.x;
     {
         const int nb = A.nblocks;
@@ -816,10 +812,8 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         const int start = xcd * per + (xcd < rem ? xcd : rem);
         bid = start + k;
     }
-    const int ntg = (A.ntiles + A.tpb - 1) / A.tpb;
-    const int tile = (bid % ntg) * A.tpb + (int)(threadIdx.x >> 6);
-    if (tile >= A.ntiles) return;
-    bid /= ntg;
+    const int tile = bid % A.ntiles;
+    bid /= A.ntiles;
     const int bi = bid % A.brick_cnt;
     const int o = A.oct_base + bid / A.brick_cnt;
     const int I = bricks[4 * (A.brick_off + bi) + 0];
@@ -1063,22 +1057,18 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     }
 }
 
-// WPE: minimum waves per SIMD the register allocation is held to (1 = the
-// compiler's own choice)
-template <typename S, int VL, int BX, int BY, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void sweep_kernel_pf(
-    const SweepArgs<S> A)
+template <typename S, int VL, int BX, int BY>
+__global__ __launch_bounds__(64) void sweep_kernel_pf(const SweepArgs<S> A)
 {
-    S* plane = reinterpret_cast<S*>(dvm_sweep_lds) + (threadIdx.x >> 6) * (BY * BX * VL * 64);
+    S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
     sweep_body_pf<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
                                  A.spec, A.partial, plane);
 }
 
-template <typename S, int VL, int BX, int BY, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void sweep_kernel(
-    const SweepArgs<S> A)
+template <typename S, int VL, int BX, int BY>
+__global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 {
-    S* plane = reinterpret_cast<S*>(dvm_sweep_lds) + (threadIdx.x >> 6) * (BY * BX * VL * 64);
+    S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
     sweep_body<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
                               A.spec, A.partial, plane);
 }
@@ -1102,16 +1092,11 @@ hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, const v
 #define X(T, V, BXX, BYY)                                                                  \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) {            \
         const SweepArgs<T>& a = *(const SweepArgs<T>*)args;                                \
-        const size_t lds = (size_t)a.tpb * BYY * BXX * V * 64 * sizeof(T);                 \
-        const dim3 g(a.nblocks), b(64 * a.tpb);                                             \
-        if (pipelined && a.wpe == 5)                                                       \
-            sweep_kernel_pf<T, V, BXX, BYY, 5><<<g, b, lds, st>>>(a);                       \
-        else if (pipelined)                                                                \
-            sweep_kernel_pf<T, V, BXX, BYY, 1><<<g, b, lds, st>>>(a);                       \
-        else if (a.wpe == 5)                                                               \
-            sweep_kernel<T, V, BXX, BYY, 5><<<g, b, lds, st>>>(a);                          \
+        const size_t lds = (size_t)BYY * BXX * V * 64 * sizeof(T);                         \
+        if (pipelined)                                                                     \
+            sweep_kernel_pf<T, V, BXX, BYY><<<a.nblocks, 64, lds, st>>>(a);                 \
         else                                                                               \
-            sweep_kernel<T, V, BXX, BYY, 1><<<g, b, lds, st>>>(a);                          \
+            sweep_kernel<T, V, BXX, BYY><<<a.nblocks, 64, lds, st>>>(a);                    \
         return hipGetLastError();                                                          \
     }
     DVM_SWEEP_VARIANTS(X)

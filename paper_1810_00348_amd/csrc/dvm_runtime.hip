@@ -74,8 +74,6 @@ struct dvm_ctx {
     int hsplit[3];  // number of nodes with xi < 0 along each axis
     int VL = 2, BX = 4, BY = 4, BZ = 8;
     int PF = 1;  // software-pipelined sweep body
-    int TPB = 1; // tiles (waves) per sweep block
-    int WPE = 1; // sweep register budget: minimum waves per SIMD
     int nbx = 0, nby = 0, nbz = 0;
     int ntiles = 0, slots = 0, lstride = 0;
     std::vector<int> bricks;           // I, J, K, 0 per brick, grouped by diagonal
@@ -141,11 +139,6 @@ void derive_schedule(dvm_ctx* c)
     // the software-pipelined sweep is faster with FP32 storage, the plain
     // one with FP64 (measured on the cavity and cube workloads)
     c->PF = env_int("DVM_PF", c->prec == DVM_F32 ? 1 : 0) != 0;
-    c->WPE = env_int("DVM_WPE", 1) == 5 ? 5 : 1;
-    c->TPB = env_int("DVM_TPB", 1);
-    if (c->TPB < 1 || c->TPB > 4) c->TPB = 1;
-    // keep a block's LDS planes within 64 KiB
-    while (c->TPB > 1 && (size_t)c->TPB * c->BX * c->BY * c->VL * 64 * c->Ssz > 65536) c->TPB--;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
     c->nby = (c->g.ny + c->BY - 1) / c->BY;
@@ -413,9 +406,7 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.noct = c->spec_on ? 4 : 8;
                 a.spec_on = c->spec_on ? 1 : 0;
                 a.has_solid = c->nfluid < c->N ? 1 : 0;
-                a.tpb = c->TPB;
-                a.wpe = c->WPE;
-                a.nblocks = a.noct * cnt * ((c->ntiles + c->TPB - 1) / c->TPB);
+                a.nblocks = a.noct * cnt * c->ntiles;
             };
             hipError_t e;
             if (c->prec == DVM_F64) {

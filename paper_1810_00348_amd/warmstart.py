@@ -1,7 +1,8 @@
 """Learned warm start of the iterative DVM solver.
 
 A 3D U-Net (include/wsn.h, HIP/MFMA kernels in csrc/wsn.hip) maps the inputs
-(log10 Kn, lid speed, wall mask) on the cell grid of a lid-driven cavity to
+(log10 Kn, lid speed, and the wall geometry: a wall mask and each cell's
+position relative to the walls) on the cell grid of a lid-driven cavity to
 its converged macroscopic fields (rho, U, T).  The prediction seeds the
 solver: the initial equilibrium is built from the predicted fields (the paper
 builds it from the initial macroscopic fields, Sec. 2.2), rescaled to the
@@ -26,7 +27,7 @@ import torch
 from . import _lib as L
 from . import cases
 
-NET_IN, NET_OUT, NET_BASE = 3, 5, 32
+NET_IN, NET_OUT, NET_BASE = 6, 5, 32
 _wsn = None
 
 
@@ -141,12 +142,15 @@ def pad4(n: int) -> int:
 
 
 def features(case: cases.Case) -> np.ndarray:
-    """[D, H, W, 3] network input on the grid padded to multiples of 4 (the
+    """[D, H, W, 6] network input on the grid padded to multiples of 4 (the
     padding cells are all zero): log10 Kn, lid speed, wall mask (1 next to the
-    moving lid, 0.5 next to the other walls, 0 inside)."""
+    moving lid, 0.5 next to the other walls, 0 inside), and the cell centre's
+    position (x, y, z) as a fraction of the cavity side -- the wall geometry
+    seen from the cell, which the network's receptive field (about 40 cells)
+    cannot always see itself."""
     nx, ny, nz = case.n
     D, H, W = pad4(nz), pad4(ny), pad4(nx)
-    x = np.zeros((D, H, W, 3), dtype=np.float32)
+    x = np.zeros((D, H, W, NET_IN), dtype=np.float32)
     lid = case.faces[3].u[0]
     x[:nz, :ny, :nx, 0] = math.log10(case.kn)
     x[:nz, :ny, :nx, 1] = lid
@@ -155,6 +159,9 @@ def features(case: cases.Case) -> np.ndarray:
     m[:, 0, :] = m[:, :, 0] = m[:, :, -1] = 0.5
     m[:, -1, :] = 1.0
     x[:nz, :ny, :nx, 2] = m
+    x[:nz, :ny, :nx, 3] = ((np.arange(nx) + 0.5) / nx)[None, None, :]
+    x[:nz, :ny, :nx, 4] = ((np.arange(ny) + 0.5) / ny)[None, :, None]
+    x[:nz, :ny, :nx, 5] = ((np.arange(nz) + 0.5) / nz)[:, None, None]
     return x
 
 

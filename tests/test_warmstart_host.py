@@ -12,13 +12,16 @@ from oracle import unet_oracle as U  # noqa: E402
 def test_features_pad_odd_grids_with_zeros():
     c = cases.cavity(25, 17, kn=0.3, lid=0.2)
     x = W.features(c)
-    assert x.shape == (28, 28, 28, 3)
+    assert x.shape == (28, 28, 28, 6)
     assert np.all(x[25:] == 0) and np.all(x[:, 25:] == 0) and np.all(x[:, :, 25:] == 0)
     inner = x[:25, :25, :25]
     assert np.allclose(inner[..., 0], np.log10(0.3)) and np.allclose(inner[..., 1], 0.2)
     # wall mask: 1 next to the moving lid (y = 1), 0.5 next to the other walls, 0 inside
     assert np.all(inner[:, -1, :, 2] == 1.0)
     assert inner[12, 12, 12, 2] == 0.0 and inner[0, 12, 12, 2] == 0.5 and inner[12, 12, 0, 2] == 0.5
+    # cell-centre positions as fractions of the side: x varies along W, z along D
+    assert np.isclose(inner[3, 4, 0, 3], 0.5 / 25) and np.isclose(inner[3, 4, 24, 3], 24.5 / 25)
+    assert np.isclose(inner[3, 7, 9, 4], 7.5 / 25) and np.isclose(inner[11, 7, 9, 5], 11.5 / 25)
 
 
 def test_targets_and_mask():
@@ -50,7 +53,7 @@ def test_channel_scale_shares_the_velocity_scale():
 
 def test_stored_weights_are_bf16_and_biases_exact(tmp_path):
     theta = W.init_theta(3, base=8)
-    specs = U.layer_specs(3, 5, 8)
+    specs = U.layer_specs(W.NET_IN, 5, 8)
     assert theta.size == U.param_count(specs)
     theta[-5:] = np.float32(0.123456789)
     s = W.store_params(theta, W.layer_table(8))
