@@ -269,11 +269,13 @@ def warm_started_solve(net: WarmStartNet, case: cases.Case, chan_std: np.ndarray
 def train(net: WarmStartNet, data, chan_std, epochs: int, lr, batch: int = 4, seed: int = 0,
           log=None, pad_jitter: int = 3, stop=None):
     """Adam on the masked MSE of normalised targets, minibatches of whole
-    grids (gradients accumulated over the batch).  Each grid is zero-padded
-    on its high side by 0..pad_jitter extra cells per axis (then to a
-    multiple of 4), drawn afresh every epoch, so that the network sees the
-    padding that odd-sized grids get at inference.  lr: a number or a
-    function of the epoch; stop(): optional early-stop test after an epoch."""
+    grids (gradients accumulated over the batch).  Each grid is placed at a
+    random offset of 0..pad_jitter cells per axis inside a zero-padded grid
+    with 0..pad_jitter more cells after it (then rounded up to a multiple of
+    4), drawn afresh every epoch: odd-sized grids at inference put their walls
+    at every alignment with the network's 2x2x2 pooling, and the network has
+    to see those alignments in training.  lr: a number or a function of the
+    epoch; stop(): optional early-stop test after an epoch."""
     rng = np.random.default_rng(seed)
     dev = net.device
     prepared = []
@@ -292,13 +294,15 @@ def train(net: WarmStartNet, data, chan_std, epochs: int, lr, batch: int = 4, se
             net.zero_grad()
             for k in idx:
                 (nx, ny, nz), x0, t0 = prepared[k]
-                D, H, W = (pad4(n + int(rng.integers(0, pad_jitter + 1))) for n in (nz, ny, nx))
+                oz, oy, ox = (int(rng.integers(0, pad_jitter + 1)) for _ in range(3))
+                D, H, W = (pad4(n + o + int(rng.integers(0, pad_jitter + 1)))
+                           for n, o in ((nz, oz), (ny, oy), (nx, ox)))
                 x = torch.zeros((D, H, W, x0.shape[-1]), dtype=torch.float32, device=dev)
                 t = torch.zeros((D, H, W, t0.shape[-1]), dtype=torch.float32, device=dev)
                 m = torch.zeros((D, H, W), dtype=torch.float32, device=dev)
-                x[:nz, :ny, :nx] = x0
-                t[:nz, :ny, :nx] = t0
-                m[:nz, :ny, :nx] = 1.0
+                x[oz:oz + nz, oy:oy + ny, ox:ox + nx] = x0
+                t[oz:oz + nz, oy:oy + ny, ox:ox + nx] = t0
+                m[oz:oz + nz, oy:oy + ny, ox:ox + nx] = 1.0
                 net.forward(x)
                 tot += net.backward_mse(t, m, 1.0 / len(idx))
             net.adam_step(cur)
@@ -447,7 +451,7 @@ def pipeline(out_dir: str, n_train=256, n_eval=32, epochs=40, lr=1e-3, batch=4, 
     t_gen = time.perf_counter() - t_start
     data = [(c, f) for c, f, s in gen if s["converged"]]
     chan_std = channel_scale(data)
-    big = max(max(pad4(n + 3) for n in c.n) for c in train_cases + heldout_cases(n_eval))
+    big = max(max(pad4(n + 6) for n in c.n) for c in train_cases + heldout_cases(n_eval))
     net = WarmStartNet(max_grid=(big, big, big))
     net.set_params(init_theta(seed=7))
     t0 = time.perf_counter()
