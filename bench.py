@@ -49,8 +49,15 @@ TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sweep kernel's source: the wave reduction, the sweep
+    bodies and kernels (up to the list of instantiated variants) and the
+    shared layout header; a measured traffic file is used only while this
+    matches."""
+    src = open(KERNEL_SRC).read()
+    a = src.index("// Wave-level reduction of 13 FP64 values")
+    b = src.index("#define DVM_SWEEP_VARIANTS")
+    hdr = open(os.path.join(os.path.dirname(KERNEL_SRC), "dvm_internal.h")).read()
+    return hashlib.sha256((hdr + src[a:b]).encode()).hexdigest()[:16]
 
 
 def _pmc_sum(path: str, counter: str, kernel_substr: str):

@@ -1076,7 +1076,9 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 // instantiated variants: (precision, VL, BX, BY)
 #define DVM_SWEEP_VARIANTS(X) \
     X(double, 1, 4, 4) X(double, 2, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) X(double, 4, 4, 4) \
-    X(float, 1, 4, 4) X(float, 2, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2) X(float, 4, 4, 4)
+    X(double, 2, 2, 2) X(double, 4, 2, 2) \
+    X(float, 1, 4, 4) X(float, 2, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2) X(float, 4, 4, 4) \
+    X(float, 4, 2, 2) X(float, 8, 4, 2) X(float, 8, 2, 2)
 
 bool sweep_variant_available(int prec, int vl, int bx, int by)
 {
