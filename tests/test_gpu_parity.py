@@ -154,19 +154,21 @@ def test_fp32_storage_error_is_bounded(oracle_mod):
         assert err[k] <= 1e-4, (k, err)
 
 
-@pytest.mark.parametrize("pf,vl,by", [(1, 2, 2), (0, 4, 2), (1, 4, 2), (0, 1, 4), (1, 2, 4)])
+@pytest.mark.parametrize("pf,vl,bx,by", [(1, 2, 4, 2), (0, 4, 4, 2), (1, 4, 4, 2), (0, 1, 4, 4), (1, 2, 4, 4),
+                                          (1, 4, 2, 2), (0, 2, 2, 2)])
 @pytest.mark.parametrize("name", ["ragged", "oddM", "cube"])
-def test_sweep_variants_match_oracle(oracle_mod, monkeypatch, name, pf, vl, by):
+def test_sweep_variants_match_oracle(oracle_mod, monkeypatch, name, pf, vl, bx, by):
     """Every sweep body (plain / software-pipelined) and lane/brick shape
     reproduces the oracle (FP64)."""
     monkeypatch.setenv("DVM_PF", str(pf))
     monkeypatch.setenv("DVM_VL", str(vl))
+    monkeypatch.setenv("DVM_BX", str(bx))
     monkeypatch.setenv("DVM_BY", str(by))
     case = _ragged_cases()[name]
     init = cases.random_fields(case, seed=11) if name != "cube" else None
     s, o = run_pair(case, 2, oracle_mod, init=init)
     inf = s.info()
-    assert inf["vel_per_lane"] == vl and inf["brick"][1] == by
+    assert inf["vel_per_lane"] == vl and inf["brick"][0] == bx and inf["brick"][1] == by
     err = field_errors(s.fields(), o.fields())
     for k in ("rho", "ux", "uy", "uz", "T"):
         assert err[k] <= FP64_TOL, (k, err, inf)
