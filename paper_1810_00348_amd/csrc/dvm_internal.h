@@ -81,8 +81,6 @@ struct SweepArgs {
     int spec_on;
     int has_solid;
     int nblocks;
-    double hx;     // velocity node spacing along x, 2 V / (M - 1)
-    double invdx;  // 1 / cell size along x
 };
 
 // kernel launchers (dvm_kernels.hip)

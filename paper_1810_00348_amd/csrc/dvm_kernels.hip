@@ -849,22 +849,20 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     const S xiy = (S)xiy_d, xiz = (S)xiz_d;
     const S ay = (S)lt[2], az = (S)lt[3];
     const int vb = (int)lt[4], vc = (int)lt[5];
-    // the lane's VL x nodes are consecutive in the octant's direction:
-    // xi_x(v) = xi_x(0) + v * hs; a slot past the last node has weight 0 (its
-    // node index is clamped, its abscissa only has to be finite)
-    const double xd0 = lt[LT_SHARED + 0];
-    const double hs = px ? A.hx : -A.hx;
-    const S invdx = (S)A.invdx;
-    double wd[VL];
-    unsigned oa[VL];
+    S xix[VL], ax[VL], asum[VL];
+    double xd[VL], wd[VL];
+    unsigned oa[VL], oal[VL];
 #pragma unroll
     for (int v = 0; v < VL; ++v) {
+        xd[v] = lt[LT_SHARED + LT_PER_V * v + 0];
         wd[v] = lt[LT_SHARED + LT_PER_V * v + 2];
-        oa[v] = (unsigned)(int)lt[LT_SHARED + LT_PER_V * v + 3] * SB;
+        const int a = (int)lt[LT_SHARED + LT_PER_V * v + 3];
+        xix[v] = (S)xd[v];
+        ax[v] = (S)lt[LT_SHARED + LT_PER_V * v + 1];
+        asum[v] = ax[v] + ay + az;
+        oa[v] = (unsigned)a * SB;
+        oal[v] = (unsigned)(a + A.mx * (vb + A.my * vc)) * SB;
     }
-    const S ayz = ay + az;
-    // emission-shape offset of (a, b, c) = oa + olyz
-    const unsigned olyz = (unsigned)(A.mx * (vb + A.my * vc)) * SB;
     const unsigned ob = (unsigned)(A.mx + vb) * SB, oc = (unsigned)(A.mx + A.my + vc) * SB;
     const double yz2 = xiy_d * xiy_d + xiz_d * xiz_d;
     const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
@@ -885,13 +883,15 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     }
 
     // ---- loads of the next cell, issued one cell ahead
-    S eb_n = (S)0, ec_n = (S)0, fx_n[VL], fy_n[VL];
+    S eb_n = (S)0, ec_n = (S)0, ex_n[VL], fx_n[VL], fy_n[VL];
 #pragma unroll
-    for (int v = 0; v < VL; ++v) fx_n[v] = fy_n[v] = (S)0;
+    for (int v = 0; v < VL; ++v) ex_n[v] = fx_n[v] = fy_n[v] = (S)0;
     auto prefetch = [&](int ii, int jj, int kk) {
         const S* E = etab + (size_t)(cell0 + ii * si + jj * sj + kk * sk) * MT;
         eb_n = ldb(E, ob);
         ec_n = ldb(E, oc);
+#pragma unroll
+        for (int v = 0; v < VL; ++v) ex_n[v] = ldb(E, oa[v]);
         if (ii == 0 && ir0 > 0) {
             const S* src = xin + ((size_t)kk * ny + jj) * fstride;
 #pragma unroll
@@ -912,9 +912,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     for (int v = 0; v < VL; ++v) prev[v] = (S)0;
     for (int n = 0; n < ncell; ++n) {
         const S eb = eb_n, ec = ec_n;
-        S fxp[VL], fyp[VL];
+        S ex[VL], fxp[VL], fyp[VL];
 #pragma unroll
         for (int v = 0; v < VL; ++v) {
+            ex[v] = ex_n[v];
             fxp[v] = fx_n[v];
             fyp[v] = fy_n[v];
         }
@@ -930,13 +931,6 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 
         const int cell = cell0 + ii * si + jj * sj + kk * sk;
         const S* P = params + (size_t)cell * PSTRIDE;
-        // this cell's x Gaussian factors, issued before its record is waited on
-        S ex[VL];
-        {
-            const S* E = etab + (size_t)cell * MT;
-#pragma unroll
-            for (int v = 0; v < VL; ++v) ex[v] = ldb(E, oa[v]);
-        }
         const uint32_t info = reinterpret_cast<const uint32_t*>(P + P_INFO)[0];
         if (!(info & SOLID_BIT)) {
             S fx[VL], fy[VL], fz[VL];
@@ -949,7 +943,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                     const S rf = P[P_RHO_SIDE + sideX];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fx[v] = rf * ldb(g, oa[v] + olyz);
+                    for (int v = 0; v < VL; ++v) fx[v] = rf * ldb(g, oal[v]);
                 }
             }
             {
@@ -966,7 +960,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                     const S rf = P[P_RHO_SIDE + sideY];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fy[v] = rf * ldb(g, oa[v] + olyz);
+                    for (int v = 0; v < VL; ++v) fy[v] = rf * ldb(g, oal[v]);
                 }
             }
             {
@@ -984,7 +978,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                     const S rf = P[P_RHO_SIDE + sideZ];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fz[v] = rf * ldb(g, oa[v] + olyz);
+                    for (int v = 0; v < VL; ++v) fz[v] = rf * ldb(g, oal[v]);
                 }
             }
 
@@ -996,28 +990,24 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             const S cyz2 = cy * cy + cz * cz;
             const S Lyz = L0 + L2 * cy + L3 * cz;
             const S Qyz = qy * cy + qz * cz;
-            const S ayzn = ayz + nu;
             double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
 #pragma unroll
             for (int v = 0; v < VL; ++v) {
-                const double xdv = xd0 + (double)v * hs;
-                const S xv = (S)xdv;
-                const S axv = fabs(xv) * invdx;
-                const S cx = xv - Ux;
+                const S cx = xix[v] - Ux;
                 const S c2 = cx * cx + cyz2;
                 const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
                 const S nfs = gyz * ex[v] * poly;
-                const S num = axv * fx[v] + ay * fy[v] + az * fz[v] + nfs;
-                const S f = num * fast_rcp(axv + ayzn);
+                const S num = ax[v] * fx[v] + ay * fy[v] + az * fz[v] + nfs;
+                const S f = num * fast_rcp(asum[v] + nu);
                 prev[v] = f;
                 lds(jj, ii, v) = f;
                 const double t0 = wd[v] * (double)f;
-                const double t1 = t0 * xdv;
-                const double t2 = t1 * xdv;
+                const double t1 = t0 * xd[v];
+                const double t2 = t1 * xd[v];
                 u0 += t0;
                 u1 += t1;
                 u2 += t2;
-                u3 += t2 * xdv;
+                u3 += t2 * xd[v];
             }
 
             if (ii == BX - 1 && wx) {

@@ -407,8 +407,6 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.spec_on = c->spec_on ? 1 : 0;
                 a.has_solid = c->nfluid < c->N ? 1 : 0;
                 a.nblocks = a.noct * cnt * c->ntiles;
-                a.hx = 2.0 * c->vg.vmax[0] / (c->vg.m[0] - 1);
-                a.invdx = 1.0 / c->dx[0];
             };
             hipError_t e;
             if (c->prec == DVM_F64) {
