@@ -124,21 +124,28 @@ void derive_schedule(dvm_ctx* c)
     c->Ssz = c->prec == DVM_F64 ? 8 : 4;
 
     // velocities per lane, brick shape (overridable for tuning)
-    // VL: 2 (FP64) or 4 (FP32) velocities per lane, halved while more than
-    // 1/8 of the lanes' velocity slots of the larger x half would be empty
+    // VL: 4 velocities per lane, halved while more than 1/8 of the lanes'
+    // velocity slots of the larger x half would be empty.  Brick and body by
+    // measurement (cavity 64^3 x 32^3 FP64, 96^3 x 28^3 and cube FP32):
+    // FP64 with 4 per lane: 2x2 bricks (the LDS plane of 4 FP64 values per
+    // lane and cell limits occupancy) and the software-pipelined body; FP64
+    // with 2: 4x2 bricks, plain body; FP32: 4x2 bricks, pipelined body.
     const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
-    int vl = c->prec == DVM_F64 ? 2 : 4;
+    int vl = 4;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
     vl = env_int("DVM_VL", vl);
-    int bx = env_int("DVM_BX", 4), by = env_int("DVM_BY", 2);
+    const bool f64 = c->prec == DVM_F64;
+    int bx = (f64 && vl == 4) ? 2 : 4;
+    int by = vl == 1 ? 4 : 2;
+    int pf = (!f64 || vl == 4) ? 1 : 0;
+    bx = env_int("DVM_BX", bx);
+    by = env_int("DVM_BY", by);
     if (!sweep_variant_available(c->prec, vl, bx, by)) { vl = 1; bx = 4; by = 4; }
     c->VL = vl;
     c->BX = bx;
     c->BY = by;
     c->BZ = env_int("DVM_BZ", 8);
-    // the software-pipelined sweep is faster with FP32 storage, the plain
-    // one with FP64 (measured on the cavity and cube workloads)
-    c->PF = env_int("DVM_PF", c->prec == DVM_F32 ? 1 : 0) != 0;
+    c->PF = env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
     c->nby = (c->g.ny + c->BY - 1) / c->BY;
