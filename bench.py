@@ -295,7 +295,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved_gbs / PEAK_HBM_GBS, 4),
             "traffic": measured_traffic(label),
-            "kernel": "sweep_kernel",
+            "kernel": info["sweep_kernel"],
             "bytes_per_point": 2 * sbytes,
             "launches_per_step": launches,
             "avg_launch_ms": round(sweep_ms / max(1, launches), 5),

@@ -98,6 +98,7 @@ typedef struct {
     int tiles_per_octant;       /* 64-lane velocity tiles per octant              */
     int sweep_launches;         /* sweep kernel launches per iteration            */
     size_t workspace_bytes;
+    int pipelined;              /* 1: software-pipelined sweep body, 0: plain     */
 } dvm_info;
 
 /* Create a context.  precision: DVM_F64 or DVM_F32 (storage and update type of

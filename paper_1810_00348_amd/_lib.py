@@ -47,7 +47,7 @@ class Info(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("ncells", C.c_int),
                 ("nfluid", C.c_int), ("m", C.c_int * 3), ("nvel", C.c_int), ("precision", C.c_int),
                 ("brick", C.c_int * 3), ("vel_per_lane", C.c_int), ("tiles_per_octant", C.c_int),
-                ("sweep_launches", C.c_int), ("workspace_bytes", C.c_size_t)]
+                ("sweep_launches", C.c_int), ("workspace_bytes", C.c_size_t), ("pipelined", C.c_int)]
 
 
 _P = C.POINTER(C.c_double)

@@ -801,6 +801,7 @@ dvm_status dvm_get_info(dvm_ctx* c, dvm_info* info)
     for (int T = 0; T < c->ndiag; ++T) launches += c->diag_cnt[T] > 0;
     info->sweep_launches = launches * (c->spec_on ? 2 : 1);
     info->workspace_bytes = c->off.end;
+    info->pipelined = c->PF;
     return DVM_OK;
 }
 

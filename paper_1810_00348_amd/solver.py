@@ -114,7 +114,8 @@ class Solver:
         return {"cells": [inf.nx, inf.ny, inf.nz], "nfluid": inf.nfluid, "m": list(inf.m),
                 "nvel": inf.nvel, "precision": inf.precision, "brick": list(inf.brick),
                 "vel_per_lane": inf.vel_per_lane, "tiles_per_octant": inf.tiles_per_octant,
-                "sweep_launches": inf.sweep_launches, "workspace_bytes": inf.workspace_bytes}
+                "sweep_launches": inf.sweep_launches, "workspace_bytes": inf.workspace_bytes,
+                "sweep_kernel": "sweep_kernel_pf" if inf.pipelined else "sweep_kernel"}
 
     def set_timing(self, enable: bool = True):
         L.check(L.lib().dvm_set_timing(self._h, int(enable)))
