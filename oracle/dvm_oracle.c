@@ -74,6 +74,9 @@ typedef struct {
     orc_case c;
     int N, NV;
     double dx[3];
+    double *h[3];           /* cell size along each axis, per index (the
+                               paper's cube runs use stretched meshes,
+                               Sec. 4.2); uniform lx/nx ... by default     */
     double *xi[3], *w1[3];
     unsigned char *solid;   /* N, may be all zero                          */
     /* wall / free-stream emission shapes: kinds 0..5 = the six domain
@@ -230,10 +233,34 @@ static int primitives(const double *W, int N, int cell, double *rho,
 void orc_destroy(orc_state *s)
 {
     if (!s) return;
-    for (int d = 0; d < 3; ++d) { free(s->xi[d]); free(s->w1[d]); }
+    for (int d = 0; d < 3; ++d) { free(s->xi[d]); free(s->w1[d]); free(s->h[d]); }
     for (int k = 0; k < 7; ++k) free(s->ghat[k]);
     free(s->solid); free(s->W); free(s->q); free(s->rho_w);
     free(s);
+}
+
+/* volume of cell id (finite-volume cell of a tensor-product mesh) */
+static double cell_volume(const orc_state *s, int id)
+{
+    const orc_case *c = &s->c;
+    const int i = id % c->nx, j = (id / c->nx) % c->ny, k = id / (c->nx * c->ny);
+    return s->h[0][i] * s->h[1][j] * s->h[2][k];
+}
+
+/* Non-uniform cell sizes along each axis (NULL keeps that axis uniform);
+   before the initial state is set.  The sizes must be positive. */
+int orc_set_spacing(orc_state *s, const double *hx, const double *hy, const double *hz)
+{
+    const double *in[3] = {hx, hy, hz};
+    const int n3[3] = {s->c.nx, s->c.ny, s->c.nz};
+    for (int d = 0; d < 3; ++d) {
+        if (!in[d]) continue;
+        for (int i = 0; i < n3[d]; ++i)
+            if (!(in[d][i] > 0)) return ORC_ERR;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (in[d]) memcpy(s->h[d], in[d], sizeof(double) * n3[d]);
+    return ORC_OK;
 }
 
 /* side s of a cell: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+; the normal pointing
@@ -253,6 +280,13 @@ orc_state *orc_create(const orc_case *cfg, const unsigned char *solid)
     s->dx[0] = cfg->lx / cfg->nx;
     s->dx[1] = cfg->ly / cfg->ny;
     s->dx[2] = cfg->lz / cfg->nz;
+    {
+        const int n3[3] = {cfg->nx, cfg->ny, cfg->nz};
+        for (int d = 0; d < 3; ++d) {
+            s->h[d] = (double *)malloc(sizeof(double) * n3[d]);
+            for (int i = 0; i < n3[d]; ++i) s->h[d][i] = s->dx[d];
+        }
+    }
     for (int d = 0; d < 3; ++d) {
         s->xi[d] = (double *)malloc(sizeof(double) * cfg->m[d]);
         s->w1[d] = (double *)malloc(sizeof(double) * cfg->m[d]);
@@ -349,12 +383,8 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
     const orc_case *c = &s->c;
     int al = a3 + c->m[0] * (b3 + c->m[1] * c3);
     double xv[3] = {s->xi[0][a3], s->xi[1][b3], s->xi[2][c3]};
-    double ad[3];
     int sg[3];
-    for (int d = 0; d < 3; ++d) {
-        sg[d] = xv[d] >= 0 ? 1 : -1;
-        ad[d] = fabs(xv[d]) / s->dx[d];
-    }
+    for (int d = 0; d < 3; ++d) sg[d] = xv[d] >= 0 ? 1 : -1;
     for (int kq = 0; kq < c->nz; ++kq) {
         int k = sg[2] > 0 ? kq : c->nz - 1 - kq;
         for (int jq = 0; jq < c->ny; ++jq) {
@@ -365,6 +395,10 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                 if (s->solid[id]) { f[id] = 0; continue; }
                 double num = nu[id] * feq[id];
                 double den = nu[id];
+                /* |xi_d| / (cell size along d): the flux through the cell's
+                   upwind face per unit volume                               */
+                const double ad[3] = {fabs(xv[0]) / s->h[0][i], fabs(xv[1]) / s->h[1][j],
+                                      fabs(xv[2]) / s->h[2][k]};
                 for (int d = 0; d < 3; ++d) {
                     if (ad[d] == 0) continue;
                     int side = 2 * d + (sg[d] > 0 ? 0 : 1); /* upwind side */
@@ -409,8 +443,7 @@ int orc_init_fields(orc_state *s, const double *rho, const double *u,
     }
     memset(s->q, 0, sizeof(double) * 3 * N);
     double m0 = 0;
-    double dv = s->dx[0] * s->dx[1] * s->dx[2];
-    for (int id = 0; id < N; ++id) if (!s->solid[id]) m0 += s->W[id] * dv;
+    for (int id = 0; id < N; ++id) if (!s->solid[id]) m0 += s->W[id] * cell_volume(s, id);
     s->M0 = m0;
     /* initial wall densities: non-penetration with the equilibrium of the
        initial state at the wall-adjacent cell                              */
@@ -717,8 +750,8 @@ int orc_iterate(orc_state *s)
                 }
         /* closed domain: rescale so that the total mass stays M0 */
         if (c->closed) {
-            double m = 0, dv = s->dx[0] * s->dx[1] * s->dx[2];
-            for (int id = 0; id < N; ++id) if (!s->solid[id]) m += Wn[id] * dv;
+            double m = 0;
+            for (int id = 0; id < N; ++id) if (!s->solid[id]) m += Wn[id] * cell_volume(s, id);
             double sc = s->M0 / m;
             for (int v = 0; v < 5 * N; ++v) Wn[v] *= sc;
             for (int v = 0; v < 3 * N; ++v) qn[v] *= sc;
@@ -779,8 +812,8 @@ int orc_set_state(orc_state *s, const double *W, const double *q,
 
 double orc_total_mass(const orc_state *s)
 {
-    double m = 0, dv = s->dx[0] * s->dx[1] * s->dx[2];
-    for (int id = 0; id < s->N; ++id) if (!s->solid[id]) m += s->W[id] * dv;
+    double m = 0;
+    for (int id = 0; id < s->N; ++id) if (!s->solid[id]) m += s->W[id] * cell_volume(s, id);
     return m;
 }
 

@@ -78,6 +78,7 @@ def lib():
         L.orc_equilibrium.argtypes = [C.POINTER(C.c_int), C.POINTER(_P), C.POINTER(_P),
                                       C.c_double, _P, C.c_double, _P, C.c_double, C.c_int, _P]
         L.orc_num_threads.argtypes = [C.c_void_p]
+        L.orc_set_spacing.argtypes = [C.c_void_p, _P, _P, _P]
         _lib = L
     return _lib
 
@@ -148,6 +149,11 @@ class Oracle:
         if not self._h:
             raise ValueError("oracle rejected the case")
         self.N = case.ncells
+        sp3 = getattr(case, "spacing", None)
+        if sp3 is not None:
+            self._sp = [None if h is None else np.ascontiguousarray(h, dtype=np.float64) for h in sp3]
+            if lib().orc_set_spacing(self._h, *[None if h is None else _ptr(h) for h in self._sp]) != 0:
+                raise ValueError("bad cell sizes")
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -69,6 +69,9 @@ class Case:
     init_rho: float = 1.0
     init_u: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     init_T: float = 1.0
+    # cell sizes along x, y, z (arrays of length nx, ny, nz summing to L),
+    # None for a uniform mesh
+    spacing: Optional[Tuple[Optional[np.ndarray], Optional[np.ndarray], Optional[np.ndarray]]] = None
 
     @property
     def ncells(self) -> int:
@@ -199,3 +202,27 @@ def random_fields(case: Case, seed: int, drho: float = 0.2, du: float = 0.2,
         u[d] = case.init_u[d] + du * (rng.random(N) - 0.5)
     T = case.init_T * (1.0 + dT * (rng.random(N) - 0.5))
     return rho, u, T
+
+
+def stretched_axis(n: int, length: float, ratio: float, centre: Optional[float] = None) -> np.ndarray:
+    """Cell sizes of a mesh line of n cells and the given length that grow
+    geometrically by ``ratio`` away from the two ends (centre None: cells
+    cluster at both walls, as next to the cavity walls) or away from the
+    interior point ``centre`` (cells cluster there, as around a body)."""
+    if ratio <= 0:
+        raise ValueError("ratio must be positive")
+    idx = np.arange(n, dtype=np.float64)
+    if centre is None:
+        k = np.minimum(idx, n - 1 - idx)
+    else:
+        pos = (idx + 0.5) / n * length
+        k = np.floor(np.abs(pos - centre) / (length / n))
+    h = ratio ** k
+    return h * (length / h.sum())
+
+
+def stretched(case: Case, ratio: float, centres=(None, None, None)) -> Case:
+    """The same case on a mesh stretched along every axis (same cell counts
+    and lengths)."""
+    sp = tuple(stretched_axis(case.n[d], case.L[d], ratio, centres[d]) for d in range(3))
+    return dataclasses.replace(case, spacing=sp, name=case.name + f"_stretch{ratio:g}")

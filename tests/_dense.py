@@ -7,7 +7,8 @@ in eq. "sweeping_example") is a linear system over all cells:
     (nu_c + sum_d a_d) f_c - sum_{d: upwind neighbour fluid} a_d f_up(c,d)
         = nu_c f~S_c + sum_{d: upwind side is a boundary} a_d f_boundary
 
-with a_d = |xi_d| / dx_d.  Here it is assembled as a dense matrix and solved
+with a_d = |xi_d| / dx_d(c), dx_d(c) the size of cell c along d (uniform or
+a stretched mesh).  Here it is assembled as a dense matrix and solved
 with LU (numpy), i.e. without any notion of sweep order, so it checks the
 oracle's sweep (traversal order, upwind selection, boundary bookkeeping).
 """
@@ -30,7 +31,10 @@ def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=
         M, V = case.m[d], case.vmax[d]
         axes.append(np.linspace(-V, V, M))
     xi = np.array([axes[0][a3], axes[1][b3], axes[2][c3]])
-    dx = np.array([case.L[0] / nx, case.L[1] / ny, case.L[2] / nz])
+    sp = getattr(case, "spacing", None)
+    h = [np.full(n, case.L[d] / n) for d, n in enumerate((nx, ny, nz))]
+    if sp is not None:
+        h = [h[d] if sp[d] is None else np.asarray(sp[d], dtype=np.float64) for d in range(3)]
     solid = case.solid_flat() if case.solid is not None else np.zeros(N, np.uint8)
     A = np.zeros((N, N))
     b = np.zeros(N)
@@ -46,7 +50,7 @@ def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=
                 pos = [i, j, k]
                 ext = [nx, ny, nz]
                 for d in range(3):
-                    ad = abs(xi[d]) / dx[d]
+                    ad = abs(xi[d]) / h[d][pos[d]]
                     if ad == 0:
                         continue
                     A[c, c] += ad

@@ -159,10 +159,13 @@ def _tiny_cases():
     c4 = dataclasses.replace(cases.cavity((3, 3, 4), 6, kn=0.5, lid=0.3, vmax=4.0), closed=True)
     c4.faces = list(c4.faces)
     c4.faces[0] = cases.Face("free", u=(0.3, 0.0, 0.0), T=1.2, rho=0.9)
-    return [c1, c2, c3, c4]
+    c5 = cases.stretched(cases.cavity((4, 3, 5), 4, kn=0.4, lid=0.3), 1.4)           # wall-clustered mesh
+    c6 = cases.stretched(cases.cube_half(nx=6, ny=4, nz=3, edge=2, x0=2, m=6, vmax=6.0, mach=1.5, kn=0.5),
+                         1.3, centres=(0.75, 1.0, None))                              # clustered at the cube
+    return [c1, c2, c3, c4, c5, c6]
 
 
-@pytest.mark.parametrize("ci", range(4))
+@pytest.mark.parametrize("ci", range(6))
 def test_sweep_matches_dense_solve(oracle_mod, ci):
     case = _tiny_cases()[ci]
     o = oracle_mod.Oracle(case)
@@ -185,6 +188,48 @@ def test_sweep_matches_dense_solve(oracle_mod, ci):
         f, feq, nu = o.sweep_one(alpha, spec)
         ref = dense_velocity_solve(case, alpha, feq, nu, rw, ghat, spec)
         assert np.abs(f - ref).max() <= 1e-12 * max(1e-300, np.abs(ref).max()), alpha
+
+
+# ------------------------------------------------------- non-uniform mesh
+
+def test_explicit_uniform_spacing_changes_nothing(oracle_mod):
+    case = cases.cavity((5, 4, 6), 6, kn=0.5, lid=0.3)
+    h = tuple(np.full(n, L / n) for n, L in zip(case.n, case.L))
+    a, b = oracle_mod.Oracle(case), oracle_mod.Oracle(dataclasses.replace(case, spacing=h))
+    for o in (a, b):
+        o.init_uniform()
+        o.iterate(2)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+
+
+def test_stretched_mesh_conserves_mass_and_rest_state(oracle_mod):
+    case = cases.stretched(cases.cavity((6, 5, 7), 8, kn=0.6, lid=0.25), 1.35)
+    o = oracle_mod.Oracle(case)
+    rho, u, T = cases.random_fields(case, seed=4)
+    o.init_fields(rho, u, T)
+    hx, hy, hz = case.spacing
+    vol = (hz[:, None, None] * hy[None, :, None] * hx[None, None, :]).ravel()
+    M0 = float((rho * vol).sum())
+    assert abs(o.initial_mass() - M0) < 1e-14 * M0
+    for _ in range(3):
+        o.iterate(1)
+        W = o.state()[0]
+        assert abs((W[0] * vol).sum() - M0) < 1e-13 * M0
+    rest = cases.stretched(cases.cavity((6, 5, 7), 8, kn=0.6, lid=0.0), 1.35)
+    o = oracle_mod.Oracle(rest)
+    o.init_uniform()
+    W0 = o.state()[0]
+    o.iterate(2)
+    assert np.abs(o.state()[0] - W0).max() < 1e-14
+
+
+def test_stretched_axis_sizes():
+    h = cases.stretched_axis(8, 2.0, 1.2)
+    assert abs(h.sum() - 2.0) < 1e-14 and np.allclose(h, h[::-1])
+    assert np.allclose(h[1:4] / h[0:3], 1.2)
+    g = cases.stretched_axis(10, 1.0, 1.5, centre=0.25)
+    assert abs(g.sum() - 1.0) < 1e-14 and np.argmin(g) in (2, 3)
 
 
 # ------------------------------------------------------------- invariants
