@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic", default=None)
     ap.add_argument("--time-to-residual", action="store_true")
+    ap.add_argument("--stretch", type=float, default=0.0,
+                    help="run the workload on a mesh stretched geometrically by this ratio per cell")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=6, default=None,
@@ -231,6 +233,10 @@ def main():
     case, prec = workload(args.workload, args.kn)
     if args.precision:
         prec = args.precision
+    if args.stretch > 0:
+        from paper_1810_00348_amd import cases as _cases
+        centres = (None, None, None) if args.workload != "c4" else (2.5, 3.0, None)
+        case = _cases.stretched(case, args.stretch, centres)
     s = Solver(case, precision=prec)
     s.init_uniform()
     info = s.info()
@@ -257,6 +263,8 @@ def main():
     # (points x 2 s) / (sweep time of one iteration).
     achieved_gbs = pts * 2 * sbytes / (sweep_ms / 1e3) / 1e9
     label = f"{args.workload}_{prec}_vl{info['vel_per_lane']}_b{info['brick'][0]}x{info['brick'][1]}x{info['brick'][2]}"
+    if args.stretch > 0:
+        label += f"_stretch{args.stretch:g}"
     line = {
         "metric": "phase-space GPoint-updates/s per iteration",
         "value": round(value, 3),

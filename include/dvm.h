@@ -123,6 +123,16 @@ dvm_status dvm_set_solid(dvm_ctx* ctx, const unsigned char* mask, const double u
    total mass stays that of the initial state (Sec. 3.4, internal flows). */
 dvm_status dvm_set_closed(dvm_ctx* ctx, int closed);
 
+/* Non-uniform tensor-product mesh (the stretched meshes of the paper's cube
+   runs, Sec. 4.2): cell sizes along x (nx values), y (ny) and z (nz), host
+   arrays copied by the call; NULL keeps that axis uniform (length / n).
+   Each axis's sizes must be positive and sum to its length in dvm_grid
+   (relative 1e-9).  The upwind coefficient of a cell along d is
+   |xi_d| / h_d(cell) (finite-volume flux form) and cell volumes weigh the
+   total mass.  Before binding the workspace; DVM_ERR_STATE after it,
+   DVM_ERR_ARG for bad sizes. */
+dvm_status dvm_set_spacing(dvm_ctx* ctx, const double* hx, const double* hy, const double* hz);
+
 /* Bytes of device workspace the context needs with its current settings. */
 dvm_status dvm_required_workspace(dvm_ctx* ctx, size_t* bytes);
 

@@ -22,8 +22,11 @@ enum {
     P_QX, P_QY, P_QZ,  // sigma * q
     P_TWO_T,    // 2 / T
     P_INFO,     // the cell info word (bit pattern in the slot's low 32 bits)
+    P_IDX,      // 1 / cell size along x (non-uniform meshes)
+    P_IDY,      // 1 / cell size along y
     P_NPARAM,
-    P_RHO_SIDE = 16  // 6 slots: inflow density of each side (wall rho_w or free-stream rho)
+    P_RHO_SIDE = 16,  // 6 slots: inflow density of each side (wall rho_w or free-stream rho)
+    P_IDZ = 22        // 1 / cell size along z
 };
 
 // cell info word: 4 bits per side (side s = 2 d + (upper ? 1 : 0)):
@@ -47,7 +50,6 @@ struct Consts {
     double omega, pr;
     int correct;
     int closed;
-    double dV;
     double kind_rho[8];   // fixed emission density (free stream), per kind
     int kind_wall[8];     // 1: density from non-penetration
 };
@@ -58,6 +60,7 @@ struct DevPtrs {
     const uint32_t* cellinfo;
     const int* bricks;    // int4 (I, J, K, 0) per brick, grouped by diagonal
     const double* lanetab;
+    const double* h;      // cell sizes: [nx] along x, then [ny], then [nz]
 };
 
 template <typename S>
@@ -93,7 +96,8 @@ hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind
 hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* params, const void* etab,
                             const double* ghat64, const double* gout, double* rho_w, int prec,
                             hipStream_t st);
-hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, const void* args, hipStream_t st);
+hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, const void* args,
+                        hipStream_t st);
 hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
                            const double* gout, double* Wn, double* qn, double* rwn,
                            double* blockmass, int nblocks, int* flag, hipStream_t st);
@@ -104,6 +108,6 @@ hipError_t launch_scale_residual(const Consts& C, const DevPtrs& D, double M0,
 hipError_t launch_residual_final(const double* respart, int nblocks, const double* blockmass,
                                  int nbm, double* out, const int* flag, hipStream_t st);
 hipError_t launch_selftest_reduce(const double* in, double* out, hipStream_t st);
-bool sweep_variant_available(int prec, int vl, int bx, int by);
+bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform);
 
 }  // namespace dvm

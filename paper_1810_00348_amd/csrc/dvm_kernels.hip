@@ -156,6 +156,15 @@ __global__ __launch_bounds__(128) void params_kernel(Consts C, DevPtrs D, const 
     reinterpret_cast<uint32_t*>(params + (size_t)cell * PSTRIDE + P_INFO)[0] = info;
     if (info & SOLID_BIT) return;
     {
+        // inverse cell sizes (the upwind coefficients |xi_d| / h_d of a
+        // non-uniform mesh)
+        S* P = params + (size_t)cell * PSTRIDE;
+        const int i = cell % C.nx, j = (cell / C.nx) % C.ny, k = cell / (C.nx * C.ny);
+        P[P_IDX] = (S)(1.0 / D.h[i]);
+        P[P_IDY] = (S)(1.0 / D.h[C.nx + j]);
+        P[P_IDZ] = (S)(1.0 / D.h[C.nx + C.ny + k]);
+    }
+    {
         // inflow density of each side: the wall density of iteration n at a
         // diffuse wall, the free-stream density at a free-stream face
         S* P = params + (size_t)cell * PSTRIDE;
@@ -544,7 +553,7 @@ __device__ __forceinline__ void stb(T* base, unsigned off, T v)
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
-template <typename S, int VL, int BX, int BY>
+template <typename S, int VL, int BX, int BY, bool NU>
 __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __restrict__ params,
                                            const S* __restrict__ etab, const S* __restrict__ ghat,
                                            const double* __restrict__ lanetab, const int* __restrict__ bricks,
@@ -720,6 +729,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 const S cyz2 = cy * cy + cz * cz;
                 const S Lyz = L0 + L2 * cy + L3 * cz;
                 const S Qyz = qy * cy + qz * cz;
+                // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
+                // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
+                S ayc = ay, azc = az, idx = (S)1, aynu = (S)0;
+                if constexpr (NU) {
+                    idx = P[P_IDX];
+                    ayc = ay * P[P_IDY];
+                    azc = az * P[P_IDZ];
+                    aynu = ayc + azc + nu;
+                }
                 double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
 #pragma unroll
                 for (int v = 0; v < VL; ++v) {
@@ -727,8 +745,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                     const S c2 = cx * cx + cyz2;
                     const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
                     const S nfs = gyz * ldb(E, oa[v]) * poly;
-                    const S num = ax[v] * fx[v] + ay * fy[v] + az * fz[v] + nfs;
-                    const S f = num * fast_rcp(asum[v] + nu);
+                    const S axv = NU ? ax[v] * idx : ax[v];
+                    const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
+                    const S f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
                     prev[v] = f;
                     lds(jj, ii, v) = f;
                     const double fd = (double)f;
@@ -795,7 +814,7 @@ extern __shared__ __align__(16) unsigned char dvm_sweep_lds[];
 // upwind operand from LDS.  Moments are accumulated from the node weight and
 // abscissa (three more multiplies per velocity instead of four per-velocity
 // weight products held in registers).
-template <typename S, int VL, int BX, int BY>
+template <typename S, int VL, int BX, int BY, bool NU>
 __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __restrict__ params,
                                               const S* __restrict__ etab, const S* __restrict__ ghat,
                                               const double* __restrict__ lanetab, const int* __restrict__ bricks,
@@ -990,6 +1009,15 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             const S cyz2 = cy * cy + cz * cz;
             const S Lyz = L0 + L2 * cy + L3 * cz;
             const S Qyz = qy * cy + qz * cz;
+            // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
+            // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
+            S ayc = ay, azc = az, idx = (S)1, aynu = (S)0;
+            if constexpr (NU) {
+                idx = P[P_IDX];
+                ayc = ay * P[P_IDY];
+                azc = az * P[P_IDZ];
+                aynu = ayc + azc + nu;
+            }
             double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
 #pragma unroll
             for (int v = 0; v < VL; ++v) {
@@ -997,8 +1025,9 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 const S c2 = cx * cx + cyz2;
                 const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
                 const S nfs = gyz * ex[v] * poly;
-                const S num = ax[v] * fx[v] + ay * fy[v] + az * fz[v] + nfs;
-                const S f = num * fast_rcp(asum[v] + nu);
+                const S axv = NU ? ax[v] * idx : ax[v];
+                const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
+                const S f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
                 prev[v] = f;
                 lds(jj, ii, v) = f;
                 const double t0 = wd[v] * (double)f;
@@ -1057,19 +1086,20 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     }
 }
 
-template <typename S, int VL, int BX, int BY>
+// NU: non-uniform mesh (the upwind coefficients take the cell's own sizes)
+template <typename S, int VL, int BX, int BY, bool NU>
 __global__ __launch_bounds__(64) void sweep_kernel_pf(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
-    sweep_body_pf<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
+    sweep_body_pf<S, VL, BX, BY, NU>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
                                  A.spec, A.partial, plane);
 }
 
-template <typename S, int VL, int BX, int BY>
+template <typename S, int VL, int BX, int BY, bool NU>
 __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
-    sweep_body<S, VL, BX, BY>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
+    sweep_body<S, VL, BX, BY, NU>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
                               A.spec, A.partial, plane);
 }
 
@@ -1079,29 +1109,51 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
     X(double, 2, 2, 2) X(double, 4, 2, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2) X(float, 4, 4, 4) \
     X(float, 4, 2, 2) X(float, 8, 4, 2) X(float, 8, 2, 2)
+// the shapes the defaults choose, also built for non-uniform meshes
+#define DVM_SWEEP_VARIANTS_NU(X) \
+    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) \
+    X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 
-bool sweep_variant_available(int prec, int vl, int bx, int by)
+bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform)
 {
 #define X(T, V, BXX, BYY) \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) return true;
-    DVM_SWEEP_VARIANTS(X)
+    if (nonuniform) {
+        DVM_SWEEP_VARIANTS_NU(X)
+    } else {
+        DVM_SWEEP_VARIANTS(X)
+    }
 #undef X
     return false;
 }
 
-hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, const void* args, hipStream_t st)
+template <typename T, int V, int BXX, int BYY, bool NU>
+hipError_t launch_sweep_t(int pipelined, const void* args, hipStream_t st)
+{
+    const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
+    const size_t lds = (size_t)BYY * BXX * V * 64 * sizeof(T);
+    if (pipelined)
+        sweep_kernel_pf<T, V, BXX, BYY, NU><<<a.nblocks, 64, lds, st>>>(a);
+    else
+        sweep_kernel<T, V, BXX, BYY, NU><<<a.nblocks, 64, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, const void* args,
+                        hipStream_t st)
 {
 #define X(T, V, BXX, BYY)                                                                  \
-    if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) {            \
-        const SweepArgs<T>& a = *(const SweepArgs<T>*)args;                                \
-        const size_t lds = (size_t)BYY * BXX * V * 64 * sizeof(T);                         \
-        if (pipelined)                                                                     \
-            sweep_kernel_pf<T, V, BXX, BYY><<<a.nblocks, 64, lds, st>>>(a);                 \
-        else                                                                               \
-            sweep_kernel<T, V, BXX, BYY><<<a.nblocks, 64, lds, st>>>(a);                    \
-        return hipGetLastError();                                                          \
+    if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY)              \
+        return launch_sweep_t<T, V, BXX, BYY, NUV>(pipelined, args, st);
+    if (nonuniform) {
+#define NUV true
+        DVM_SWEEP_VARIANTS_NU(X)
+#undef NUV
+    } else {
+#define NUV false
+        DVM_SWEEP_VARIANTS(X)
+#undef NUV
     }
-    DVM_SWEEP_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -1173,7 +1225,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, cons
                 }
                 rwn[(size_t)s * N + cell] = r;
             }
-            mass = rho;
+            const int i = cell % C.nx, j = (cell / C.nx) % C.ny, k = cell / (C.nx * C.ny);
+            mass = rho * (D.h[i] * D.h[C.nx + j] * D.h[C.nx + C.ny + k]);
         }
     }
     red[threadIdx.x] = mass;
@@ -1217,7 +1270,7 @@ __global__ __launch_bounds__(256) void scale_residual_kernel(Consts C, DevPtrs D
 {
     __shared__ double red[256];
     const double total = block_sum_fixed(blockmass, nbm, red);
-    const double s = C.closed ? M0 / (total * C.dV) : 1.0;
+    const double s = C.closed ? M0 / total : 1.0;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = C.N;
     double dd[5] = {0, 0, 0, 0, 0}, nn[5] = {0, 0, 0, 0, 0};
@@ -1254,7 +1307,7 @@ hipError_t launch_scale_residual(const Consts& C, const DevPtrs& D, double M0, c
     return hipGetLastError();
 }
 
-// out[0..4]: residual per field, out[5]: total mass before rescaling (sum rho),
+// out[0..4]: residual per field, out[5]: total mass before rescaling,
 // out[6]: error flag
 __global__ __launch_bounds__(256) void residual_final_kernel(const double* __restrict__ respart, int nblocks,
                                                              const double* __restrict__ blockmass, int nbm,

@@ -74,6 +74,9 @@ struct dvm_ctx {
     int hsplit[3];  // number of nodes with xi < 0 along each axis
     int VL = 2, BX = 4, BY = 4, BZ = 8;
     int PF = 1;  // software-pipelined sweep body
+    std::vector<double> h[3];  // cell sizes along x, y, z (empty: uniform)
+    std::vector<double> hstage;  // host copy of the uploaded sizes
+    bool nonuniform = false;
     int nbx = 0, nby = 0, nbz = 0;
     int ntiles = 0, slots = 0, lstride = 0;
     std::vector<int> bricks;           // I, J, K, 0 per brick, grouped by diagonal
@@ -86,7 +89,7 @@ struct dvm_ctx {
     size_t ws_bytes = 0;
     bool bound = false;
     struct {
-        size_t axes, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
+        size_t axes, spacing, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
             partial, xface, yface, zface, spec, blockmass, respart, out, flag, end;
     } off;
     size_t Ssz = 8;
@@ -143,7 +146,12 @@ void derive_schedule(dvm_ctx* c)
     int pf = (!f64 || vl == 4) ? 1 : 0;
     bx = env_int("DVM_BX", bx);
     by = env_int("DVM_BY", by);
-    if (!sweep_variant_available(c->prec, vl, bx, by)) { vl = 1; bx = 4; by = 4; }
+    if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform)) {
+        // the shape is not built (for this mesh kind): the defaults' shape for VL
+        bx = (f64 && vl == 4) ? 2 : 4;
+        by = vl == 1 ? 4 : 2;
+        if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform)) { vl = 1; bx = 4; by = 4; }
+    }
     c->VL = vl;
     c->BX = bx;
     c->BY = by;
@@ -190,6 +198,16 @@ void derive_schedule(dvm_ctx* c)
     c->nbF = (c->N + 255) / 256;
 }
 
+// cell size along axis d of index i
+double cell_size(const dvm_ctx* c, int d, int i) { return c->nonuniform ? c->h[d][i] : c->dx[d]; }
+
+double cell_volume(const dvm_ctx* c, size_t cell)
+{
+    const int nx = c->g.nx, ny = c->g.ny;
+    const int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((size_t)nx * ny));
+    return cell_size(c, 0, i) * cell_size(c, 1, j) * cell_size(c, 2, k);
+}
+
 void layout(dvm_ctx* c)
 {
     size_t o = 0;
@@ -201,6 +219,7 @@ void layout(dvm_ctx* c)
     const size_t N = (size_t)c->N, S = c->Ssz;
     const size_t fst = (size_t)c->slots * c->VL;
     c->off.axes = take(sizeof(double) * 2 * 3 * MAXM);
+    c->off.spacing = take(sizeof(double) * (size_t)(c->g.nx + c->g.ny + c->g.nz));
     c->off.cellinfo = take(sizeof(uint32_t) * N);
     c->off.bricks = take(sizeof(int) * c->bricks.size());
     c->off.lanetab = take(sizeof(double) * 8 * (size_t)c->slots * c->lstride);
@@ -245,7 +264,6 @@ Consts make_consts(const dvm_ctx* c)
     C.pr = c->gas.pr;
     C.correct = c->gas.conservative_correction;
     C.closed = c->closed;
-    C.dV = c->dx[0] * c->dx[1] * c->dx[2];
     for (int k = 0; k < 8; ++k) {
         C.kind_rho[k] = c->kind_rho[k];
         C.kind_wall[k] = c->kind_wall[k];
@@ -261,6 +279,7 @@ DevPtrs make_ptrs(const dvm_ctx* c)
     D.cellinfo = c->P<uint32_t>(c->off.cellinfo);
     D.bricks = c->P<int>(c->off.bricks);
     D.lanetab = c->P<double>(c->off.lanetab);
+    D.h = c->P<double>(c->off.spacing);
     return D;
 }
 
@@ -340,8 +359,10 @@ std::vector<double> build_lanetab(const dvm_ctx* c, const std::vector<double> xi
             const int b = na[1] > 0 ? node(1, bl) : 0, cc = na[2] > 0 ? node(2, cl) : 0;
             L[0] = xi[1][b];
             L[1] = xi[2][cc];
-            L[2] = fabs(xi[1][b]) / c->dx[1];
-            L[3] = fabs(xi[2][cc]) / c->dx[2];
+            // |xi_d| / h_d; on a non-uniform mesh |xi_d| (the sweep takes the
+            // cell's own inverse sizes)
+            L[2] = fabs(xi[1][b]) / (c->nonuniform ? 1.0 : c->dx[1]);
+            L[3] = fabs(xi[2][cc]) / (c->nonuniform ? 1.0 : c->dx[2]);
             L[4] = b;
             L[5] = cc;
             for (int v = 0; v < c->VL; ++v) {
@@ -351,7 +372,7 @@ std::vector<double> build_lanetab(const dvm_ctx* c, const std::vector<double> xi
                 const int a = na[0] > 0 ? node(0, al) : 0;
                 double* Lv = L + LT_SHARED + LT_PER_V * v;
                 Lv[0] = xi[0][a];
-                Lv[1] = fabs(xi[0][a]) / c->dx[0];
+                Lv[1] = fabs(xi[0][a]) / (c->nonuniform ? 1.0 : c->dx[0]);
                 Lv[2] = on ? weight(0, a) * weight(1, b) * weight(2, cc) : 0.0;
                 Lv[3] = a;
             }
@@ -422,11 +443,11 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
             if (c->prec == DVM_F64) {
                 SweepArgs<double> a;
                 fill(a);
-                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, &a, st);
+                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, &a, st);
             } else {
                 SweepArgs<float> a;
                 fill(a);
-                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, &a, st);
+                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, &a, st);
             }
             if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
         }
@@ -482,8 +503,8 @@ dvm_status upload_initial(dvm_ctx* c, const std::vector<double>& Wh)
     if (hflag) return fail(DVM_ERR_NONPHYSICAL, "non-physical initial state (flag %d)", hflag);
     double m = 0;
     for (size_t i = 0; i < N; ++i)
-        if (!(c->cellinfo[i] & SOLID_BIT)) m += Wh[i];
-    c->M0 = m * c->dx[0] * c->dx[1] * c->dx[2];
+        if (!(c->cellinfo[i] & SOLID_BIT)) m += Wh[i] * cell_volume(c, i);
+    c->M0 = m;
     for (int v = 0; v < 5; ++v) c->res[v] = 0;
     c->initialized = true;
     return DVM_OK;
@@ -560,6 +581,36 @@ dvm_status dvm_set_solid(dvm_ctx* c, const unsigned char* mask, const double u_w
     return DVM_OK;
 }
 
+dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const double* hz)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "cell sizes must be set before binding the workspace");
+    const double* in[3] = {hx, hy, hz};
+    const int n3[3] = {c->g.nx, c->g.ny, c->g.nz};
+    const double L3[3] = {c->g.lx, c->g.ly, c->g.lz};
+    for (int d = 0; d < 3; ++d) {
+        if (!in[d]) continue;
+        double sum = 0;
+        for (int i = 0; i < n3[d]; ++i) {
+            if (!(in[d][i] > 0) || !isfinite(in[d][i])) return fail(DVM_ERR_ARG, "axis %d: cell size %d must be > 0", d, i);
+            sum += in[d][i];
+        }
+        if (fabs(sum - L3[d]) > 1e-9 * L3[d]) return fail(DVM_ERR_ARG, "axis %d: cell sizes sum to %.17g, not the length %.17g", d, sum, L3[d]);
+    }
+    bool any = false;
+    for (int d = 0; d < 3; ++d) {
+        if (in[d]) {
+            c->h[d].assign(in[d], in[d] + n3[d]);
+            any = true;
+        } else {
+            c->h[d].assign(n3[d], c->dx[d]);
+        }
+    }
+    c->nonuniform = any;
+    derive_schedule(c);
+    return DVM_OK;
+}
+
 dvm_status dvm_set_closed(dvm_ctx* c, int closed)
 {
     if (check_ctx(c)) return DVM_ERR_ARG;
@@ -615,6 +666,15 @@ dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
         ks[4 * k + 3] = T;
     }
     HIPCHK(hipMemcpyAsync(c->ws + c->off.axes, axes.data(), sizeof(double) * axes.size(), hipMemcpyHostToDevice, st));
+    {
+        std::vector<double> hs;
+        const int n3[3] = {c->g.nx, c->g.ny, c->g.nz};
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i < n3[d]; ++i) hs.push_back(cell_size(c, d, i));
+        c->hstage = hs;
+        HIPCHK(hipMemcpyAsync(c->ws + c->off.spacing, c->hstage.data(), sizeof(double) * c->hstage.size(),
+                              hipMemcpyHostToDevice, st));
+    }
     HIPCHK(hipMemcpyAsync(c->ws + c->off.cellinfo, c->cellinfo.data(), sizeof(uint32_t) * c->N, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(c->ws + c->off.bricks, c->bricks.data(), sizeof(int) * c->bricks.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(c->ws + c->off.lanetab, lt.data(), sizeof(double) * lt.size(), hipMemcpyHostToDevice, st));
@@ -643,10 +703,9 @@ dvm_status dvm_init_fields(dvm_ctx* c, const double* rho, const double* u, const
         if (!(rho[i] > 0) || !(T[i] > 0) || !isfinite(rho[i]) || !isfinite(T[i]) || !isfinite(u[i]) ||
             !isfinite(u[N + i]) || !isfinite(u[2 * N + i]))
             return fail(DVM_ERR_NONPHYSICAL, "cell %zu: rho, T must be > 0 and finite", i);
-        mass += rho[i];
+        mass += rho[i] * cell_volume(c, i);
     }
-    const double dV = c->dx[0] * c->dx[1] * c->dx[2];
-    const double scale = target_mass > 0 ? target_mass / (mass * dV) : 1.0;
+    const double scale = target_mass > 0 ? target_mass / mass : 1.0;
     std::vector<double> Wh(5 * N, 0.0);
     for (size_t i = 0; i < N; ++i) {
         if (c->cellinfo[i] & SOLID_BIT) continue;

@@ -48,6 +48,9 @@ class Solver:
             u = np.ascontiguousarray(case.solid_u, dtype=np.float64)
             L.check(lib.dvm_set_solid(h, self._solid.ctypes.data_as(C.c_void_p), _ptr(u), case.solid_T))
         L.check(lib.dvm_set_closed(h, int(case.closed)))
+        if case.spacing is not None:
+            self._spacing = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in case.spacing]
+            L.check(lib.dvm_set_spacing(h, *[None if a is None else _ptr(a) for a in self._spacing]))
         nbytes = C.c_size_t()
         L.check(lib.dvm_required_workspace(h, C.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)

@@ -104,3 +104,30 @@ def test_argument_errors(L):
     assert lib.dvm_init_uniform(h, 1.0, (C.c_double * 3)(0, 0, 0), 1.0) == -2  # no workspace
     assert lib.dvm_bind_workspace(h, C.c_void_p(1024), 10) == -3  # too small
     lib.dvm_destroy(h)
+
+
+def test_spacing_arguments(L):
+    """dvm_set_spacing: host-side validation and the variant it selects."""
+    import numpy as np
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    case = cases.cavity((6, 5, 4), 16, kn=1.0)
+    h = _ctx(L, case)
+    P = C.POINTER(C.c_double)
+    good = np.full(6, 1.0 / 6)
+    bad_sum = np.full(6, 0.2)
+    neg = good.copy()
+    neg[2] = -neg[2]
+    assert lib.dvm_set_spacing(h, bad_sum.ctypes.data_as(P), None, None) == -1
+    assert b"sum" in lib.dvm_last_error()
+    assert lib.dvm_set_spacing(h, neg.ctypes.data_as(P), None, None) == -1
+    hy = cases.stretched_axis(5, 1.0, 1.3)
+    assert lib.dvm_set_spacing(h, good.ctypes.data_as(P), hy.ctypes.data_as(P), None) == 0
+    inf = L.Info()
+    assert lib.dvm_get_info(h, C.byref(inf)) == 0
+    # FP64 with 8 nodes per x half: 4 per lane, 2x2 bricks, pipelined body
+    assert (inf.vel_per_lane, inf.brick[0], inf.brick[1], inf.pipelined) == (4, 2, 2, 1)
+    n = C.c_size_t()
+    assert lib.dvm_required_workspace(h, C.byref(n)) == 0
+    assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 16) == -3
+    lib.dvm_destroy(h)
