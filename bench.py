@@ -88,6 +88,18 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_byt
         "bytes_per_launch": (f * 1024.0 * ffac + w * 1024.0 * wfac) / max(1, nf),
         "read_bytes_per_launch": f * 1024.0 * ffac / max(1, nf),
         "write_bytes_per_launch": w * 1024.0 * wfac / max(1, nw),
+        "commands": [
+            "cd /tmp && export TMPDIR=/tmp",
+            "timeout -s KILL 100 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc/f -o f "
+            "-- python3 $R/bench.py --workload W --steps 1 --warmup 0 --no-cpu",
+            "timeout -s KILL 100 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc/w -o w "
+            "-- python3 $R/bench.py --workload W --steps 1 --warmup 0 --no-cpu",
+            "timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc/cf -o cf "
+            "-- python3 $R/bench.py --copy-calib 4   (and WRITE_SIZE into .../cw)",
+            "python bench.py --summarize-pmc <f csv> <w csv> <cf csv> <cw csv> 4294967296 LABEL",
+        ],
+        "note": "R = repository root; W = the workload of LABEL (one iteration = launches sweep launches); "
+                "factors = bytes of a 4 GiB device copy / counter KiB x 1024",
     }
     with open(out, "w") as fo:
         json.dump(rec, fo, indent=1)
