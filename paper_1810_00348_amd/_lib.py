@@ -14,6 +14,7 @@ import torch  # noqa: F401  (loads the HIP runtime before the library)
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdvm_hip.so")
 
 DVM_OK, DVM_NOT_CONVERGED = 0, 1
+DVM_ERR_ARG, DVM_ERR_STATE, DVM_ERR_OOM, DVM_ERR_DEVICE, DVM_ERR_NONPHYSICAL = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "DVM_OK", 1: "DVM_NOT_CONVERGED", -1: "DVM_ERR_ARG", -2: "DVM_ERR_STATE",
                 -3: "DVM_ERR_OOM", -4: "DVM_ERR_DEVICE", -5: "DVM_ERR_NONPHYSICAL"}
 DVM_F64, DVM_F32 = 0, 1
