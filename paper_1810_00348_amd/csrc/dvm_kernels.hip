@@ -185,7 +185,9 @@ __global__ __launch_bounds__(128) void params_kernel(Consts C, DevPtrs D, const 
     if (!(rho > 0.0) || !(T > 0.0) || !isfinite(Ux) || !isfinite(Uy) || !isfinite(Uz) ||
         !isfinite(T)) {
         atomicOr(flag, 1);
-        for (int k = 0; k < PSTRIDE; ++k) P[k] = (S)0;
+        // neutral equilibrium parameters; the info word, inverse sizes and
+        // inflow densities written above stay
+        for (int k = 0; k < P_INFO; ++k) P[k] = (S)0;
         P[P_NU] = (S)1;
         for (int k = 0; k < C.MT; ++k) E[k] = (S)0;
         return;
