@@ -907,8 +907,17 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     S eb_n = (S)0, ec_n = (S)0, ex_n[VL], fx_n[VL], fy_n[VL];
 #pragma unroll
     for (int v = 0; v < VL; ++v) ex_n[v] = fx_n[v] = fy_n[v] = (S)0;
+    // the next cell's record is read one cell ahead as well: its info word
+    // and 1/tau (which also bring the record's first cache lines into the
+    // scalar cache for the rest of its loads)
+    S nu_n = (S)1;
+    uint32_t info_n = 0;
     auto prefetch = [&](int ii, int jj, int kk) {
-        const S* E = etab + (size_t)(cell0 + ii * si + jj * sj + kk * sk) * MT;
+        const int cn = cell0 + ii * si + jj * sj + kk * sk;
+        const S* Pn = params + (size_t)cn * PSTRIDE;
+        nu_n = Pn[P_NU];
+        info_n = reinterpret_cast<const uint32_t*>(Pn + P_INFO)[0];
+        const S* E = etab + (size_t)cn * MT;
         eb_n = ldb(E, ob);
         ec_n = ldb(E, oc);
 #pragma unroll
@@ -932,7 +941,8 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 #pragma unroll
     for (int v = 0; v < VL; ++v) prev[v] = (S)0;
     for (int n = 0; n < ncell; ++n) {
-        const S eb = eb_n, ec = ec_n;
+        const S eb = eb_n, ec = ec_n, nu = nu_n;
+        const uint32_t info = info_n;
         S ex[VL], fxp[VL], fyp[VL];
 #pragma unroll
         for (int v = 0; v < VL; ++v) {
@@ -952,7 +962,6 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 
         const int cell = cell0 + ii * si + jj * sj + kk * sk;
         const S* P = params + (size_t)cell * PSTRIDE;
-        const uint32_t info = reinterpret_cast<const uint32_t*>(P + P_INFO)[0];
         if (!(info & SOLID_BIT)) {
             S fx[VL], fy[VL], fz[VL];
             {
@@ -1003,7 +1012,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 }
             }
 
-            const S nu = P[P_NU], Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
+            const S Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
             const S L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
             const S qx = P[P_QX], qy = P[P_QY], qz = P[P_QZ], tT = P[P_TWO_T];
             const S gyz = eb * ec;
