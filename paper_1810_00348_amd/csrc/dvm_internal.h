@@ -9,6 +9,10 @@
 namespace dvm {
 
 constexpr int NMOM = 13;     // raw velocity moments accumulated per cell
+// stride of a partial record: 16 doubles = one 128-byte cache line, written
+// whole by one store (the 3 slots past the moments take the reduction's
+// unused sums), so that no line of the partials is ever partially written
+constexpr int PREC = 16;
 constexpr int PSTRIDE = 24;  // per-cell parameter slots
 constexpr int MAXM = 512;    // velocity nodes per axis (upper bound)
 constexpr int NKIND = 7;     // emission kinds: 6 box faces + the solid body
@@ -75,7 +79,7 @@ struct SweepArgs {
     S* yface;
     S* zface;
     S* spec;
-    double* partial;      // [8*ntiles][N][NMOM]
+    double* partial;      // [8*ntiles][N][PREC]
     int nx, ny, nz, N, mx, my, MT, NV;
     int nbx, nby, nbz, bz;
     int ntiles, slots, lstride;

@@ -638,9 +638,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
     const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
     const int shX = 4 * sideX, shY = 4 * sideY, shZ = 4 * sideZ;
     const int ridx = reduce13_index(lane);
-    const bool writer = ((lane & 3) == 0) && ridx < NMOM;
+    const bool writer = (lane & 3) == 0;  // one lane per slot 0..15 of the record
     const unsigned oridx = (unsigned)ridx * 8u;
-    double* part = partial + ((size_t)(o * A.ntiles + tile) * A.N) * NMOM;
+    double* part = partial + ((size_t)(o * A.ntiles + tile) * A.N) * PREC;
 
     for (int kk = 0; kk < kend; ++kk) {
         const int kcell = cell0 + kk * sk;
@@ -797,7 +797,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 m[11] = xiy_d * t2;
                 m[12] = xiz_d * t2;
                 const double tot = wave_reduce13(m);
-                if (writer) stb(part + (size_t)cell * NMOM, oridx, tot);
+                if (writer) stb(part + (size_t)cell * PREC, oridx, tot);
             }
         }
     }
@@ -889,9 +889,9 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
     const int shX = 4 * sideX, shY = 4 * sideY, shZ = 4 * sideZ;
     const int ridx = reduce13_index(lane);
-    const bool writer = ((lane & 3) == 0) && ridx < NMOM;
+    const bool writer = (lane & 3) == 0;  // one lane per slot 0..15 of the record
     const unsigned oridx = (unsigned)ridx * 8u;
-    double* part = partial + ((size_t)(o * A.ntiles + tile) * A.N) * NMOM;
+    double* part = partial + ((size_t)(o * A.ntiles + tile) * A.N) * PREC;
 
     // ---- the first plane's z inflow: the upwind brick's outflow face
     if (kr0 > 0) {
@@ -1089,7 +1089,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             m[11] = xiy_d * t2;
             m[12] = xiz_d * t2;
             const double tot = wave_reduce13(m);
-            if (writer) stb(part + (size_t)cell * NMOM, oridx, tot);
+            if (writer) stb(part + (size_t)cell * PREC, oridx, tot);
         }
         ii = ni;
         jj = nj;
@@ -1196,7 +1196,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, cons
             for (int o = 0; o < 8; ++o) {
                 double g1 = 0, g2 = 0, g3 = 0;
                 for (int t = 0; t < ntiles; ++t) {
-                    const double* p = partial + ((size_t)(o * ntiles + t) * N + cell) * NMOM;
+                    const double* p = partial + ((size_t)(o * ntiles + t) * N + cell) * PREC;
 #pragma unroll
                     for (int k = 0; k < 13; ++k) m[k] += p[k];
                     g1 += p[1];

@@ -232,7 +232,7 @@ void layout(dvm_ctx* c)
     c->off.rw = take(sizeof(double) * 2 * 6 * N);
     c->off.params = take(S * PSTRIDE * N);
     c->off.etab = take(S * (size_t)(c->vg.m[0] + c->vg.m[1] + c->vg.m[2]) * N);
-    c->off.partial = take(sizeof(double) * NMOM * 8 * (size_t)c->ntiles * N);
+    c->off.partial = take(sizeof(double) * PREC * 8 * (size_t)c->ntiles * N);
     c->off.xface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.ny * fst);
     c->off.yface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.nx * fst);
     c->off.zface = take(S * 8 * 2 * (size_t)c->g.ny * c->g.nx * fst);
