@@ -554,6 +554,14 @@ __device__ __forceinline__ void stb(T* base, unsigned off, T v)
 {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
+// streaming store (non-temporal hint): the outflow faces and moment partials
+// are read back only by a later launch, so they should not displace the cell
+// tables and faces of the running launch from the caches
+template <typename T>
+__device__ __forceinline__ void stb_nt(T* base, unsigned off, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off));
+}
 
 template <typename S, int VL, int BX, int BY, bool NU>
 __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __restrict__ params,
@@ -762,22 +770,22 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 // ---- outflow faces for the downstream bricks
                 if (ii == BX - 1 && wx) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) stb(xrow_out, lofs + v * SB, prev[v]);
+                    for (int v = 0; v < VL; ++v) stb_nt(xrow_out, lofs + v * SB, prev[v]);
                 }
                 if (jj == BY - 1 && wy) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) stb(yout + ((size_t)kk * nx + ii) * fstride, lofs + v * SB, prev[v]);
+                    for (int v = 0; v < VL; ++v) stb_nt(yout + ((size_t)kk * nx + ii) * fstride, lofs + v * SB, prev[v]);
                 }
                 if (kk == A.bz - 1 && wz) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) stb(zout + ((size_t)jj * nx + ii) * fstride, lofs + v * SB, prev[v]);
+                    for (int v = 0; v < VL; ++v) stb_nt(zout + ((size_t)jj * nx + ii) * fstride, lofs + v * SB, prev[v]);
                 }
                 if (sbuf != nullptr && !pz && kr0 + kk == nz - 1) {
                     const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
                     const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
                     S* dst = sbuf + ((size_t)j * nx + i) * fstride;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+                    for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
                 }
 
                 // ---- 13 raw moments of this tile at this cell
@@ -797,7 +805,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 m[11] = xiy_d * t2;
                 m[12] = xiz_d * t2;
                 const double tot = wave_reduce13(m);
-                if (writer) stb(part + (size_t)cell * PREC, oridx, tot);
+                if (writer) stb_nt(part + (size_t)cell * PREC, oridx, tot);
             }
         }
     }
@@ -1053,24 +1061,24 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             if (ii == BX - 1 && wx) {
                 S* dst = xout + ((size_t)kk * ny + jj) * fstride;
 #pragma unroll
-                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
             }
             if (jj == BY - 1 && wy) {
                 S* dst = yout + ((size_t)kk * nx + ii) * fstride;
 #pragma unroll
-                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
             }
             if (kk == A.bz - 1 && wz) {
                 S* dst = zout + ((size_t)jj * nx + ii) * fstride;
 #pragma unroll
-                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
             }
             if (sbuf != nullptr && !pz && kr0 + kk == nz - 1) {
                 const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
                 const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
                 S* dst = sbuf + ((size_t)j * nx + i) * fstride;
 #pragma unroll
-                for (int v = 0; v < VL; ++v) stb(dst, lofs + v * SB, prev[v]);
+                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
             }
 
             double m[13];
@@ -1089,7 +1097,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             m[11] = xiy_d * t2;
             m[12] = xiz_d * t2;
             const double tot = wave_reduce13(m);
-            if (writer) stb(part + (size_t)cell * PREC, oridx, tot);
+            if (writer) stb_nt(part + (size_t)cell * PREC, oridx, tot);
         }
         ii = ni;
         jj = nj;
