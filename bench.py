@@ -127,7 +127,20 @@ def workload(name: str, kn: float):
         return cases.config("c3"), "f32"
     if name == "c4":
         return cases.config("c4"), "f32"
+    if name == "c6":
+        return cases.config("c6"), "f32"
     raise SystemExit(f"unknown workload {name}")
+
+
+def describe(name: str, case) -> str:
+    grid = f"{case.n[0]}x{case.n[1]}x{case.n[2]}"
+    vel = f"{case.m[0]}^3 velocities on [-{case.vmax[0]:g},{case.vmax[0]:g}]^3"
+    if name == "c4":
+        return f"{case.name}: cube half-domain {grid} cells x {vel}, Ma 5, Kn 0.1"
+    if name == "c6":
+        return (f"{case.name}: full-domain cube of the paper's Sec. 4.2, {grid} stretched cells x {vel}, "
+                f"Ma 2, Kn 1 ({case.points:.3g} points)")
+    return f"{case.name}: lid-driven cavity {grid} cells x {vel}, Kn={case.kn:g}, lid {case.faces[3].u[0]:g}"
 
 
 def cpu_baseline(case, budget_s: float = 25.0):
@@ -291,12 +304,8 @@ def main():
         "dtype": prec,
         "data": "synthetic",
         "config": {
-            "workload": (f"{case.name}: lid-driven cavity {case.n[0]}x{case.n[1]}x{case.n[2]} cells x "
-                         f"{case.m[0]}^3 velocities on [-{case.vmax[0]:g},{case.vmax[0]:g}]^3, "
-                         f"Kn={case.kn:g}, lid {case.faces[3].u[0]:g}"
-                         if args.workload != "c4" else
-                         f"{case.name}: cube half-domain {case.n[0]}x{case.n[1]}x{case.n[2]} cells x "
-                         f"{case.m[0]}^3 velocities on [-{case.vmax[0]:g},{case.vmax[0]:g}]^3, Ma 5, Kn 0.1"),
+            "workload": describe(args.workload, case),
+            "velocity_groups": info["velocity_groups"],
             "points_per_iteration": pts,
             "brick": info["brick"],
             "vel_per_lane": info["vel_per_lane"],
@@ -325,7 +334,7 @@ def main():
             "traffic_label": label,
         },
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload != "c6":
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)
 

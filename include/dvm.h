@@ -99,6 +99,7 @@ typedef struct {
     int sweep_launches;         /* sweep kernel launches per iteration            */
     size_t workspace_bytes;
     int pipelined;              /* 1: software-pipelined sweep body, 0: plain     */
+    int velocity_groups;        /* velocity groups swept one after another        */
 } dvm_info;
 
 /* Create a context.  precision: DVM_F64 or DVM_F32 (storage and update type of
@@ -132,6 +133,21 @@ dvm_status dvm_set_closed(dvm_ctx* ctx, int closed);
    total mass.  Before binding the workspace; DVM_ERR_STATE after it,
    DVM_ERR_ARG for bad sizes. */
 dvm_status dvm_set_spacing(dvm_ctx* ctx, const double* hx, const double* hy, const double* hz);
+
+/* Sweep the velocity set in `groups` parts, one after another, within each
+   iteration: each octant's 64-lane velocity tiles are split into `groups`
+   consecutive ranges of (nearly) equal size (at most one range per tile).
+   The sweep of one velocity does not depend on the others within an
+   iteration (the equilibrium and the wall densities come from the previous
+   iterate, Sec. 2.2 and 3.4), so the result is that of one group up to the
+   order of the FP64 moment sums.  The face buffers, the mirror planes of a
+   specular side and the per-tile moment partials then hold one range only,
+   which divides the workspace (dominated by them on large grids) by about
+   `groups`; an FP64 accumulator of 8 x 16 doubles per cell is added when
+   groups > 1.  This is how the largest meshes of Sec. 4.2 (181 x 181 x 191
+   cells, 48^3 velocities) fit one device.  Before binding the workspace;
+   DVM_ERR_STATE after it, DVM_ERR_ARG for groups < 1. */
+dvm_status dvm_set_velocity_groups(dvm_ctx* ctx, int groups);
 
 /* Bytes of device workspace the context needs with its current settings. */
 dvm_status dvm_required_workspace(dvm_ctx* ctx, size_t* bytes);

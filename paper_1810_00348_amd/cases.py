@@ -17,6 +17,8 @@ Workloads (all synthetic; the paper's DSMC data and figures are not used):
 * ``cube``: supersonic flow past a cube (Sec. 4.2), re-parameterised as a
   symmetry half-domain: specular plane at z = 0, free stream on the other
   five faces, a diffuse cube wall.
+* ``cube_paper``: the paper's own full-domain cube run (stretched
+  191 x 181 x 181 mesh, 48^3 velocities, Ma 2, Kn 1).
 """
 from __future__ import annotations
 
@@ -166,6 +168,63 @@ def cube_full_mirror(half: Case) -> Case:
                                faces=faces)
 
 
+def graded_segment(length: float, n: int, h0: float) -> np.ndarray:
+    """n cell sizes h0 r, h0 r^2, ..., h0 r^n (growing away from a cell of
+    size h0) with the ratio r chosen so that they sum to ``length``."""
+    if n < 1 or not (length > 0 and h0 > 0):
+        raise ValueError("need n >= 1 cells, a positive length and a positive h0")
+    k = np.arange(1, n + 1, dtype=np.float64)
+    lo, hi = 0.25, 4.0
+    for _ in range(200):
+        r = 0.5 * (lo + hi)
+        if h0 * np.sum(r ** k) > length:
+            hi = r
+        else:
+            lo = r
+    h = h0 * r ** k
+    return h * (length / h.sum())
+
+
+def body_fitted_axis(n_body: int, body_len: float, before: float, n_before: int, after: float,
+                     n_after: int) -> np.ndarray:
+    """Cell sizes along one axis of a mesh around a body: n_body equal cells
+    across the body, graded geometrically away from it on both sides
+    (``before`` / ``after``: lengths of the two sides)."""
+    h0 = body_len / n_body
+    return np.concatenate([graded_segment(before, n_before, h0)[::-1], np.full(n_body, h0),
+                           graded_segment(after, n_after, h0)])
+
+
+def cube_paper(n_body: int = 31, n_side: int = 75, n_front: int = 65, n_rear: int = 95,
+               m: int = 48, vmax: float = 4.0, mach: float = 2.0, kn: float = 1.0,
+               front: float = 4.5, rear: float = 8.5, side: float = 5.5,
+               name: Optional[str] = None) -> Case:
+    """The full-domain cube of Sec. 4.2: a unit cube in a 14 x 12 x 12 box,
+    free stream at Mach ``mach`` along +x on all six faces, a diffuse cube
+    wall at the free-stream temperature, 48^3 velocities on [-4, 4]^3 (units
+    of sqrt(2 R T_wall)).  Mesh: ``n_body`` equal cells across the cube and
+    cells growing geometrically away from it -- ``n_side`` cells over the
+    ``side`` length on each lateral side, ``n_front`` over the ``front``
+    length upstream and ``n_rear`` over the ``rear`` length downstream.  The
+    defaults give 191 x 181 x 181 cells with growth ratios of about 1.02 in
+    every direction (the paper's faster growth downstream, 1.03, would leave
+    fewer than its 191 cells along x over this length)."""
+    hx = body_fitted_axis(n_body, 1.0, front, n_front, rear, n_rear)
+    hy = body_fitted_axis(n_body, 1.0, side, n_side, side, n_side)
+    hz = hy.copy()
+    nx, ny, nz = hx.size, hy.size, hz.size
+    u_inf = mach * math.sqrt(5.0 / 6.0)
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    solid[n_side:n_side + n_body, n_side:n_side + n_body, n_front:n_front + n_body] = 1
+    free = Face("free", u=(u_inf, 0.0, 0.0), T=1.0, rho=1.0)
+    return Case(name=name or f"cube_full_{nx}x{ny}x{nz}_v{m}",
+                n=(nx, ny, nz), L=(float(hx.sum()), float(hy.sum()), float(hz.sum())),
+                m=(m, m, m), vmax=(vmax, vmax, vmax), kn=kn,
+                faces=[dataclasses.replace(free) for _ in range(6)], closed=False,
+                solid=solid, solid_u=(0.0, 0.0, 0.0), solid_T=1.0,
+                init_rho=1.0, init_u=(u_inf, 0.0, 0.0), init_T=1.0, spacing=(hx, hy, hz))
+
+
 # ---- the configurations the benchmark and the parity tests use ------------
 
 def config(name: str, **kw) -> Case:
@@ -176,6 +235,9 @@ def config(name: str, **kw) -> Case:
     c3: cavity 96^3 x 28^3, Kn=0.5, lid 0.3 (FP32 storage form)
     c4: cube half-domain 64x48x48 cells, 48^3 velocities on [-12,12]^3,
         Ma=5, Kn=0.1 (FP32 storage form)
+    c6: the full-domain cube of Sec. 4.2, 191x181x181 stretched cells x 48^3
+        velocities on [-4,4]^3, Ma=2, Kn=1 (6.9e11 points; FP32 storage
+        form, velocity groups to fit one device)
     """
     if name == "c1":
         return cavity(16, 12, kn=kw.get("kn", 1.0), lid=0.16, vmax=5.0, name="c1_cavity_16^3_v12^3")
@@ -187,6 +249,8 @@ def config(name: str, **kw) -> Case:
     if name == "c4":
         return cube_half(64, 48, 48, edge=8, x0=16, m=48, vmax=12.0, mach=5.0, kn=0.1,
                          name="c4_cube_half_64x48x48_v48^3")
+    if name == "c6":
+        return cube_paper(name="c6_cube_full_191x181x181_v48^3")
     raise KeyError(name)
 
 

@@ -111,6 +111,8 @@ hipError_t launch_scale_residual(const Consts& C, const DevPtrs& D, double M0,
                                  hipStream_t st);
 hipError_t launch_residual_final(const double* respart, int nblocks, const double* blockmass,
                                  int nbm, double* out, const int* flag, hipStream_t st);
+// acc[o][cell] (= or +=) sum over the ntiles records partial[o*ntiles + t][cell]
+hipError_t launch_fold(const double* partial, int ntiles, int N, int add, double* acc, hipStream_t st);
 hipError_t launch_selftest_reduce(const double* in, double* out, hipStream_t st);
 bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform);
 

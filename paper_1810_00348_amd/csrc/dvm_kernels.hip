@@ -1265,6 +1265,32 @@ hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* part
     return hipGetLastError();
 }
 
+// Velocity groups: the records of one group's tiles summed per octant and
+// cell, in tile order, into the accumulator that finalize reads as a single
+// tile.  One thread per (octant, cell, record slot): a 16-thread group reads
+// one 128-byte record line.
+__global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ partial, int ntiles, int N,
+                                                   int add, double* __restrict__ acc)
+{
+    const size_t n = (size_t)8 * N * PREC;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t rec = i / PREC;  // o * N + cell
+    const int k = (int)(i % PREC);
+    const size_t o = rec / N, cell = rec % N;
+    double s = add ? acc[i] : 0.0;
+    for (int t = 0; t < ntiles; ++t) s += partial[((o * ntiles + t) * N + cell) * PREC + k];
+    acc[i] = s;
+}
+
+hipError_t launch_fold(const double* partial, int ntiles, int N, int add, double* acc, hipStream_t st)
+{
+    const size_t n = (size_t)8 * N * PREC;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    fold_kernel<<<nb, 256, 0, st>>>(partial, ntiles, N, add, acc);
+    return hipGetLastError();
+}
+
 // deterministic block sum of n values (fixed strided order + fixed tree)
 __device__ double block_sum_fixed(const double* x, int n, double* red)
 {

@@ -79,6 +79,11 @@ struct dvm_ctx {
     bool nonuniform = false;
     int nbx = 0, nby = 0, nbz = 0;
     int ntiles = 0, slots = 0, lstride = 0;
+    // velocity groups: each octant's tiles split into ngroups consecutive
+    // ranges, swept one after another (faces, mirror planes and partials
+    // sized for one range; the moments folded into acc between ranges)
+    int groups_req = 1, ngroups = 1, gtiles = 0;
+    std::vector<int> gt0;  // first tile of each group, plus ntiles at the end
     std::vector<int> bricks;           // I, J, K, 0 per brick, grouped by diagonal
     std::vector<int> diag_off, diag_cnt;
     int ndiag = 0;
@@ -90,7 +95,7 @@ struct dvm_ctx {
     bool bound = false;
     struct {
         size_t axes, spacing, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
-            partial, xface, yface, zface, spec, blockmass, respart, out, flag, end;
+            partial, acc, xface, yface, zface, spec, blockmass, respart, out, flag, end;
     } off;
     size_t Ssz = 8;
     int nbF = 0;  // blocks of the per-cell kernels (256 threads)
@@ -174,6 +179,11 @@ void derive_schedule(dvm_ctx* c)
     }
     c->ntiles = nt;
     c->slots = nt * 64;
+    c->ngroups = std::max(1, std::min(c->groups_req, nt));
+    c->gt0.assign(c->ngroups + 1, 0);
+    c->gtiles = 0;
+    for (int g = 0; g <= c->ngroups; ++g) c->gt0[g] = (int)((long long)nt * g / c->ngroups);
+    for (int g = 0; g < c->ngroups; ++g) c->gtiles = std::max(c->gtiles, c->gt0[g + 1] - c->gt0[g]);
     c->lstride = LT_SHARED + LT_PER_V * c->VL;
     if (c->lstride & 1) c->lstride++;
 
@@ -217,7 +227,8 @@ void layout(dvm_ctx* c)
         return at;
     };
     const size_t N = (size_t)c->N, S = c->Ssz;
-    const size_t fst = (size_t)c->slots * c->VL;
+    // faces, mirror planes and partials hold one velocity group
+    const size_t fst = (size_t)c->gtiles * 64 * c->VL;
     c->off.axes = take(sizeof(double) * 2 * 3 * MAXM);
     c->off.spacing = take(sizeof(double) * (size_t)(c->g.nx + c->g.ny + c->g.nz));
     c->off.cellinfo = take(sizeof(uint32_t) * N);
@@ -232,7 +243,8 @@ void layout(dvm_ctx* c)
     c->off.rw = take(sizeof(double) * 2 * 6 * N);
     c->off.params = take(S * PSTRIDE * N);
     c->off.etab = take(S * (size_t)(c->vg.m[0] + c->vg.m[1] + c->vg.m[2]) * N);
-    c->off.partial = take(sizeof(double) * PREC * 8 * (size_t)c->ntiles * N);
+    c->off.partial = take(sizeof(double) * PREC * 8 * (size_t)c->gtiles * N);
+    c->off.acc = take(c->ngroups > 1 ? sizeof(double) * PREC * 8 * N : 0);
     c->off.xface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.ny * fst);
     c->off.yface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.nx * fst);
     c->off.zface = take(S * 8 * 2 * (size_t)c->g.ny * c->g.nx * fst);
@@ -328,6 +340,8 @@ void build_cellinfo(dvm_ctx* c)
 
 std::vector<double> build_lanetab(const dvm_ctx* c, const std::vector<double> xi[3])
 {
+    // grouped layout: group g holds [8][its slots][lstride], the groups in
+    // order (one group: [8][slots][lstride])
     std::vector<double> lt((size_t)8 * c->slots * c->lstride, 0.0);
     for (int o = 0; o < 8; ++o) {
         int na[3];
@@ -347,7 +361,10 @@ std::vector<double> build_lanetab(const dvm_ctx* c, const std::vector<double> xi
             return (a == 0 || a == M - 1) ? 0.5 * h : h;
         };
         for (int s = 0; s < c->slots; ++s) {
-            double* L = &lt[((size_t)o * c->slots + s) * c->lstride];
+            int grp = 0;
+            while (s >= 64 * c->gt0[grp + 1]) ++grp;
+            const int s0 = 64 * c->gt0[grp], gs = 64 * c->gt0[grp + 1] - s0;
+            double* L = &lt[((size_t)8 * s0 + (size_t)o * gs + (s - s0)) * c->lstride];
             const bool lane_on = s < lanes && na[1] > 0 && na[2] > 0 && na[0] > 0;
             const int ss = lane_on ? s : 0;
             int g = 0, bl = 0, cl = 0;
@@ -409,8 +426,12 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
 
     // sweep: one launch per brick diagonal; with a specular plane the
     // octants moving towards it go first so that the others can read their
-    // mirror images
+    // mirror images.  Velocity groups are swept one after another, each
+    // group's moments folded into the accumulator before the next reuses the
+    // faces and partials.
     const int phases = c->spec_on ? 2 : 1;
+    for (int grp = 0; grp < c->ngroups; ++grp) {
+    const int t0 = c->gt0[grp], gnt = c->gt0[grp + 1] - t0;
     for (int ph = 0; ph < phases; ++ph) {
         for (int T = 0; T < c->ndiag; ++T) {
             const int cnt = c->diag_cnt[T];
@@ -421,7 +442,7 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.etab = c->P<S>(c->off.etab);
                 a.cellinfo = c->P<uint32_t>(c->off.cellinfo);
                 a.ghat = c->P<S>(c->off.ghat);
-                a.lanetab = c->P<double>(c->off.lanetab);
+                a.lanetab = c->P<double>(c->off.lanetab) + (size_t)8 * 64 * t0 * c->lstride;
                 a.bricks = c->P<int>(c->off.bricks);
                 a.xface = c->P<S>(c->off.xface);
                 a.yface = c->P<S>(c->off.yface);
@@ -431,13 +452,13 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.N = c->N;
                 a.mx = c->vg.m[0]; a.my = c->vg.m[1]; a.MT = C.MT; a.NV = c->NV;
                 a.nbx = c->nbx; a.nby = c->nby; a.nbz = c->nbz; a.bz = c->BZ;
-                a.ntiles = c->ntiles; a.slots = c->slots; a.lstride = c->lstride;
+                a.ntiles = gnt; a.slots = gnt * 64; a.lstride = c->lstride;
                 a.brick_off = c->diag_off[T]; a.brick_cnt = cnt;
                 a.oct_base = c->spec_on ? 4 * ph : 0;
                 a.noct = c->spec_on ? 4 : 8;
                 a.spec_on = c->spec_on ? 1 : 0;
                 a.has_solid = c->nfluid < c->N ? 1 : 0;
-                a.nblocks = a.noct * cnt * c->ntiles;
+                a.nblocks = a.noct * cnt * gnt;
             };
             hipError_t e;
             if (c->prec == DVM_F64) {
@@ -452,12 +473,17 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
             if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
         }
     }
+    if (c->ngroups > 1)
+        HIPCHK(launch_fold(c->P<double>(c->off.partial), gnt, c->N, grp > 0, c->P<double>(c->off.acc), st));
+    }
     if (c->timing) HIPCHK(hipEventRecord(c->ev[2], st));
 
     double* blockmass = c->P<double>(c->off.blockmass);
     double* respart = c->P<double>(c->off.respart);
     double* out = c->P<double>(c->off.out);
-    HIPCHK(launch_finalize(C, D, c->P<double>(c->off.partial), c->ntiles, c->P<double>(c->off.gout),
+    const bool folded = c->ngroups > 1;
+    HIPCHK(launch_finalize(C, D, c->P<double>(folded ? c->off.acc : c->off.partial), folded ? 1 : c->ntiles,
+                           c->P<double>(c->off.gout),
                            W + nxt * 5 * N, q + nxt * 3 * N, rw + nxt * 6 * N, blockmass, c->nbF, flag,
                            st));
     HIPCHK(launch_scale_residual(C, D, c->M0, blockmass, c->nbF, W + nxt * 5 * N, q + nxt * 3 * N,
@@ -607,6 +633,16 @@ dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const
         }
     }
     c->nonuniform = any;
+    derive_schedule(c);
+    return DVM_OK;
+}
+
+dvm_status dvm_set_velocity_groups(dvm_ctx* c, int groups)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "velocity groups must be set before binding the workspace");
+    if (groups < 1) return fail(DVM_ERR_ARG, "groups must be >= 1 (got %d)", groups);
+    c->groups_req = groups;
     derive_schedule(c);
     return DVM_OK;
 }
@@ -861,9 +897,10 @@ dvm_status dvm_get_info(dvm_ctx* c, dvm_info* info)
     info->tiles_per_octant = c->ntiles;
     int launches = 0;
     for (int T = 0; T < c->ndiag; ++T) launches += c->diag_cnt[T] > 0;
-    info->sweep_launches = launches * (c->spec_on ? 2 : 1);
+    info->sweep_launches = launches * (c->spec_on ? 2 : 1) * c->ngroups;
     info->workspace_bytes = c->off.end;
     info->pipelined = c->PF;
+    info->velocity_groups = c->ngroups;
     return DVM_OK;
 }
 

@@ -24,7 +24,11 @@ class Solver:
     """
 
     def __init__(self, case: Case, precision: str = "f64", device: str = "cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, velocity_groups: Optional[int] = None,
+                 memory_fraction: float = 0.9):
+        """velocity_groups: sweep the velocity set in that many parts per
+        iteration (None: the fewest parts whose workspace fits
+        memory_fraction of the device's free memory)."""
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
         self.case = case
@@ -52,7 +56,19 @@ class Solver:
             self._spacing = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in case.spacing]
             L.check(lib.dvm_set_spacing(h, *[None if a is None else _ptr(a) for a in self._spacing]))
         nbytes = C.c_size_t()
+        groups = 1 if velocity_groups is None else int(velocity_groups)
+        L.check(lib.dvm_set_velocity_groups(h, groups))
         L.check(lib.dvm_required_workspace(h, C.byref(nbytes)))
+        if velocity_groups is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            # memory torch holds in its cache is free for this allocation too
+            free += torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+            info = L.Info()
+            L.check(lib.dvm_get_info(h, C.byref(info)))
+            while nbytes.value > memory_fraction * free and groups < info.tiles_per_octant:
+                groups += 1
+                L.check(lib.dvm_set_velocity_groups(h, groups))
+                L.check(lib.dvm_required_workspace(h, C.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         with torch.cuda.device(self.device):
             L.check(lib.dvm_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value))
@@ -118,7 +134,8 @@ class Solver:
                 "nvel": inf.nvel, "precision": inf.precision, "brick": list(inf.brick),
                 "vel_per_lane": inf.vel_per_lane, "tiles_per_octant": inf.tiles_per_octant,
                 "sweep_launches": inf.sweep_launches, "workspace_bytes": inf.workspace_bytes,
-                "sweep_kernel": "sweep_kernel_pf" if inf.pipelined else "sweep_kernel"}
+                "sweep_kernel": "sweep_kernel_pf" if inf.pipelined else "sweep_kernel",
+                "velocity_groups": inf.velocity_groups}
 
     def set_timing(self, enable: bool = True):
         L.check(L.lib().dvm_set_timing(self._h, int(enable)))

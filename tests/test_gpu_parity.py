@@ -37,9 +37,9 @@ def field_errors(g, r):
     return out
 
 
-def run_pair(case, iters, oracle_mod, precision="f64", init=None):
+def run_pair(case, iters, oracle_mod, precision="f64", init=None, groups=1):
     Solver = _solver()
-    s = Solver(case, precision=precision)
+    s = Solver(case, precision=precision, velocity_groups=groups)
     o = oracle_mod.Oracle(case)
     if init is None:
         s.init_uniform(); o.init_uniform()
@@ -232,3 +232,84 @@ def test_stretched_mesh_fp32_and_mass(oracle_mod):
     vol = (hz[:, None, None] * hy[None, :, None] * hx[None, None, :]).ravel()
     W, _, _, M0 = s.state()
     assert abs((W[0] * vol).sum() - M0) <= 1e-12 * M0
+
+
+def _group_cases():
+    a = cases.cavity((9, 8, 7), 24, kn=0.5, lid=0.3, vmax=5.0)          # 7 tiles per octant (FP64)
+    b = cases.cube_half(nx=12, ny=10, nz=6, edge=4, x0=4, m=20, vmax=6.0, mach=2.0, kn=0.5)  # specular
+    c = cases.cube_paper(n_body=3, n_side=4, n_front=3, n_rear=5, m=18, front=1.5, rear=2.5, side=1.5)
+    return {"cavity": a, "cube_half": b, "cube_paper_small": c}
+
+
+@pytest.mark.parametrize("name,groups", [("cavity", 2), ("cavity", 3), ("cavity", 7), ("cavity", 50),
+                                         ("cube_half", 3), ("cube_paper_small", 2)])
+def test_velocity_groups_match_oracle(oracle_mod, name, groups):
+    """The velocity set swept in consecutive groups (faces, mirror planes and
+    partials sized for one group, moments folded between groups) gives the
+    oracle's iterate (FP64); with more groups than tiles every tile is a
+    group."""
+    case = _group_cases()[name]
+    init = cases.random_fields(case, seed=33) if name == "cavity" else None
+    s, o = run_pair(case, 3, oracle_mod, init=init, groups=groups)
+    info = s.info()
+    assert info["velocity_groups"] == min(groups, info["tiles_per_octant"]) > 1, info
+    err = field_errors(s.fields(), o.fields())
+    print(name, groups, err, info)
+    for k in ("rho", "ux", "uy", "uz", "T", "qx", "qy"):
+        assert err[k] <= FP64_TOL, (k, err)
+    rg, ro = s.residual(per_field=True), o.residual(per_field=True)
+    assert np.abs(rg - ro).max() <= 1e-8 * ro.max()
+
+
+def test_velocity_groups_fp32_match_one_group():
+    """FP32 storage: grouped and ungrouped sweeps compute every f value in
+    the same order; only the FP64 moment sums are ordered differently."""
+    Solver = _solver()
+    case = _group_cases()["cube_paper_small"]
+    for iters, tol in ((1, 1e-13), (3, 1e-5)):
+        out = []
+        for groups in (1, 3):
+            s = Solver(case, precision="f32", velocity_groups=groups)
+            s.init_uniform()
+            s.iterate(iters)
+            out.append(s.fields())
+        err = field_errors(out[1], out[0])
+        print(iters, err)
+        # after the first iteration the FP32 parameters may round differently
+        for k in ("rho", "ux", "uy", "uz", "T"):
+            assert err[k] <= tol, (iters, k, err)
+
+
+def test_paper_cube_full_size_is_mirror_symmetric():
+    """The paper's full-domain cube (191 x 181 x 181 stretched cells, 48^3
+    velocities, 6.9e11 points, FP32 storage, velocity groups chosen to fit
+    the device) at its real size: two iterations from the free stream stay
+    finite, keep the free-stream inflow and are mirror-symmetric in y and z
+    and symmetric under y <-> z, as the mesh, the body and the inflow are."""
+    Solver = _solver()
+    case = cases.config("c6")
+    s = Solver(case, precision="f32")
+    info = s.info()
+    print(info, flush=True)
+    s.init_uniform()
+    s.iterate(2)
+    f = s.fields()
+    nx, ny, nz = case.n
+    solid = case.solid.astype(bool)
+    for name, arr in (("rho", f["rho"]), ("T", f["T"]), ("ux", f["u"][0]), ("uy", f["u"][1]), ("uz", f["u"][2])):
+        a = arr.reshape(nz, ny, nx)
+        assert np.isfinite(a[~solid]).all(), name
+        scale = np.abs(a[~solid]).max()
+        sign_y = -1.0 if name == "uy" else 1.0
+        sign_z = -1.0 if name == "uz" else 1.0
+        assert np.abs(a - sign_y * a[:, ::-1, :]).max() <= 2e-5 * scale, name
+        assert np.abs(a - sign_z * a[::-1, :, :]).max() <= 2e-5 * scale, name
+    ux, uy, uz = (f["u"][d].reshape(nz, ny, nx) for d in range(3))
+    rho = f["rho"].reshape(nz, ny, nx)
+    # y <-> z exchange: rho(z, y) = rho(y, z), u_y(z, y) = u_z(y, z)
+    assert np.abs(rho - rho.transpose(1, 0, 2)).max() <= 2e-5 * rho.max()
+    assert np.abs(uy - uz.transpose(1, 0, 2)).max() <= 2e-5 * np.abs(ux).max()
+    # upstream of the bow region the gas is still close to the free stream
+    assert abs(rho[90, 90, 0] - 1.0) < 0.1 and abs(ux[90, 90, 0] - case.init_u[0]) < 0.1
+    # the stagnation region in front of the cube is compressed
+    assert rho[90, 90, case.solid[90, 90].argmax() - 1] > 1.2

@@ -232,6 +232,29 @@ def test_stretched_axis_sizes():
     assert abs(g.sum() - 1.0) < 1e-14 and np.argmin(g) in (2, 3)
 
 
+def test_paper_cube_mesh():
+    """The full-domain cube of Sec. 4.2: 191 x 181 x 181 cells over a
+    14 x 12 x 12 box, equal cells across the unit cube, geometric growth
+    about 1.02 in every direction; the mesh and body
+    are mirror-symmetric in y and z; 0.69e12 phase-space points."""
+    c = cases.config("c6")
+    hx, hy, hz = c.spacing
+    assert c.n == (191, 181, 181) and c.m == (48, 48, 48) and c.vmax == (4.0, 4.0, 4.0)
+    assert abs(hx.sum() - 14.0) < 1e-12 and abs(hy.sum() - 12.0) < 1e-12
+    assert np.array_equal(hy, hy[::-1]) and np.array_equal(hy, hz)
+    assert np.allclose(hx[65:96], 1 / 31) and np.allclose(hy[75:106], 1 / 31)
+    assert abs(hx[65:96].sum() - 1.0) < 1e-12
+    ry = hy[:74] / hy[1:75]
+    assert np.allclose(ry, ry[0]) and abs(ry[0] - 1.02) < 0.002
+    assert abs(hx[63] / hx[64] - 1.02) < 0.002 and abs(hx[97] / hx[96] - 1.02) < 0.002
+    solid = c.solid.astype(bool)
+    assert solid.sum() == 31 ** 3 and solid[75:106, 75:106, 65:96].all()
+    assert np.array_equal(solid, solid[::-1]) and np.array_equal(solid, solid[:, ::-1])
+    assert 0.68e12 < c.points < 0.7e12
+    e = cases.graded_segment(3.0, 10, 0.1)
+    assert abs(e.sum() - 3.0) < 1e-12 and np.allclose(e[1:] / e[:-1], e[1] / e[0]) and e[0] > 0.1
+
+
 # ------------------------------------------------------------- invariants
 
 def test_uniform_rest_equilibrium_is_a_fixed_point(oracle_mod):
