@@ -169,6 +169,42 @@ def cpu_baseline(case, budget_s: float = 25.0):
     }
 
 
+def solve(case, prec, max_iters, tol, desc):
+    """Iterate from the uniform start, printing the residual of every
+    iteration; one JSON line with the totals and a few field values."""
+    import numpy as np
+    import torch
+    from paper_1810_00348_amd.solver import Solver
+    t0 = time.perf_counter()
+    s = Solver(case, precision=prec)
+    s.init_uniform()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    hist = []
+    t1 = time.perf_counter()
+    for it in range(1, max_iters + 1):
+        _, r, _ = s.iterate(1)
+        hist.append(r)
+        print(f"iter {it} residual {r:.4e} elapsed {time.perf_counter() - t1:.2f} s", file=sys.stderr, flush=True)
+        if tol > 0 and r <= tol:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    f = s.fields()
+    nx, ny, nz = case.n
+    rho = f["rho"].reshape(nz, ny, nx)
+    T = f["T"].reshape(nz, ny, nx)
+    fluid = ~case.solid.astype(bool) if case.solid is not None else np.ones_like(rho, bool)
+    out = {"workload": desc, "precision": prec, "velocity_groups": s.info()["velocity_groups"],
+           "workspace_GiB": round(s.info()["workspace_bytes"] / 2 ** 30, 1),
+           "setup_seconds": round(t_setup, 2), "iterations": len(hist), "seconds": round(dt, 2),
+           "s_per_iter": round(dt / len(hist), 4), "GPt_per_s": round(case.points * len(hist) / dt / 1e9, 1),
+           "residual_history": [float(f"{x:.4e}") for x in hist],
+           "fields": {"rho_max": float(rho[fluid].max()), "T_max": float(T[fluid].max()),
+                      "rho_min": float(rho[fluid].min())}}
+    print(json.dumps(out), flush=True)
+
+
 def time_to_residual(workloads, tol=1e-6, max_iters=3000):
     """Wall time to the residual tolerance from the uniform start (the full
     dvm_iterate loop including its per-iteration residual read-back): FP64
@@ -217,6 +253,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic", default=None)
     ap.add_argument("--time-to-residual", action="store_true")
+    ap.add_argument("--solve", type=int, default=0, metavar="ITERS",
+                    help="solve the workload from the uniform start for up to ITERS iterations "
+                         "(or to --tol), one progress line per iteration")
+    ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--stretch", type=float, default=0.0,
                     help="run the workload on a mesh stretched geometrically by this ratio per cell")
     ap.add_argument("--copy-calib", type=float, default=0.0,
@@ -262,6 +302,9 @@ def main():
         from paper_1810_00348_amd import cases as _cases
         centres = (None, None, None) if args.workload != "c4" else (2.5, 3.0, None)
         case = _cases.stretched(case, args.stretch, centres)
+    if args.solve > 0:
+        solve(case, prec, args.solve, args.tol, describe(args.workload, case))
+        return
     s = Solver(case, precision=prec)
     s.init_uniform()
     info = s.info()
