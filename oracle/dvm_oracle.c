@@ -20,6 +20,10 @@
  *     characteristic direction (eqs. "iter_outer", "sweeping_example"), the
  *     boundary values being the diffuse-wall emission (eqs. "maxwell_wall",
  *     "rho_wall"), the free-stream equilibrium, or the specular mirror image;
+ *     optionally (orc_set_order) the second-order upwind sweep that the
+ *     paper's closing section proposes (three consecutive cells per axis:
+ *     each face carries the upwind cell's value extrapolated linearly from
+ *     that cell and its own upwind neighbour), uniform meshes only;
  *   - the discrete moments of eq. "macros" of the new f.  The heat flux uses
  *     the NEW bulk velocity U^{n+1}, so each velocity is swept twice: once for
  *     rho, rho U, rho E and the wall fluxes, once for q (the sweep is a
@@ -90,6 +94,8 @@ typedef struct {
     double M0;
     double res[5];
     int iter;
+    int order;              /* 1: first-order upwind (the paper's scheme);
+                               2: second-order upwind (Sec. 6 outlook)    */
 } orc_state;
 
 /* ----------------------------------------------------------------------- */
@@ -263,6 +269,22 @@ int orc_set_spacing(orc_state *s, const double *hx, const double *hy, const doub
     return ORC_OK;
 }
 
+/* Spatial order of the upwind scheme (1 or 2).  The second order is the one
+   the paper's closing section proposes, built from three consecutive cells
+   along each axis; it is defined here for uniform meshes only.             */
+int orc_set_order(orc_state *s, int order)
+{
+    if (order != 1 && order != 2) return ORC_ERR;
+    if (order == 2) {
+        const int n3[3] = {s->c.nx, s->c.ny, s->c.nz};
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i < n3[d]; ++i)
+                if (fabs(s->h[d][i] - s->dx[d]) > 1e-12 * s->dx[d]) return ORC_ERR;
+    }
+    s->order = order;
+    return ORC_OK;
+}
+
 /* side s of a cell: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+; the normal pointing
    from that face INTO the cell (into the gas) is -(side odd ? +e_d : -e_d). */
 static double into_gas_normal_sign(int side) { return (side & 1) ? -1.0 : 1.0; }
@@ -295,6 +317,7 @@ orc_state *orc_create(const orc_case *cfg, const unsigned char *solid)
             return NULL;
         }
     }
+    s->order = 1;
     s->solid = (unsigned char *)calloc(s->N, 1);
     if (solid) memcpy(s->solid, solid, s->N);
     const double zero3[3] = {0, 0, 0};
@@ -374,12 +397,25 @@ typedef struct {
 /* One upwind sweep of discrete velocity al (eq. "sweeping_example" in the
  * finite-volume flux form: the upwind value at a boundary or solid face is
  * that face's inflow value).  feq: corrected equilibrium of this velocity
- * at every cell (nu-weighted source).  spec: z=0 plane values of the
- * mirrored velocity (symmetry plane) or NULL.                               */
+ * at every cell (nu-weighted source).  spec_mirror: the z=0 plane of the
+ * mirrored velocity (symmetry plane), two planes of nx*ny values -- its f,
+ * then what it carries through z = 0 (its fo along z) -- or NULL.  The
+ * mirror image stands for the cell beyond the plane, so with the second
+ * order the plane is an interior face.
+ *
+ * fo[d] (3 x N): the value this velocity carries through each cell's
+ * downstream face along axis d.  First order: the cell value.  Second
+ * order: the linear extrapolation from the cell and its upwind neighbour
+ * along d, f + (f - f_up)/2, or the cell value when the upwind side is a
+ * boundary.  The cell balance is then, per axis with a = |xi_d| / h,
+ * a (fo_d(cell) - fo_d(upwind)) (the boundary's inflow value in place of
+ * fo_d(upwind) at a boundary), so that the unknown f enters with
+ * coefficient 3a/2 behind an interior face and a behind a boundary.        */
 static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                            const double *feq, const double *nu,
-                           const double *spec_mirror, double *f)
+                           const double *spec_mirror, double *f, double *fo)
 {
+    const int N = s->N;
     const orc_case *c = &s->c;
     int al = a3 + c->m[0] * (b3 + c->m[1] * c3);
     double xv[3] = {s->xi[0][a3], s->xi[1][b3], s->xi[2][c3]};
@@ -392,9 +428,15 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
             for (int iq = 0; iq < c->nx; ++iq) {
                 int i = sg[0] > 0 ? iq : c->nx - 1 - iq;
                 int id = cell_index(c, i, j, k);
-                if (s->solid[id]) { f[id] = 0; continue; }
+                if (s->solid[id]) {
+                    f[id] = 0;
+                    for (int d = 0; d < 3; ++d) fo[(size_t)d * N + id] = 0;
+                    continue;
+                }
                 double num = nu[id] * feq[id];
                 double den = nu[id];
+                double up[3] = {0, 0, 0};  /* f of the interior upwind cell */
+                int interior[3] = {0, 0, 0};
                 /* |xi_d| / (cell size along d): the flux through the cell's
                    upwind face per unit volume                               */
                 const double ad[3] = {fabs(xv[0]) / s->h[0][i], fabs(xv[1]) / s->h[1][j],
@@ -405,6 +447,18 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                     int nb = -1;
                     int t = face_type(s, i, j, k, side, &nb);
                     double fu;
+                    if (s->order == 2 && (t < 0 || t == 100 + FACE_SPECULAR)) {
+                        /* inflow = the upwind cell's downstream face value;
+                           own outflow f + (f - f_up)/2 adds a/2 (f - f_up) */
+                        const int nxy = c->nx * c->ny, ij = i + c->nx * j;
+                        const double fup = t < 0 ? f[nb] : spec_mirror[ij];
+                        const double fin = t < 0 ? fo[(size_t)d * N + nb] : spec_mirror[nxy + ij];
+                        interior[d] = 1;
+                        up[d] = fup;
+                        num += ad[d] * (fin + 0.5 * fup);
+                        den += 1.5 * ad[d];
+                        continue;
+                    }
                     if (t < 0) fu = f[nb];
                     else if (t == 100 + FACE_SPECULAR) fu = spec_mirror[i + c->nx * j];
                     else if (kind_is_wall(s, t)) fu = s->rho_w[side * s->N + id] * s->ghat[t][al];
@@ -413,6 +467,8 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                     den += ad[d];
                 }
                 f[id] = num / den;
+                for (int d = 0; d < 3; ++d)
+                    fo[(size_t)d * N + id] = interior[d] ? f[id] + 0.5 * (f[id] - up[d]) : f[id];
             }
         }
     }
@@ -634,7 +690,7 @@ int orc_iterate(orc_state *s)
     int spec = has_specular(s);
     int nxy = c->nx * c->ny;
     /* z=0 plane values of every velocity moving towards -z (symmetry plane) */
-    double *specbuf = spec ? (double *)calloc((size_t)NV * nxy, sizeof(double)) : NULL;
+    double *specbuf = spec ? (double *)calloc((size_t)NV * 2 * nxy, sizeof(double)) : NULL;
 
     /* per-thread accumulators: 5 conserved moments, 3 heat flux, 6 wall
        fluxes (pass 1), then the heat flux (pass 2)                          */
@@ -655,6 +711,7 @@ int orc_iterate(orc_state *s)
                 tid = omp_get_thread_num();
 #endif
                 double *f = (double *)malloc(sizeof(double) * N);
+                double *fo = (double *)malloc(sizeof(double) * 3 * N);
                 double *feq = (double *)malloc(sizeof(double) * N);
                 double *A = acc + (size_t)tid * 11 * N;
 #pragma omp for schedule(static)
@@ -671,11 +728,15 @@ int orc_iterate(orc_state *s)
                     if (spec && xz > 0) {
                         int cm = c->m[2] - 1 - c3; /* mirrored z index */
                         int alm = a3 + c->m[0] * (b3 + c->m[1] * cm);
-                        mir = specbuf + (size_t)alm * nxy;
+                        mir = specbuf + (size_t)alm * 2 * nxy;
                     }
-                    sweep_velocity(s, a3, b3, c3, feq, p.nu, mir, f);
+                    sweep_velocity(s, a3, b3, c3, feq, p.nu, mir, f, fo);
+                    /* the mirror image takes what crosses the plane z = 0 */
                     if (spec && xz < 0 && pass == 0)
-                        for (int ij = 0; ij < nxy; ++ij) specbuf[(size_t)al * nxy + ij] = f[ij];
+                        for (int ij = 0; ij < nxy; ++ij) {
+                            specbuf[(size_t)al * 2 * nxy + ij] = f[ij];
+                            specbuf[((size_t)al * 2 + 1) * nxy + ij] = fo[(size_t)2 * N + ij];
+                        }
                     double x2 = xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2];
                     for (int k = 0; k < c->nz; ++k)
                         for (int j = 0; j < c->ny; ++j)
@@ -697,7 +758,8 @@ int orc_iterate(orc_state *s)
                                         int nb;
                                         int t = face_type(s, i, j, k, side, &nb);
                                         if (t < 0 || t >= 100 || !kind_is_wall(s, t)) continue;
-                                        A[(5 + side) * N + id] += -xn * wf;
+                                        /* what crosses the wall face */
+                                        A[(5 + side) * N + id] += -xn * (w * fo[(size_t)d * N + id]);
                                     }
                                 } else {
                                     /* heat flux about the NEW bulk velocity */
@@ -711,7 +773,7 @@ int orc_iterate(orc_state *s)
                                 }
                             }
                 }
-                free(f); free(feq);
+                free(f); free(fo); free(feq);
             }
         }
         /* fixed-order reduction over threads */
@@ -846,7 +908,8 @@ int orc_get_ghat(const orc_state *s, int kind, double *g, double *gout6)
 
 /* The f field of one discrete velocity produced by the sweep of the NEXT
    iteration from the current state (for the brute-force dense check).
-   spec_mirror: z=0 plane of the mirrored velocity or NULL.                   */
+   spec_mirror: z=0 planes of the mirrored velocity (its f, then its fo
+   along z; the second plane is read with the second order only) or NULL.   */
 int orc_sweep_one(const orc_state *s, int al, const double *spec_mirror,
                   double *f_out, double *feq_out, double *nu_out)
 {
@@ -867,8 +930,10 @@ int orc_sweep_one(const orc_state *s, int al, const double *spec_mirror,
         int b3 = (al / c->m[0]) % c->m[1];
         int c3 = al / (c->m[0] * c->m[1]);
         double *feq = (double *)malloc(sizeof(double) * N);
+        double *fo = (double *)malloc(sizeof(double) * 3 * N);
         velocity_feq(s, &p, lam, a3, b3, c3, feq);
-        sweep_velocity(s, a3, b3, c3, feq, p.nu, spec_mirror, f_out);
+        sweep_velocity(s, a3, b3, c3, feq, p.nu, spec_mirror, f_out, fo);
+        free(fo);
         if (feq_out) memcpy(feq_out, feq, sizeof(double) * N);
         if (nu_out) memcpy(nu_out, p.nu, sizeof(double) * N);
         free(feq);

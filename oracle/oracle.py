@@ -79,6 +79,7 @@ def lib():
                                       C.c_double, _P, C.c_double, _P, C.c_double, C.c_int, _P]
         L.orc_num_threads.argtypes = [C.c_void_p]
         L.orc_set_spacing.argtypes = [C.c_void_p, _P, _P, _P]
+        L.orc_set_order.argtypes = [C.c_void_p, C.c_int]
         _lib = L
     return _lib
 
@@ -154,6 +155,9 @@ class Oracle:
             self._sp = [None if h is None else np.ascontiguousarray(h, dtype=np.float64) for h in sp3]
             if lib().orc_set_spacing(self._h, *[None if h is None else _ptr(h) for h in self._sp]) != 0:
                 raise ValueError("bad cell sizes")
+        order = getattr(case, "order", 1)
+        if order != 1 and lib().orc_set_order(self._h, order) != 0:
+            raise ValueError("second order needs a uniform mesh (order 1 or 2)")
 
     def __del__(self):
         h = getattr(self, "_h", None)

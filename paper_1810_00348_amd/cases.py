@@ -74,6 +74,9 @@ class Case:
     # cell sizes along x, y, z (arrays of length nx, ny, nz summing to L),
     # None for a uniform mesh
     spacing: Optional[Tuple[Optional[np.ndarray], Optional[np.ndarray], Optional[np.ndarray]]] = None
+    # spatial order of the upwind scheme: 1 (the paper's), or 2 (linear
+    # upwind extrapolation from two upwind cells; uniform meshes only)
+    order: int = 1
 
     @property
     def ncells(self) -> int:

@@ -11,6 +11,14 @@ with a_d = |xi_d| / dx_d(c), dx_d(c) the size of cell c along d (uniform or
 a stretched mesh).  Here it is assembled as a dense matrix and solved
 with LU (numpy), i.e. without any notion of sweep order, so it checks the
 oracle's sweep (traversal order, upwind selection, boundary bookkeeping).
+
+order=2: the flux through each face is the upwind cell's value extrapolated
+linearly from that cell and its own upwind neighbour, f_u + (f_u - f_uu)/2
+(just f_u when the upwind cell's upwind side is a boundary), and a
+boundary's inflow value where the face is a boundary; the cell's balance
+per axis is a_d (F_out(c) - F_in(c)).  A symmetry plane is an interior face
+whose far side is the mirror image: spec_mirror then holds two planes (the
+mirror's f and its extrapolated face value).
 """
 from __future__ import annotations
 
@@ -19,7 +27,7 @@ import numpy as np
 from paper_1810_00348_amd.cases import FREE, SPECULAR, WALL
 
 
-def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=None):
+def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=None, order=1):
     nx, ny, nz = case.n
     N = nx * ny * nz
     mx, my, mz = case.m
@@ -36,6 +44,29 @@ def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=
     if sp is not None:
         h = [h[d] if sp[d] is None else np.asarray(sp[d], dtype=np.float64) for d in range(3)]
     solid = case.solid_flat() if case.solid is not None else np.zeros(N, np.uint8)
+    ext = [nx, ny, nz]
+
+    def upwind(pos, d, c):
+        """What lies on the upwind side of cell pos along d:
+        ("cell", index, pos), ("spec", i + nx j) or ("bnd", inflow value)."""
+        step = -1 if xi[d] >= 0 else +1
+        side = 2 * d + (0 if xi[d] >= 0 else 1)
+        p = list(pos)
+        p[d] += step
+        if 0 <= p[d] < ext[d]:
+            nb = p[0] + nx * (p[1] + ny * p[2])
+            if not solid[nb]:
+                return ("cell", nb, p)
+            return ("bnd", rho_w[side, c] * ghat_of_kind(6)[alpha])
+        kind = case.faces[side].code
+        if kind == WALL:
+            return ("bnd", rho_w[side, c] * ghat_of_kind(side)[alpha])
+        if kind == FREE:
+            return ("bnd", case.faces[side].rho * ghat_of_kind(side)[alpha])
+        if kind == SPECULAR:
+            return ("spec", pos[0] + nx * pos[1])
+        raise ValueError(kind)
+
     A = np.zeros((N, N))
     b = np.zeros(N)
     for k in range(nz):
@@ -48,31 +79,40 @@ def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=
                 A[c, c] = nu[c]
                 b[c] = nu[c] * feq[c]
                 pos = [i, j, k]
-                ext = [nx, ny, nz]
                 for d in range(3):
                     ad = abs(xi[d]) / h[d][pos[d]]
                     if ad == 0:
                         continue
-                    A[c, c] += ad
-                    step = -1 if xi[d] >= 0 else +1       # towards the upwind side
-                    side = 2 * d + (0 if xi[d] >= 0 else 1)
-                    p = list(pos)
-                    p[d] += step
-                    if 0 <= p[d] < ext[d]:
-                        nb = p[0] + nx * (p[1] + ny * p[2])
-                        if not solid[nb]:
-                            A[c, nb] -= ad
-                            continue
-                        fb = rho_w[side, c] * ghat_of_kind(6)[alpha]
-                    else:
-                        kind = case.faces[side].code
-                        if kind == WALL:
-                            fb = rho_w[side, c] * ghat_of_kind(side)[alpha]
-                        elif kind == FREE:
-                            fb = case.faces[side].rho * ghat_of_kind(side)[alpha]
-                        elif kind == SPECULAR:
-                            fb = spec_mirror[i + nx * j]
+                    up = upwind(pos, d, c)
+                    if order == 1:
+                        A[c, c] += ad
+                        if up[0] == "cell":
+                            A[c, up[1]] -= ad
+                        elif up[0] == "spec":
+                            b[c] += ad * spec_mirror[up[1]]
                         else:
-                            raise ValueError(kind)
-                    b[c] += ad * fb
+                            b[c] += ad * up[1]
+                        continue
+                    if up[0] == "bnd":
+                        # first-order face: a (f_c - f_b)
+                        A[c, c] += ad
+                        b[c] += ad * up[1]
+                        continue
+                    # interior face: a (1.5 f_c - 0.5 f_u - F_out(u))
+                    A[c, c] += 1.5 * ad
+                    if up[0] == "spec":
+                        nxy = nx * ny
+                        b[c] += ad * (0.5 * spec_mirror[up[1]] + spec_mirror[nxy + up[1]])
+                        continue
+                    u = up[1]
+                    A[c, u] -= 0.5 * ad
+                    uu = upwind(up[2], d, u)
+                    if uu[0] == "bnd":            # F_out(u) = f_u
+                        A[c, u] -= ad
+                    elif uu[0] == "cell":         # F_out(u) = 1.5 f_u - 0.5 f_uu
+                        A[c, u] -= 1.5 * ad
+                        A[c, uu[1]] += 0.5 * ad
+                    else:                         # beyond u: the mirror image
+                        A[c, u] -= 1.5 * ad
+                        b[c] -= 0.5 * ad * spec_mirror[uu[1]]
     return np.linalg.solve(A, b)
