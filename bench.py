@@ -257,6 +257,8 @@ def main():
                     help="solve the workload from the uniform start for up to ITERS iterations "
                          "(or to --tol), one progress line per iteration")
     ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--order", type=int, default=1, choices=(1, 2),
+                    help="spatial order of the upwind sweep (2: the second-order extension)")
     ap.add_argument("--stretch", type=float, default=0.0,
                     help="run the workload on a mesh stretched geometrically by this ratio per cell")
     ap.add_argument("--copy-calib", type=float, default=0.0,
@@ -302,6 +304,9 @@ def main():
         from paper_1810_00348_amd import cases as _cases
         centres = (None, None, None) if args.workload != "c4" else (2.5, 3.0, None)
         case = _cases.stretched(case, args.stretch, centres)
+    if args.order != 1:
+        import dataclasses as _dc
+        case = _dc.replace(case, order=args.order, name=case.name + f"_order{args.order}")
     if args.solve > 0:
         solve(case, prec, args.solve, args.tol, describe(args.workload, case))
         return
@@ -333,6 +338,8 @@ def main():
     label = f"{args.workload}_{prec}_vl{info['vel_per_lane']}_b{info['brick'][0]}x{info['brick'][1]}x{info['brick'][2]}"
     if args.stretch > 0:
         label += f"_stretch{args.stretch:g}"
+    if args.order != 1:
+        label += f"_order{args.order}"
     line = {
         "metric": "phase-space GPoint-updates/s per iteration",
         "value": round(value, 3),
@@ -349,6 +356,7 @@ def main():
         "config": {
             "workload": describe(args.workload, case),
             "velocity_groups": info["velocity_groups"],
+            "upwind_order": case.order,
             "points_per_iteration": pts,
             "brick": info["brick"],
             "vel_per_lane": info["vel_per_lane"],

@@ -134,6 +134,19 @@ dvm_status dvm_set_closed(dvm_ctx* ctx, int closed);
    DVM_ERR_ARG for bad sizes. */
 dvm_status dvm_set_spacing(dvm_ctx* ctx, const double* hx, const double* hy, const double* hz);
 
+/* Spatial order of the upwind sweep: 1 (default; the paper's first-order
+   scheme, Sec. 2.2) or 2 (the extension its closing section proposes, from
+   three consecutive cells along each axis).  Second order: every face
+   carries the upwind cell's value extrapolated linearly from that cell and
+   its own upwind neighbour, f + (f - f_up)/2 (f alone when that cell's
+   upwind side is a boundary); a boundary face carries its inflow value; a
+   symmetry plane is an interior face whose far side is the mirror image;
+   the wall densities are balanced with what crosses the wall faces.
+   Uniform meshes only.  Before binding the workspace (DVM_ERR_STATE after
+   it); DVM_ERR_ARG for another order or on a non-uniform mesh.  Order 2
+   doubles the face and mirror-plane buffers and the sweep's LDS plane. */
+dvm_status dvm_set_order(dvm_ctx* ctx, int order);
+
 /* Sweep the velocity set in `groups` parts, one after another, within each
    iteration: each octant's 64-lane velocity tiles are split into `groups`
    consecutive ranges of (nearly) equal size (at most one range per tile).

@@ -54,6 +54,7 @@ struct Consts {
     double omega, pr;
     int correct;
     int closed;
+    int order2;           // second-order upwind: wall fluxes take the face values
     double kind_rho[8];   // fixed emission density (free stream), per kind
     int kind_wall[8];     // 1: density from non-penetration
 };
@@ -79,6 +80,13 @@ struct SweepArgs {
     S* yface;
     S* zface;
     S* spec;
+    // second-order upwind: what each cell carries through its downstream
+    // face (the linear extrapolation from it and its upwind neighbour),
+    // beside the cell values of the faces and mirror planes above
+    S* xgface;
+    S* ygface;
+    S* zgface;
+    S* specg;
     double* partial;      // [8*ntiles][N][PREC]
     int nx, ny, nz, N, mx, my, MT, NV;
     int nbx, nby, nbz, bz;
@@ -100,8 +108,8 @@ hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind
 hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* params, const void* etab,
                             const double* ghat64, const double* gout, double* rho_w, int prec,
                             hipStream_t st);
-hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, const void* args,
-                        hipStream_t st);
+hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, int order2,
+                        const void* args, hipStream_t st);
 hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
                            const double* gout, double* Wn, double* qn, double* rwn,
                            double* blockmass, int nblocks, int* flag, hipStream_t st);
@@ -114,6 +122,6 @@ hipError_t launch_residual_final(const double* respart, int nblocks, const doubl
 // acc[o][cell] (= or +=) sum over the ntiles records partial[o*ntiles + t][cell]
 hipError_t launch_fold(const double* partial, int ntiles, int N, int add, double* acc, hipStream_t st);
 hipError_t launch_selftest_reduce(const double* in, double* out, hipStream_t st);
-bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform);
+bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2 = 0);
 
 }  // namespace dvm

@@ -495,6 +495,31 @@ __device__ __forceinline__ double wave_reduce13(const double v[13])
     return O;
 }
 
+// The same reduction of 16 values: the three slots that the 13-value form
+// pads with zeros carry values 13..15 (one more 32-lane swap).  Lane
+// L = 16 r + 4 b + x then holds the sum of value idx(r, b), all 16 valid.
+__device__ __forceinline__ double wave_reduce16(const double v[16])
+{
+    double a0 = v[0], b0 = v[1]; pl32_swap(a0, b0); const double R0 = a0 + b0;
+    double a1 = v[2], b1 = v[3]; pl32_swap(a1, b1); const double R1 = a1 + b1;
+    double a2 = v[4], b2 = v[5]; pl32_swap(a2, b2); const double R2 = a2 + b2;
+    double a3 = v[6], b3 = v[7]; pl32_swap(a3, b3); const double R3 = a3 + b3;
+    double a4 = v[8], b4 = v[9]; pl32_swap(a4, b4); const double R4 = a4 + b4;
+    double a5 = v[10], b5 = v[11]; pl32_swap(a5, b5); const double R5 = a5 + b5;
+    double a6 = v[12], b6 = v[13]; pl32_swap(a6, b6); const double R6 = a6 + b6;
+    double a7 = v[14], b7 = v[15]; pl32_swap(a7, b7); const double R7 = a7 + b7;
+    double c0 = R0, d0 = R1; pl16_swap(c0, d0); const double Q0 = c0 + d0;
+    double c1 = R2, d1 = R3; pl16_swap(c1, d1); const double Q1 = c1 + d1;
+    double c2 = R4, d2 = R5; pl16_swap(c2, d2); const double Q2 = c2 + d2;
+    double c3 = R6, d3 = R7; pl16_swap(c3, d3); const double Q3 = c3 + d3;  // rows: v12 v14 v13 v15
+    const double P0 = halve8(Q0, Q1);
+    const double P1 = halve8(Q2, Q3);
+    double O = halve4(P0, P1);
+    O += dpp_mov<DPP_QUAD_2301>(O);
+    O += dpp_mov<DPP_QUAD_1032>(O);
+    return O;
+}
+
 __device__ __forceinline__ int reduce13_index(int lane)
 {
     const int r = lane >> 4, b = (lane >> 2) & 3;
@@ -563,7 +588,19 @@ __device__ __forceinline__ void stb_nt(T* base, unsigned off, T v)
     __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off));
 }
 
-template <typename S, int VL, int BX, int BY, bool NU>
+// O2: second-order upwind.  Each face carries the upwind cell's value
+// extrapolated linearly from that cell and its own upwind neighbour,
+// F = f + (f - f_up)/2 (F = f when that cell's upwind side is a boundary);
+// per axis the cell balance a (F_out - F_in) makes the unknown enter with
+// 3a/2 behind an interior face (a behind a boundary) and takes F_in + f_up/2
+// from the upwind side.  Carried along: x -- the previous cell's (f, F) in
+// registers; y -- f of the two previous rows from the plane, F rebuilt from
+// them (a bit per plane cell records a boundary behind it); z -- a second
+// LDS plane with each column's newest F.  Faces and the mirror plane hold
+// (f, F) pairs; a symmetry plane is an interior face (the mirror image is
+// the cell beyond it).  Three more raw moments, sum w xi_d (F_d - f), turn
+// the cell-value fluxes into face fluxes for the wall densities.
+template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __restrict__ params,
                                            const S* __restrict__ etab, const S* __restrict__ ghat,
                                            const double* __restrict__ lanetab, const int* __restrict__ bricks,
@@ -612,9 +649,27 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
     const S* zin = zface + ((size_t)(o * 2 + ((K - 1) & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
     S* zout = zface + ((size_t)(o * 2 + (K & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
     S* sbuf = A.spec_on ? spec + (size_t)(o & 3) * ny * nx * fstride : nullptr;
+    // second order: the F layers of the same faces and mirror plane
+    const S* xgin = nullptr; S* xgout = nullptr;
+    const S* ygin = nullptr; S* ygout = nullptr;
+    const S* zgin = nullptr; S* zgout = nullptr;
+    S* sgbuf = nullptr;
+    if constexpr (O2) {
+        xgin = A.xgface + (xin - xface);
+        xgout = A.xgface + (xout - xface);
+        ygin = A.ygface + (yin - yface);
+        ygout = A.ygface + (yout - yface);
+        zgin = A.zgface + (zin - zface);
+        zgout = A.zgface + (zout - zface);
+        sgbuf = A.spec_on ? A.specg + (size_t)(o & 3) * ny * nx * fstride : nullptr;
+    }
 
-    // the brick's newest plane of f: lds(jj, ii, v) = plane[((jj*BX + ii)*VL + v)*64 + lane]
+    // the brick's newest plane of f: lds(jj, ii, v) = plane[((jj*BX + ii)*VL + v)*64 + lane];
+    // second order: ldz, the newest F along z of each column, follows it
     auto lds = [&](int jj, int ii, int v) -> S& { return plane[((jj * BX + ii) * VL + v) * 64 + lane]; };
+    auto ldz = [&](int jj, int ii, int v) -> S& {
+        return plane[((BY * BX + jj * BX + ii) * VL + v) * 64 + lane];
+    };
 
     // ---- lane constants
     const double* lt = lanetab + ((size_t)o * A.slots + slot) * A.lstride;
@@ -652,11 +707,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
 
     for (int kk = 0; kk < kend; ++kk) {
         const int kcell = cell0 + kk * sk;
+        uint32_t ybnd = 0;  // second order: plane cells whose y upwind side is a boundary
         for (int jj = 0; jj < jend; ++jj) {
             const int rcell = kcell + jj * sj;
             const S* xrow_in = xin + ((size_t)kk * ny + jj) * fstride;
             S* xrow_out = xout + ((size_t)kk * ny + jj) * fstride;
             S prev[VL];
+            S prevF[VL];  // second order: the previous cell's F along x
             for (int ii = 0; ii < iend; ++ii) {
                 const int cell = rcell + ii * si;
                 const S* P = params + (size_t)cell * PSTRIDE;
@@ -667,11 +724,31 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 // ---- upwind operands: 0 = interior neighbour (in the plane,
                 //      the previous cell, or the upwind brick's face), 8 =
                 //      symmetry plane, 7 = solid body, else the box face
+                // second order: fx.. hold F_in + f_up / 2 behind an interior
+                // face, ux.. hold f_up, and ix.. say which faces are interior
                 S fx[VL], fy[VL], fz[VL];
+                S ux[VL], uy[VL], uz[VL];
+                bool ixf = false, iyf = false, izf = false;
                 {
                     const uint32_t code = (info >> shX) & 15u;
                     if (code == 0) {
-                        if (ii > 0) {
+                        if constexpr (O2) {
+                            ixf = true;
+                            if (ii > 0) {
+#pragma unroll
+                                for (int v = 0; v < VL; ++v) {
+                                    ux[v] = prev[v];
+                                    fx[v] = prevF[v] + (S)0.5 * prev[v];
+                                }
+                            } else {
+                                const S* grow_in = xgin + ((size_t)kk * ny + jj) * fstride;
+#pragma unroll
+                                for (int v = 0; v < VL; ++v) {
+                                    ux[v] = ldb(xrow_in, lofs + v * SB);
+                                    fx[v] = ldb(grow_in, lofs + v * SB) + (S)0.5 * ux[v];
+                                }
+                            }
+                        } else if (ii > 0) {
 #pragma unroll
                             for (int v = 0; v < VL; ++v) fx[v] = prev[v];
                         } else {
@@ -687,8 +764,37 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 }
                 {
                     const uint32_t code = (info >> shY) & 15u;
+                    if constexpr (O2) {
+                        if (code != 0) ybnd |= 1u << (jj * BX + ii);
+                    }
                     if (code == 0) {
-                        if (jj > 0) {
+                        if constexpr (O2) {
+                            iyf = true;
+                            if (jj > 0) {
+                                // F of the row behind: from its own upwind row
+                                const bool edge = (ybnd >> ((jj - 1) * BX + ii)) & 1u;
+                                const S* f2row = yin + ((size_t)kk * nx + ii) * fstride;
+#pragma unroll
+                                for (int v = 0; v < VL; ++v) {
+                                    const S fu = lds(jj - 1, ii, v);
+                                    S Fu = fu;
+                                    if (!edge) {
+                                        const S f2 = jj >= 2 ? lds(jj - 2, ii, v) : ldb(f2row, lofs + v * SB);
+                                        Fu = (S)1.5 * fu - (S)0.5 * f2;
+                                    }
+                                    uy[v] = fu;
+                                    fy[v] = Fu + (S)0.5 * fu;
+                                }
+                            } else {
+                                const S* src = yin + ((size_t)kk * nx + ii) * fstride;
+                                const S* gsrc = ygin + ((size_t)kk * nx + ii) * fstride;
+#pragma unroll
+                                for (int v = 0; v < VL; ++v) {
+                                    uy[v] = ldb(src, lofs + v * SB);
+                                    fy[v] = ldb(gsrc, lofs + v * SB) + (S)0.5 * uy[v];
+                                }
+                            }
+                        } else if (jj > 0) {
 #pragma unroll
                             for (int v = 0; v < VL; ++v) fy[v] = lds(jj - 1, ii, v);
                         } else {
@@ -705,7 +811,35 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 }
                 {
                     const uint32_t code = (info >> shZ) & 15u;
-                    if (code == 0) {
+                    if (O2 && (code == 0 || code == CODE_SPECULAR)) {
+                        izf = true;
+                        if (code == 0 && kk > 0) {
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) {
+                                uz[v] = lds(jj, ii, v);
+                                fz[v] = ldz(jj, ii, v) + (S)0.5 * uz[v];
+                            }
+                        } else {
+                            // the upwind brick's face, or the mirror image
+                            // beyond the symmetry plane
+                            const S* src;
+                            const S* gsrc;
+                            if (code == 0) {
+                                src = zin + ((size_t)jj * nx + ii) * fstride;
+                                gsrc = zgin + ((size_t)jj * nx + ii) * fstride;
+                            } else {
+                                const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
+                                const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
+                                src = sbuf + ((size_t)j * nx + i) * fstride;
+                                gsrc = sgbuf + ((size_t)j * nx + i) * fstride;
+                            }
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) {
+                                uz[v] = ldb(src, lofs + v * SB);
+                                fz[v] = ldb(gsrc, lofs + v * SB) + (S)0.5 * uz[v];
+                            }
+                        }
+                    } else if (code == 0) {
                         if (kk > 0) {
 #pragma unroll
                             for (int v = 0; v < VL; ++v) fz[v] = lds(jj, ii, v);
@@ -749,6 +883,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                     aynu = ayc + azc + nu;
                 }
                 double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+                double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // second order: sum w (F_d - f)
+                S Fy[VL], Fz[VL];
+                // second order: 3a/2 behind an interior face
+                const S kx = O2 && ixf ? (S)1.5 : (S)1, ky = O2 && iyf ? (S)1.5 : (S)1;
+                const S kz = O2 && izf ? (S)1.5 : (S)1;
+                const S ayk = ayc * ky, azk = azc * kz;
 #pragma unroll
                 for (int v = 0; v < VL; ++v) {
                     const S cx = xix[v] - Ux;
@@ -756,8 +896,26 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                     const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
                     const S nfs = gyz * ldb(E, oa[v]) * poly;
                     const S axv = NU ? ax[v] * idx : ax[v];
-                    const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
-                    const S f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
+                    S f;
+                    if constexpr (O2) {
+                        const S axk = axv * kx;
+                        const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
+                        f = num * fast_rcp(axk + ayk + azk + nu);
+                        // what this cell carries through its downstream faces
+                        const S dx = ixf ? (S)0.5 * (f - ux[v]) : (S)0;
+                        const S dy = iyf ? (S)0.5 * (f - uy[v]) : (S)0;
+                        const S dz = izf ? (S)0.5 * (f - uz[v]) : (S)0;
+                        prevF[v] = f + dx;
+                        Fy[v] = f + dy;
+                        Fz[v] = f + dz;
+                        ldz(jj, ii, v) = Fz[v];
+                        e0 += wm1[v] * (double)dx;
+                        e1 += wm0[v] * (double)dy;
+                        e2 += wm0[v] * (double)dz;
+                    } else {
+                        const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
+                        f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
+                    }
                     prev[v] = f;
                     lds(jj, ii, v) = f;
                     const double fd = (double)f;
@@ -771,14 +929,29 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 if (ii == BX - 1 && wx) {
 #pragma unroll
                     for (int v = 0; v < VL; ++v) stb_nt(xrow_out, lofs + v * SB, prev[v]);
+                    if constexpr (O2) {
+                        S* g = xgout + ((size_t)kk * ny + jj) * fstride;
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, prevF[v]);
+                    }
                 }
                 if (jj == BY - 1 && wy) {
 #pragma unroll
                     for (int v = 0; v < VL; ++v) stb_nt(yout + ((size_t)kk * nx + ii) * fstride, lofs + v * SB, prev[v]);
+                    if constexpr (O2) {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v)
+                            stb_nt(ygout + ((size_t)kk * nx + ii) * fstride, lofs + v * SB, Fy[v]);
+                    }
                 }
                 if (kk == A.bz - 1 && wz) {
 #pragma unroll
                     for (int v = 0; v < VL; ++v) stb_nt(zout + ((size_t)jj * nx + ii) * fstride, lofs + v * SB, prev[v]);
+                    if constexpr (O2) {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v)
+                            stb_nt(zgout + ((size_t)jj * nx + ii) * fstride, lofs + v * SB, Fz[v]);
+                    }
                 }
                 if (sbuf != nullptr && !pz && kr0 + kk == nz - 1) {
                     const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
@@ -786,10 +959,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                     S* dst = sbuf + ((size_t)j * nx + i) * fstride;
 #pragma unroll
                     for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+                    if constexpr (O2) {
+                        S* g = sgbuf + ((size_t)j * nx + i) * fstride;
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, Fz[v]);
+                    }
                 }
 
                 // ---- 13 raw moments of this tile at this cell
-                double m[13];
+                double m[O2 ? 16 : 13];
                 m[0] = u0;
                 m[1] = u1;
                 m[2] = xiy_d * u0;
@@ -804,7 +982,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 const double t2 = u2 + yz2 * u0;
                 m[11] = xiy_d * t2;
                 m[12] = xiz_d * t2;
-                const double tot = wave_reduce13(m);
+                double tot;
+                if constexpr (O2) {
+                    m[13] = e0;
+                    m[14] = xiy_d * e1;
+                    m[15] = xiz_d * e2;
+                    tot = wave_reduce16(m);
+                } else {
+                    tot = wave_reduce13(m);
+                }
                 if (writer) stb_nt(part + (size_t)cell * PREC, oridx, tot);
             }
         }
@@ -1122,6 +1308,15 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
                               A.spec, A.partial, plane);
 }
 
+// second-order upwind (uniform meshes)
+template <typename S, int VL, int BX, int BY>
+__global__ __launch_bounds__(64) void sweep_kernel_o2(const SweepArgs<S> A)
+{
+    S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
+    sweep_body<S, VL, BX, BY, false, true>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface,
+                                           A.zface, A.spec, A.partial, plane);
+}
+
 // instantiated variants: (precision, VL, BX, BY)
 #define DVM_SWEEP_VARIANTS(X) \
     X(double, 1, 4, 4) X(double, 2, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) X(double, 4, 4, 4) \
@@ -1132,12 +1327,19 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 #define DVM_SWEEP_VARIANTS_NU(X) \
     X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
+// and for the second-order sweep
+#define DVM_SWEEP_VARIANTS_O2(X) \
+    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) \
+    X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 
-bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform)
+bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2)
 {
 #define X(T, V, BXX, BYY) \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) return true;
-    if (nonuniform) {
+    if (order2) {
+        if (nonuniform) return false;
+        DVM_SWEEP_VARIANTS_O2(X)
+    } else if (nonuniform) {
         DVM_SWEEP_VARIANTS_NU(X)
     } else {
         DVM_SWEEP_VARIANTS(X)
@@ -1158,9 +1360,27 @@ hipError_t launch_sweep_t(int pipelined, const void* args, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, const void* args,
-                        hipStream_t st)
+template <typename T, int V, int BXX, int BYY>
+hipError_t launch_sweep_o2(const void* args, hipStream_t st)
 {
+    const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
+    const size_t lds = (size_t)2 * BYY * BXX * V * 64 * sizeof(T);  // f and F along z
+    sweep_kernel_o2<T, V, BXX, BYY><<<a.nblocks, 64, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, int order2,
+                        const void* args, hipStream_t st)
+{
+    if (order2) {
+        if (nonuniform) return hipErrorInvalidValue;
+#define X(T, V, BXX, BYY)                                                     \
+        if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) \
+            return launch_sweep_o2<T, V, BXX, BYY>(args, st);
+        DVM_SWEEP_VARIANTS_O2(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
 #define X(T, V, BXX, BYY)                                                                  \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY)              \
         return launch_sweep_t<T, V, BXX, BYY, NUV>(pipelined, args, st);
@@ -1210,6 +1430,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, cons
                     g1 += p[1];
                     g2 += p[2];
                     g3 += p[3];
+                    if (C.order2) {
+                        // second order: what crosses the downstream faces
+                        g1 += p[13];
+                        g2 += p[14];
+                        g3 += p[15];
+                    }
                 }
                 if (o & 1) hp[0] += g1; else hm[0] += g1;
                 if (o & 2) hp[1] += g2; else hm[1] += g2;

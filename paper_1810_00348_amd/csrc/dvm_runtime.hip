@@ -74,6 +74,7 @@ struct dvm_ctx {
     int hsplit[3];  // number of nodes with xi < 0 along each axis
     int VL = 2, BX = 4, BY = 4, BZ = 8;
     int PF = 1;  // software-pipelined sweep body
+    int order = 1;  // spatial order of the upwind scheme (1 or 2)
     std::vector<double> h[3];  // cell sizes along x, y, z (empty: uniform)
     std::vector<double> hstage;  // host copy of the uploaded sizes
     bool nonuniform = false;
@@ -95,7 +96,7 @@ struct dvm_ctx {
     bool bound = false;
     struct {
         size_t axes, spacing, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
-            partial, acc, xface, yface, zface, spec, blockmass, respart, out, flag, end;
+            partial, acc, xface, yface, zface, spec, xg, yg, zg, specg, blockmass, respart, out, flag, end;
     } off;
     size_t Ssz = 8;
     int nbF = 0;  // blocks of the per-cell kernels (256 threads)
@@ -151,17 +152,19 @@ void derive_schedule(dvm_ctx* c)
     int pf = (!f64 || vl == 4) ? 1 : 0;
     bx = env_int("DVM_BX", bx);
     by = env_int("DVM_BY", by);
-    if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform)) {
+    const int o2 = c->order == 2;
+    if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2)) {
         // the shape is not built (for this mesh kind): the defaults' shape for VL
         bx = (f64 && vl == 4) ? 2 : 4;
         by = vl == 1 ? 4 : 2;
-        if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform)) { vl = 1; bx = 4; by = 4; }
+        if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2)) { vl = 1; bx = 4; by = 4; }
     }
     c->VL = vl;
     c->BX = bx;
     c->BY = by;
     c->BZ = env_int("DVM_BZ", 8);
-    c->PF = env_int("DVM_PF", pf) != 0;
+    // the second-order sweep has the plain body only
+    c->PF = o2 ? 0 : env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
     c->nby = (c->g.ny + c->BY - 1) / c->BY;
@@ -249,6 +252,12 @@ void layout(dvm_ctx* c)
     c->off.yface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.nx * fst);
     c->off.zface = take(S * 8 * 2 * (size_t)c->g.ny * c->g.nx * fst);
     c->off.spec = take(c->spec_on ? S * 4 * (size_t)c->g.ny * c->g.nx * fst : 0);
+    // second order: the F layer of every face buffer and of the mirror plane
+    const bool o2 = c->order == 2;
+    c->off.xg = take(o2 ? c->off.yface - c->off.xface : 0);
+    c->off.yg = take(o2 ? c->off.zface - c->off.yface : 0);
+    c->off.zg = take(o2 ? c->off.spec - c->off.zface : 0);
+    c->off.specg = take(o2 && c->spec_on ? S * 4 * (size_t)c->g.ny * c->g.nx * fst : 0);
     c->off.blockmass = take(sizeof(double) * c->nbF);
     c->off.respart = take(sizeof(double) * 10 * c->nbF);
     c->off.out = take(sizeof(double) * 8);
@@ -276,6 +285,7 @@ Consts make_consts(const dvm_ctx* c)
     C.pr = c->gas.pr;
     C.correct = c->gas.conservative_correction;
     C.closed = c->closed;
+    C.order2 = c->order == 2;
     for (int k = 0; k < 8; ++k) {
         C.kind_rho[k] = c->kind_rho[k];
         C.kind_wall[k] = c->kind_wall[k];
@@ -448,6 +458,11 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.yface = c->P<S>(c->off.yface);
                 a.zface = c->P<S>(c->off.zface);
                 a.spec = c->spec_on ? c->P<S>(c->off.spec) : nullptr;
+                const bool o2 = c->order == 2;
+                a.xgface = o2 ? c->P<S>(c->off.xg) : nullptr;
+                a.ygface = o2 ? c->P<S>(c->off.yg) : nullptr;
+                a.zgface = o2 ? c->P<S>(c->off.zg) : nullptr;
+                a.specg = o2 && c->spec_on ? c->P<S>(c->off.specg) : nullptr;
                 a.partial = c->P<double>(c->off.partial);
                 a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.N = c->N;
                 a.mx = c->vg.m[0]; a.my = c->vg.m[1]; a.MT = C.MT; a.NV = c->NV;
@@ -464,11 +479,11 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
             if (c->prec == DVM_F64) {
                 SweepArgs<double> a;
                 fill(a);
-                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, &a, st);
+                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, &a, st);
             } else {
                 SweepArgs<float> a;
                 fill(a);
-                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, &a, st);
+                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, &a, st);
             }
             if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
         }
@@ -632,7 +647,19 @@ dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const
             c->h[d].assign(n3[d], c->dx[d]);
         }
     }
+    if (any && c->order == 2) return fail(DVM_ERR_ARG, "the second-order sweep needs a uniform mesh");
     c->nonuniform = any;
+    derive_schedule(c);
+    return DVM_OK;
+}
+
+dvm_status dvm_set_order(dvm_ctx* c, int order)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "the order must be set before binding the workspace");
+    if (order != 1 && order != 2) return fail(DVM_ERR_ARG, "order must be 1 or 2 (got %d)", order);
+    if (order == 2 && c->nonuniform) return fail(DVM_ERR_ARG, "the second-order sweep needs a uniform mesh");
+    c->order = order;
     derive_schedule(c);
     return DVM_OK;
 }

@@ -55,6 +55,8 @@ class Solver:
         if case.spacing is not None:
             self._spacing = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in case.spacing]
             L.check(lib.dvm_set_spacing(h, *[None if a is None else _ptr(a) for a in self._spacing]))
+        if case.order != 1:
+            L.check(lib.dvm_set_order(h, int(case.order)))
         nbytes = C.c_size_t()
         groups = 1 if velocity_groups is None else int(velocity_groups)
         L.check(lib.dvm_set_velocity_groups(h, groups))

@@ -163,3 +163,31 @@ def test_velocity_groups_arguments_and_workspace(L):
     assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 16) == -3
     assert lib.dvm_set_velocity_groups(h, 2) == 0
     lib.dvm_destroy(h)
+
+
+def test_order_arguments(L):
+    """dvm_set_order: 1 or 2, uniform meshes only, before binding; the
+    second order uses the plain sweep body and doubles the face buffers."""
+    import numpy as np
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    case = cases.cavity((6, 5, 4), 16, kn=1.0)
+    h = _ctx(L, case)
+    n1 = C.c_size_t()
+    assert lib.dvm_required_workspace(h, C.byref(n1)) == 0
+    assert lib.dvm_set_order(h, 3) == -1 and b"order" in lib.dvm_last_error()
+    assert lib.dvm_set_order(h, 2) == 0
+    info = L.Info()
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert info.pipelined == 0 and (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 2, 2)
+    n2 = C.c_size_t()
+    assert lib.dvm_required_workspace(h, C.byref(n2)) == 0
+    assert n2.value > n1.value
+    P = C.POINTER(C.c_double)
+    hy = cases.stretched_axis(5, 1.0, 1.3)
+    assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(P), None) == -1
+    assert b"uniform" in lib.dvm_last_error()
+    assert lib.dvm_set_order(h, 1) == 0
+    assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(P), None) == 0
+    assert lib.dvm_set_order(h, 2) == -1
+    lib.dvm_destroy(h)

@@ -313,3 +313,91 @@ def test_paper_cube_full_size_is_mirror_symmetric():
     assert abs(rho[90, 90, 0] - 1.0) < 0.1 and abs(ux[90, 90, 0] - case.init_u[0]) < 0.1
     # the stagnation region in front of the cube is compressed
     assert rho[90, 90, case.solid[90, 90].argmax() - 1] > 1.2
+
+
+def _o2_cases():
+    a = cases.cavity((13, 10, 19), 8, kn=0.3, lid=0.4, vmax=4.5)      # ragged bricks
+    b = cases.cavity((9, 11, 7), 9, kn=2.0, lid=0.2, vmax=5.0)         # odd M: xi = 0 nodes
+    c = cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=10, vmax=7.0, mach=2.0, kn=0.5)  # mirror, body
+    d = cases.cube_full_mirror(cases.cube_half(nx=12, ny=8, nz=4, edge=4, x0=3, m=12, vmax=6.0, mach=1.5,
+                                               kn=0.3))
+    e = cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2)                  # 4 per lane, 2x2 bricks (FP64)
+    f = cases.cavity((9, 8, 7), 24, kn=0.5, lid=0.3, vmax=5.0)         # 7 tiles per octant
+    return {k: dataclasses.replace(v, order=2) for k, v in
+            {"ragged": a, "oddM": b, "cube_half": c, "cube_full": d, "cavity_m16": e, "cavity_m24": f}.items()}
+
+
+@pytest.mark.parametrize("name", ["ragged", "oddM", "cube_half", "cube_full", "cavity_m16"])
+def test_second_order_matches_oracle(oracle_mod, name):
+    """Second-order upwind sweep (FP64) against the oracle's, including the
+    wall densities balanced with the extrapolated face values."""
+    case = _o2_cases()[name]
+    init = cases.random_fields(case, seed=41) if name in ("ragged", "cavity_m16") else None
+    s, o = run_pair(case, 3, oracle_mod, init=init)
+    err = field_errors(s.fields(), o.fields())
+    print(name, err, s.info())
+    for k in ("rho", "ux", "uy", "uz", "T", "qx", "qy"):
+        assert err[k] <= FP64_TOL, (k, err)
+    _, _, rwg, _ = s.state()
+    _, _, rwo = o.state()
+    assert np.abs(rwg - rwo).max() <= FP64_TOL * np.abs(rwo).max()
+
+
+@pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2)])
+@pytest.mark.parametrize("name", ["ragged", "cube_half"])
+def test_second_order_sweep_variants(oracle_mod, monkeypatch, name, vl, bx, by):
+    monkeypatch.setenv("DVM_VL", str(vl))
+    monkeypatch.setenv("DVM_BX", str(bx))
+    monkeypatch.setenv("DVM_BY", str(by))
+    case = _o2_cases()[name]
+    s, o = run_pair(case, 2, oracle_mod)
+    info = s.info()
+    assert (info["vel_per_lane"], info["brick"][0], info["brick"][1]) == (vl, bx, by), info
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "uy", "uz", "T"):
+        assert err[k] <= FP64_TOL, (k, err)
+
+
+def test_second_order_with_velocity_groups(oracle_mod):
+    case = _o2_cases()["cavity_m24"]
+    s, o = run_pair(case, 2, oracle_mod, init=cases.random_fields(case, seed=5), groups=3)
+    assert s.info()["velocity_groups"] == 3
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "uy", "uz", "T", "qx"):
+        assert err[k] <= FP64_TOL, (k, err)
+
+
+def test_second_order_fp32_storage(oracle_mod):
+    case = _o2_cases()["cube_half"]
+    s, o = run_pair(case, 3, oracle_mod, precision="f32")
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "T"):
+        assert err[k] <= 2e-5, (k, err)
+
+
+def test_second_order_converges_like_oracle(oracle_mod):
+    """c1 cavity with the second-order sweep: the HIP solver and the oracle
+    reach residual 1e-6 after the same number of iterations and agree on the
+    converged fields."""
+    case = dataclasses.replace(cases.config("c1"), order=2)
+    Solver = _solver()
+    s = Solver(case)
+    s.init_uniform()
+    n, r, ok = s.iterate(400, tol=1e-6)
+    o = oracle_mod.Oracle(case)
+    o.init_uniform()
+    k = 0
+    while k < 400:
+        k += 1
+        if o.iterate(1) <= 1e-6:
+            break
+    assert ok and n == k, (n, k)
+    err = field_errors(s.fields(), o.fields())
+    for key in ("rho", "ux", "uy", "T"):
+        assert err[key] <= 1e-9, (key, err)
+    # and it differs from the first-order solution at the discretisation level
+    s1 = Solver(cases.config("c1"))
+    s1.init_uniform()
+    s1.iterate(400, tol=1e-6)
+    d = field_errors(s1.fields(), s.fields())
+    assert 1e-3 < d["ux"] < 0.5, d
