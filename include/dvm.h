@@ -134,6 +134,18 @@ dvm_status dvm_set_closed(dvm_ctx* ctx, int closed);
    DVM_ERR_ARG for bad sizes. */
 dvm_status dvm_set_spacing(dvm_ctx* ctx, const double* hx, const double* hy, const double* hz);
 
+/* Velocity nodes and quadrature weights per axis (m[d] values each, host
+   arrays copied by the call) in place of the uniform trapezoid axes -- the
+   non-uniform velocity grids the paper recommends over very large uniform
+   ones (Sec. 5.2).  NULL nodes and weights keep that axis uniform on
+   [-vmax, vmax].  Nodes must increase and be symmetric about 0
+   (xi[M-1-a] = -xi[a], relative 1e-12; the sweep splits each axis at 0),
+   weights positive and symmetric.  Equilibria, emission shapes and moments
+   then use these nodes and weights.  Before binding the workspace
+   (DVM_ERR_STATE after it); DVM_ERR_ARG for invalid axes. */
+dvm_status dvm_set_velocity_axes(dvm_ctx* ctx, const double* xi_x, const double* w_x, const double* xi_y,
+                                 const double* w_y, const double* xi_z, const double* w_z);
+
 /* Spatial order of the upwind sweep: 1 (default; the paper's first-order
    scheme, Sec. 2.2) or 2 (the extension its closing section proposes, from
    three consecutive cells along each axis).  Second order: every face

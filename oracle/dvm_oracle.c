@@ -33,6 +33,9 @@
  *     normalisation), total-mass rescaling for a closed domain (Sec. 3.4),
  *     and the relative change of the conserved fields (Sec. 4.1).
  *
+ * The velocity axes are uniform with trapezoid weights (Sec. 4.1) unless
+ * orc_set_velocity_axis supplies other nodes and weights.
+ *
  * Normalisation: lengths by the reference length L that defines Kn,
  * velocities by sqrt(2 R T0), temperature by T0, density by rho0.  Hence
  * R T = T/2, p = rho T/2, f^M = rho (pi T)^{-3/2} exp(-|c|^2/T),
@@ -289,6 +292,72 @@ int orc_set_order(orc_state *s, int order)
    from that face INTO the cell (into the gas) is -(side odd ? +e_d : -e_d). */
 static double into_gas_normal_sign(int side) { return (side & 1) ? -1.0 : 1.0; }
 
+/* Unit-density emission shapes of the six faces and the solid body (the
+   corrected Maxwellian of each face's wall or free-stream state) and their
+   emitted-flux normalisers for every face orientation, on the current
+   velocity axes.                                                           */
+static int emission_tables(orc_state *s)
+{
+    const double zero3[3] = {0, 0, 0};
+    int any_solid = 0;
+    for (int id = 0; id < s->N; ++id) any_solid |= s->solid[id];
+    for (int k = 0; k < 7; ++k) {
+        if (k == 6 && !any_solid) continue;
+        const double *u = k < 6 ? s->c.face_u[k] : s->c.solid_u;
+        double T = k < 6 ? s->c.face_T[k] : s->c.solid_T;
+        if (k < 6 && s->c.face_kind[k] == FACE_SPECULAR) continue;
+        if (!(T > 0)) return ORC_ERR;
+        free(s->ghat[k]);
+        s->ghat[k] = (double *)malloc(sizeof(double) * s->NV);
+        if (orc_equilibrium(s->c.m, (const double *const *)s->xi,
+                            (const double *const *)s->w1, 1.0, u, T, zero3,
+                            s->c.pr, s->c.correction, s->ghat[k])) {
+            return ORC_ERR;
+        }
+        /* emitted-flux normaliser for each possible face orientation */
+        for (int side = 0; side < 6; ++side) {
+            int d = side >> 1;
+            double ns = into_gas_normal_sign(side);
+            double g = 0;
+            for (int c3 = 0; c3 < s->c.m[2]; ++c3)
+                for (int b3 = 0; b3 < s->c.m[1]; ++b3)
+                    for (int a3 = 0; a3 < s->c.m[0]; ++a3) {
+                        int idx[3] = {a3, b3, c3};
+                        double xn = s->xi[d][idx[d]] * ns;
+                        if (xn > 0) {
+                            int al = a3 + s->c.m[0] * (b3 + s->c.m[1] * c3);
+                            double w = s->w1[0][a3] * s->w1[1][b3] * s->w1[2][c3];
+                            g += w * xn * s->ghat[k][al];
+                        }
+                    }
+            s->gout[k][side] = g;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Nodes and quadrature weights of velocity axis d (m[d] values each) in
+   place of the uniform trapezoid axis -- the non-uniform velocity grids the
+   paper recommends over very large uniform ones (Sec. 5.2).  The nodes must
+   increase and be symmetric about 0 (xi[M-1-a] = -xi[a]), the weights be
+   positive and symmetric.  Before the initial state is set.                */
+int orc_set_velocity_axis(orc_state *s, int d, const double *xi, const double *w)
+{
+    if (!s || d < 0 || d > 2 || !xi || !w) return ORC_ERR;
+    const int M = s->c.m[d];
+    double big = 0;
+    for (int a = 0; a < M; ++a) big = fmax(big, fabs(xi[a]));
+    for (int a = 0; a < M; ++a) {
+        if (!(w[a] > 0) || !isfinite(xi[a])) return ORC_ERR;
+        if (a > 0 && !(xi[a] > xi[a - 1])) return ORC_ERR;
+        if (fabs(xi[a] + xi[M - 1 - a]) > 1e-12 * big) return ORC_ERR;
+        if (fabs(w[a] - w[M - 1 - a]) > 1e-12 * w[a]) return ORC_ERR;
+    }
+    memcpy(s->xi[d], xi, sizeof(double) * M);
+    memcpy(s->w1[d], w, sizeof(double) * M);
+    return emission_tables(s);
+}
+
 orc_state *orc_create(const orc_case *cfg, const unsigned char *solid)
 {
     if (!cfg) return NULL;
@@ -320,40 +389,9 @@ orc_state *orc_create(const orc_case *cfg, const unsigned char *solid)
     s->order = 1;
     s->solid = (unsigned char *)calloc(s->N, 1);
     if (solid) memcpy(s->solid, solid, s->N);
-    const double zero3[3] = {0, 0, 0};
-    int any_solid = 0;
-    for (int id = 0; id < s->N; ++id) any_solid |= s->solid[id];
-    for (int k = 0; k < 7; ++k) {
-        if (k == 6 && !any_solid) continue;
-        const double *u = k < 6 ? cfg->face_u[k] : cfg->solid_u;
-        double T = k < 6 ? cfg->face_T[k] : cfg->solid_T;
-        if (k < 6 && cfg->face_kind[k] == FACE_SPECULAR) continue;
-        if (!(T > 0)) { orc_destroy(s); return NULL; }
-        s->ghat[k] = (double *)malloc(sizeof(double) * s->NV);
-        if (orc_equilibrium(cfg->m, (const double *const *)s->xi,
-                            (const double *const *)s->w1, 1.0, u, T, zero3,
-                            cfg->pr, cfg->correction, s->ghat[k])) {
-            orc_destroy(s);
-            return NULL;
-        }
-        /* emitted-flux normaliser for each possible face orientation */
-        for (int side = 0; side < 6; ++side) {
-            int d = side >> 1;
-            double ns = into_gas_normal_sign(side);
-            double g = 0;
-            for (int c3 = 0; c3 < cfg->m[2]; ++c3)
-                for (int b3 = 0; b3 < cfg->m[1]; ++b3)
-                    for (int a3 = 0; a3 < cfg->m[0]; ++a3) {
-                        int idx[3] = {a3, b3, c3};
-                        double xn = s->xi[d][idx[d]] * ns;
-                        if (xn > 0) {
-                            int al = a3 + cfg->m[0] * (b3 + cfg->m[1] * c3);
-                            double w = s->w1[0][a3] * s->w1[1][b3] * s->w1[2][c3];
-                            g += w * xn * s->ghat[k][al];
-                        }
-                    }
-            s->gout[k][side] = g;
-        }
+    if (emission_tables(s)) {
+        orc_destroy(s);
+        return NULL;
     }
     s->W = (double *)calloc((size_t)5 * s->N, sizeof(double));
     s->q = (double *)calloc((size_t)3 * s->N, sizeof(double));

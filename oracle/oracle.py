@@ -80,6 +80,7 @@ def lib():
         L.orc_num_threads.argtypes = [C.c_void_p]
         L.orc_set_spacing.argtypes = [C.c_void_p, _P, _P, _P]
         L.orc_set_order.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_velocity_axis.argtypes = [C.c_void_p, C.c_int, _P, _P]
         _lib = L
     return _lib
 
@@ -155,6 +156,16 @@ class Oracle:
             self._sp = [None if h is None else np.ascontiguousarray(h, dtype=np.float64) for h in sp3]
             if lib().orc_set_spacing(self._h, *[None if h is None else _ptr(h) for h in self._sp]) != 0:
                 raise ValueError("bad cell sizes")
+        vax = getattr(case, "velocity_axes", None)
+        if vax is not None:
+            self._vax = []
+            for d, ax in enumerate(vax):
+                if ax is None:
+                    continue
+                xi, w = (np.ascontiguousarray(a, dtype=np.float64) for a in ax)
+                self._vax.append((xi, w))
+                if lib().orc_set_velocity_axis(self._h, d, _ptr(xi), _ptr(w)) != 0:
+                    raise ValueError(f"bad velocity axis {d}")
         order = getattr(case, "order", 1)
         if order != 1 and lib().orc_set_order(self._h, order) != 0:
             raise ValueError("second order needs a uniform mesh (order 1 or 2)")

@@ -77,6 +77,9 @@ class Case:
     # spatial order of the upwind scheme: 1 (the paper's), or 2 (linear
     # upwind extrapolation from two upwind cells; uniform meshes only)
     order: int = 1
+    # velocity nodes and quadrature weights per axis, (xi, w) pairs of
+    # length m[d] (None: m[d] uniform nodes on [-vmax, vmax], trapezoid)
+    velocity_axes: Optional[Tuple] = None
 
     @property
     def ncells(self) -> int:
@@ -226,6 +229,42 @@ def cube_paper(n_body: int = 31, n_side: int = 75, n_front: int = 65, n_rear: in
                 faces=[dataclasses.replace(free) for _ in range(6)], closed=False,
                 solid=solid, solid_u=(0.0, 0.0, 0.0), solid_T=1.0,
                 init_rho=1.0, init_u=(u_inf, 0.0, 0.0), init_T=1.0, spacing=(hx, hy, hz))
+
+
+def gauss_hermite_axis(M: int, scale: float = 1.0):
+    """M Gauss-Hermite nodes and weights for integrals over the whole line of
+    functions that decay like exp(-xi^2 / scale^2) (the rest Maxwellian at
+    T = scale^2): nodes scale * x_i, weights scale * w_i * exp(x_i^2), with
+    (x_i, w_i) the rule for the weight exp(-x^2); symmetric about 0."""
+    x, w = np.polynomial.hermite.hermgauss(M)
+    xi = scale * x
+    wt = scale * w * np.exp(x * x)
+    return 0.5 * (xi - xi[::-1]), 0.5 * (wt + wt[::-1])
+
+
+def graded_velocity_axis(M: int, vmax: float, ratio: float):
+    """M nodes on [-vmax, vmax], spaced most finely around 0 and growing
+    geometrically by ``ratio`` towards +-vmax, with trapezoid weights on
+    those nodes."""
+    if M < 2 or ratio <= 0:
+        raise ValueError("need M >= 2 and a positive ratio")
+    half = M // 2
+    gaps = ratio ** np.arange(half, dtype=np.float64)    # outward from the centre
+    if M % 2:
+        pos = np.cumsum(gaps)                            # nodes 0 < ... on the + side
+        pos = pos * (vmax / pos[-1])
+        xi = np.concatenate([-pos[::-1], [0.0], pos])
+    else:
+        g = gaps.copy()
+        g[0] *= 0.5                                      # the two central nodes at +-g0/2
+        pos = np.cumsum(g)
+        pos = pos * (vmax / pos[-1])
+        xi = np.concatenate([-pos[::-1], pos])
+    w = np.empty(M)
+    w[1:-1] = 0.5 * (xi[2:] - xi[:-2])
+    w[0] = 0.5 * (xi[1] - xi[0])
+    w[-1] = 0.5 * (xi[-1] - xi[-2])
+    return xi, 0.5 * (w + w[::-1])
 
 
 # ---- the configurations the benchmark and the parity tests use ------------

@@ -75,6 +75,8 @@ struct dvm_ctx {
     int VL = 2, BX = 4, BY = 4, BZ = 8;
     int PF = 1;  // software-pipelined sweep body
     int order = 1;  // spatial order of the upwind scheme (1 or 2)
+    // velocity nodes and weights per axis (empty: uniform, trapezoid)
+    std::vector<double> vnode[3], vweight[3];
     std::vector<double> h[3];  // cell sizes along x, y, z (empty: uniform)
     std::vector<double> hstage;  // host copy of the uploaded sizes
     bool nonuniform = false;
@@ -366,6 +368,7 @@ std::vector<double> build_lanetab(const dvm_ctx* c, const std::vector<double> xi
             return pos[d] ? c->hsplit[d] + local : c->hsplit[d] - 1 - local;
         };
         auto weight = [&](int d, int a) {
+            if (!c->vweight[d].empty()) return c->vweight[d][a];
             const int M = c->vg.m[d];
             const double h = 2.0 * c->vg.vmax[d] / (M - 1);
             return (a == 0 || a == M - 1) ? 0.5 * h : h;
@@ -653,6 +656,39 @@ dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const
     return DVM_OK;
 }
 
+dvm_status dvm_set_velocity_axes(dvm_ctx* c, const double* xi_x, const double* w_x, const double* xi_y,
+                                 const double* w_y, const double* xi_z, const double* w_z)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "velocity axes must be set before binding the workspace");
+    const double* xs[3] = {xi_x, xi_y, xi_z};
+    const double* ws[3] = {w_x, w_y, w_z};
+    for (int d = 0; d < 3; ++d) {
+        if (!xs[d] != !ws[d]) return fail(DVM_ERR_ARG, "axis %d: give both nodes and weights, or neither", d);
+        if (!xs[d]) continue;
+        const int M = c->vg.m[d];
+        double big = 0;
+        for (int a = 0; a < M; ++a) big = fmax(big, fabs(xs[d][a]));
+        for (int a = 0; a < M; ++a) {
+            if (!isfinite(xs[d][a]) || !(ws[d][a] > 0) || !isfinite(ws[d][a]))
+                return fail(DVM_ERR_ARG, "axis %d: node %d or its weight is invalid", d, a);
+            if (a > 0 && !(xs[d][a] > xs[d][a - 1])) return fail(DVM_ERR_ARG, "axis %d: nodes must increase", d);
+            if (fabs(xs[d][a] + xs[d][M - 1 - a]) > 1e-12 * big || fabs(ws[d][a] - ws[d][M - 1 - a]) > 1e-12 * ws[d][a])
+                return fail(DVM_ERR_ARG, "axis %d: nodes and weights must be symmetric about 0", d);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (xs[d]) {
+            c->vnode[d].assign(xs[d], xs[d] + c->vg.m[d]);
+            c->vweight[d].assign(ws[d], ws[d] + c->vg.m[d]);
+        } else {
+            c->vnode[d].clear();
+            c->vweight[d].clear();
+        }
+    }
+    return DVM_OK;
+}
+
 dvm_status dvm_set_order(dvm_ctx* c, int order)
 {
     if (check_ctx(c)) return DVM_ERR_ARG;
@@ -702,7 +738,8 @@ dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
     c->ws_bytes = bytes;
     hipStream_t st = c->stream;
 
-    // velocity axes (exactly antisymmetric nodes), trapezoid weights
+    // velocity axes: uniform (exactly antisymmetric nodes) with trapezoid
+    // weights, or the nodes and weights given to dvm_set_velocity_axes
     std::vector<double> axes(2 * 3 * MAXM, 0.0);
     std::vector<double> xi[3];
     for (int d = 0; d < 3; ++d) {
@@ -711,9 +748,10 @@ dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
         const double half = V / (M - 1), h = 2.0 * V / (M - 1);
         xi[d].resize(M);
         for (int a = 0; a < M; ++a) {
-            xi[d][a] = (double)(2 * a - (M - 1)) * half;
+            const bool given = !c->vnode[d].empty();
+            xi[d][a] = given ? c->vnode[d][a] : (double)(2 * a - (M - 1)) * half;
             axes[d * MAXM + a] = xi[d][a];
-            axes[3 * MAXM + d * MAXM + a] = (a == 0 || a == M - 1) ? 0.5 * h : h;
+            axes[3 * MAXM + d * MAXM + a] = given ? c->vweight[d][a] : (a == 0 || a == M - 1) ? 0.5 * h : h;
         }
     }
     build_cellinfo(c);

@@ -55,6 +55,17 @@ class Solver:
         if case.spacing is not None:
             self._spacing = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in case.spacing]
             L.check(lib.dvm_set_spacing(h, *[None if a is None else _ptr(a) for a in self._spacing]))
+        if case.velocity_axes is not None:
+            args = []
+            self._vax = []
+            for ax in case.velocity_axes:
+                if ax is None:
+                    args += [None, None]
+                    continue
+                xi, w = (np.ascontiguousarray(a, dtype=np.float64) for a in ax)
+                self._vax.append((xi, w))
+                args += [_ptr(xi), _ptr(w)]
+            L.check(lib.dvm_set_velocity_axes(h, *args))
         if case.order != 1:
             L.check(lib.dvm_set_order(h, int(case.order)))
         nbytes = C.c_size_t()

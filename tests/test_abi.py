@@ -191,3 +191,23 @@ def test_order_arguments(L):
     assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(P), None) == 0
     assert lib.dvm_set_order(h, 2) == -1
     lib.dvm_destroy(h)
+
+
+def test_velocity_axes_arguments(L):
+    import numpy as np
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    case = cases.cavity((6, 5, 4), 10, kn=1.0)
+    h = _ctx(L, case)
+    P = C.POINTER(C.c_double)
+    xi, w = cases.graded_velocity_axis(10, 5.0, 1.2)
+    p = lambda a: np.ascontiguousarray(a).ctypes.data_as(P)
+    keep = [xi, w, xi[::-1].copy(), xi + 0.01, -w]
+    assert lib.dvm_set_velocity_axes(h, p(keep[0]), None, None, None, None, None) == -1
+    assert lib.dvm_set_velocity_axes(h, p(keep[2]), p(keep[1]), None, None, None, None) == -1
+    assert lib.dvm_set_velocity_axes(h, p(keep[3]), p(keep[1]), None, None, None, None) == -1
+    assert b"symmetric" in lib.dvm_last_error()
+    assert lib.dvm_set_velocity_axes(h, p(keep[0]), p(keep[4]), None, None, None, None) == -1
+    assert lib.dvm_set_velocity_axes(h, p(keep[0]), p(keep[1]), None, None, p(keep[0]), p(keep[1])) == 0
+    assert lib.dvm_set_velocity_axes(h, None, None, None, None, None, None) == 0
+    lib.dvm_destroy(h)

@@ -571,3 +571,58 @@ def test_second_order_wall_density_uses_the_face_values(oracle_mod):
     ratios = np.concatenate(ratios)
     # one closed-domain mass factor for every wall cell, close to 1
     assert np.abs(ratios - ratios[0]).max() < 1e-12 and abs(ratios[0] - 1) < 0.05
+
+
+# ------------------------------------------------ non-uniform velocity axes
+
+def test_explicit_uniform_velocity_axes_change_nothing(oracle_mod):
+    case = cases.cavity((5, 4, 6), 9, kn=0.5, lid=0.3)
+    ax = tuple(oracle_mod.velocity_axis(case.m[d], case.vmax[d]) for d in range(3))
+    a, b = oracle_mod.Oracle(case), oracle_mod.Oracle(dataclasses.replace(case, velocity_axes=ax))
+    for o in (a, b):
+        o.init_uniform()
+        o.iterate(2)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("M", [8, 10])
+def test_gauss_hermite_axes_keep_the_rest_state_without_correction(oracle_mod, M):
+    """Without the conservative correction the rest equilibrium between
+    resting walls is steady only if the quadrature reproduces its density
+    and energy: Gauss-Hermite nodes do so exactly (to rounding), the same
+    number of uniform trapezoid nodes over the same range does not."""
+    gh = cases.gauss_hermite_axis(M)
+    base = dataclasses.replace(cases.cavity((5, 4, 6), M, kn=0.8, lid=0.0, vmax=float(gh[0].max())),
+                               correction=False)
+    drift = {}
+    for name, vax in (("trapezoid", None), ("gauss_hermite", (gh, gh, gh))):
+        o = oracle_mod.Oracle(dataclasses.replace(base, velocity_axes=vax))
+        o.init_uniform(1.0, (0, 0, 0), 1.0)
+        W0 = o.state()[0].copy()
+        o.iterate(2)
+        drift[name] = np.abs(o.state()[0] - W0).max()
+    assert drift["gauss_hermite"] < 1e-13 and drift["trapezoid"] > 1e-6, drift
+
+
+def test_velocity_axis_validation(oracle_mod):
+    case = cases.cavity(4, 6, kn=1.0)
+    xi, w = cases.graded_velocity_axis(6, 4.0, 1.3)
+    for bad in ((xi[::-1], w), (xi + 0.1, w), (xi, -w), (xi, w * np.arange(1, 7))):
+        with pytest.raises(ValueError):
+            oracle_mod.Oracle(dataclasses.replace(case, velocity_axes=(bad, None, None)))
+    o = oracle_mod.Oracle(dataclasses.replace(case, velocity_axes=((xi, w), (xi, w), None)))
+    o.init_uniform()
+    o.iterate(1)
+
+
+def test_graded_and_gauss_hermite_axes():
+    xi, w = cases.graded_velocity_axis(9, 5.0, 1.2)
+    assert xi[4] == 0 and np.allclose(xi, -xi[::-1]) and abs(w.sum() - 10.0) < 1e-12
+    gaps = np.diff(xi[4:])
+    assert np.allclose(gaps[1:] / gaps[:-1], 1.2)
+    x, g = cases.gauss_hermite_axis(12, 1.3)
+    # exact for polynomial moments of the Maxwellian at T = 1.3^2
+    f = np.exp(-(x / 1.3) ** 2)
+    assert abs((g * f).sum() - 1.3 * math.sqrt(math.pi)) < 1e-13
+    assert abs((g * x ** 4 * f).sum() - 0.75 * 1.3 ** 5 * math.sqrt(math.pi)) < 1e-12
