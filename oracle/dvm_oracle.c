@@ -24,6 +24,9 @@
  *     paper's closing section proposes (three consecutive cells per axis:
  *     each face carries the upwind cell's value extrapolated linearly from
  *     that cell and its own upwind neighbour), uniform meshes only;
+ *   - optionally (orc_set_model) the ES-BGK model in place of Shakhov's:
+ *     an anisotropic Gaussian built from the stress of the iterate,
+ *     relaxing with frequency Pr p / mu, corrected the same way;
  *   - the discrete moments of eq. "macros" of the new f.  The heat flux uses
  *     the NEW bulk velocity U^{n+1}, so each velocity is swept twice: once for
  *     rho, rho U, rho E and the wall fluxes, once for q (the sweep is a
@@ -99,6 +102,10 @@ typedef struct {
     int iter;
     int order;              /* 1: first-order upwind (the paper's scheme);
                                2: second-order upwind (Sec. 6 outlook)    */
+    int model;              /* 0: Shakhov (the paper's), 1: ES-BGK         */
+    double *P;              /* 6 x N: Theta = (1/rho) sum w c c f, the
+                               stress of the current iterate per unit mass
+                               (xx, yy, zz, xy, xz, yz; ES-BGK only)      */
 } orc_state;
 
 /* ----------------------------------------------------------------------- */
@@ -169,6 +176,53 @@ static int spd_solve5(double A[5][5], double b[5], double x[5])
  * i.e. the discrete mass, momentum and energy of f~ are exactly those the
  * state (rho, U, T) was computed from.  All sums run over the full grid.
  */
+/* ES-BGK (Holway's ellipsoidal statistical model; the paper states that the
+   scheme applies to other model equations than Shakhov's, Sec. 2.1).  In the
+   normalised units (R T = T/2) its Gaussian is
+     G = rho (2 pi)^{-3/2} det(Lam)^{-1/2} exp(-c^T Lam^{-1} c / 2),
+     Lam = (T/2) I / Pr + (1 - 1/Pr) Theta,
+   Theta the stress per unit mass; it relaxes with frequency Pr p / mu, so
+   that both the viscosity and the Prandtl number are those of the gas.     */
+static int es_tensor(double T, const double th[6], double pr, double inv[6], double *det)
+{
+    /* Lam in (xx, yy, zz, xy, xz, yz) order */
+    double L[6];
+    for (int k = 0; k < 6; ++k) L[k] = (1.0 - 1.0 / pr) * th[k];
+    for (int k = 0; k < 3; ++k) L[k] += 0.5 * T / pr;
+    const double a = L[0], b = L[1], c = L[2], d = L[3], e = L[4], f = L[5];
+    /* cofactors of the symmetric matrix [[a d e] [d b f] [e f c]] */
+    const double A = b * c - f * f, B = a * c - e * e, C = a * b - d * d;
+    const double D = e * f - d * c, E = d * f - e * b, F = d * e - a * f;
+    const double dt = a * A + d * D + e * E;
+    if (!(dt > 0) || !(A > 0) || !(C > 0)) return ORC_ERR;   /* not positive definite */
+    inv[0] = A / dt; inv[1] = B / dt; inv[2] = C / dt;
+    inv[3] = D / dt; inv[4] = E / dt; inv[5] = F / dt;
+    *det = dt;
+    return ORC_OK;
+}
+
+static double es_exponent(const double inv[6], double cx, double cy, double cz)
+{
+    return 0.5 * (inv[0] * cx * cx + inv[1] * cy * cy + inv[2] * cz * cz) +
+           inv[3] * cx * cy + inv[4] * cx * cz + inv[5] * cy * cz;
+}
+
+/* The ES-BGK Gaussian (no correction) on the velocity grid. */
+int orc_esbgk_gaussian(const int m[3], const double *const xi[3], double rho, const double U[3],
+                       double T, const double theta[6], double pr, double *out)
+{
+    double inv[6], det;
+    if (!(rho > 0) || !(T > 0) || es_tensor(T, theta, pr, inv, &det)) return ORC_ERR;
+    const double pre = rho * pow(2.0 * M_PI, -1.5) / sqrt(det);
+    for (int c3 = 0; c3 < m[2]; ++c3)
+        for (int b3 = 0; b3 < m[1]; ++b3)
+            for (int a3 = 0; a3 < m[0]; ++a3) {
+                int al = a3 + m[0] * (b3 + m[1] * c3);
+                out[al] = pre * exp(-es_exponent(inv, xi[0][a3] - U[0], xi[1][b3] - U[1], xi[2][c3] - U[2]));
+            }
+    return ORC_OK;
+}
+
 int orc_equilibrium(const int m[3], const double *const xi[3],
                     const double *const w1[3], double rho, const double U[3],
                     double T, const double qv[3], double pr, int correct,
@@ -244,7 +298,7 @@ void orc_destroy(orc_state *s)
     if (!s) return;
     for (int d = 0; d < 3; ++d) { free(s->xi[d]); free(s->w1[d]); free(s->h[d]); }
     for (int k = 0; k < 7; ++k) free(s->ghat[k]);
-    free(s->solid); free(s->W); free(s->q); free(s->rho_w);
+    free(s->solid); free(s->W); free(s->q); free(s->rho_w); free(s->P);
     free(s);
 }
 
@@ -285,6 +339,20 @@ int orc_set_order(orc_state *s, int order)
                 if (fabs(s->h[d][i] - s->dx[d]) > 1e-12 * s->dx[d]) return ORC_ERR;
     }
     s->order = order;
+    return ORC_OK;
+}
+
+/* Collision model: 0 Shakhov (default), 1 ES-BGK. */
+int orc_set_model(orc_state *s, int model)
+{
+    if (model != 0 && model != 1) return ORC_ERR;
+    s->model = model;
+    return ORC_OK;
+}
+
+int orc_get_stress(const orc_state *s, double *P)
+{
+    memcpy(P, s->P, sizeof(double) * 6 * s->N);
     return ORC_OK;
 }
 
@@ -396,6 +464,7 @@ orc_state *orc_create(const orc_case *cfg, const unsigned char *solid)
     s->W = (double *)calloc((size_t)5 * s->N, sizeof(double));
     s->q = (double *)calloc((size_t)3 * s->N, sizeof(double));
     s->rho_w = (double *)calloc((size_t)6 * s->N, sizeof(double));
+    s->P = (double *)calloc((size_t)6 * s->N, sizeof(double));
     return s;
 }
 
@@ -430,6 +499,7 @@ static int kind_is_wall(const orc_state *s, int kind)
 
 typedef struct {
     double *rho, *U, *T, *nu, *q;   /* per cell */
+    double *esinv, *espre;           /* ES-BGK: Lam^{-1} (6) and prefactor */
 } cellprm;
 
 /* One upwind sweep of discrete velocity al (eq. "sweeping_example" in the
@@ -536,6 +606,11 @@ int orc_init_fields(orc_state *s, const double *rho, const double *u,
                            0.75 * rho[id] * T[id];
     }
     memset(s->q, 0, sizeof(double) * 3 * N);
+    /* equilibrium stress per unit mass: (T/2) I */
+    memset(s->P, 0, sizeof(double) * 6 * N);
+    for (int id = 0; id < N; ++id)
+        if (!s->solid[id])
+            for (int k = 0; k < 3; ++k) s->P[k * N + id] = 0.5 * T[id];
     double m0 = 0;
     for (int id = 0; id < N; ++id) if (!s->solid[id]) m0 += s->W[id] * cell_volume(s, id);
     s->M0 = m0;
@@ -620,6 +695,14 @@ static int cell_params(const orc_state *s, cellprm *p)
         }
         double tau = kap * s->c.kn * pow(T, s->c.omega - 1.0) / r;
         p->nu[id] = 1.0 / tau;
+        if (s->model == 1) {
+            /* ES-BGK relaxes with Pr p / mu */
+            p->nu[id] = s->c.pr / tau;
+            double th[6], det;
+            for (int k = 0; k < 6; ++k) th[k] = s->P[k * N + id];
+            if (es_tensor(T, th, s->c.pr, p->esinv + 6 * (size_t)id, &det)) return ORC_ERR;
+            p->espre[id] = r * pow(2.0 * M_PI, -1.5) / sqrt(det);
+        }
     }
     return ORC_OK;
 }
@@ -637,10 +720,16 @@ static void velocity_feq(const orc_state *s, const cellprm *p, const double *lam
         double cy = s->xi[1][b3] - p->U[N + id];
         double cz = s->xi[2][c3] - p->U[2 * N + id];
         double c2 = cx * cx + cy * cy + cz * cz;
-        double fm = rho * pow(M_PI * T, -1.5) * exp(-c2 / T);
-        double cq = cx * p->q[id] + cy * p->q[N + id] + cz * p->q[2 * N + id];
-        double sig = (1.0 - pr) * 4.0 / (5.0 * rho * T * T);
-        double v = fm * (1.0 + sig * cq * (2.0 * c2 / T - 5.0));
+        double fm, v;
+        if (s->model == 1) {
+            fm = p->espre[id] * exp(-es_exponent(p->esinv + 6 * (size_t)id, cx, cy, cz));
+            v = fm;
+        } else {
+            fm = rho * pow(M_PI * T, -1.5) * exp(-c2 / T);
+            double cq = cx * p->q[id] + cy * p->q[N + id] + cz * p->q[2 * N + id];
+            double sig = (1.0 - pr) * 4.0 / (5.0 * rho * T * T);
+            v = fm * (1.0 + sig * cq * (2.0 * c2 / T - 5.0));
+        }
         if (lam) {
             const double *L = lam + 5 * (size_t)id;
             v += fm * (L[0] + L[1] * cx + L[2] * cy + L[3] * cz + L[4] * c2);
@@ -672,9 +761,16 @@ static int cell_lambdas(const orc_state *s, const cellprm *p, double *lam)
                     double cy = s->xi[1][b3] - U[1];
                     double cz = s->xi[2][c3] - U[2];
                     double c2 = cx * cx + cy * cy + cz * cz;
-                    double fm = pre * exp(-c2 / T);
-                    double cq = cx * qv[0] + cy * qv[1] + cz * qv[2];
-                    double fs = fm * (1.0 + sig * cq * (2.0 * c2 / T - 5.0));
+                    double fm, fs;
+                    if (s->model == 1) {
+                        /* correct the ES-BGK Gaussian with the same basis */
+                        fm = p->espre[id] * exp(-es_exponent(p->esinv + 6 * (size_t)id, cx, cy, cz));
+                        fs = fm;
+                    } else {
+                        fm = pre * exp(-c2 / T);
+                        double cq = cx * qv[0] + cy * qv[1] + cz * qv[2];
+                        fs = fm * (1.0 + sig * cq * (2.0 * c2 / T - 5.0));
+                    }
                     double w = s->w1[0][a3] * s->w1[1][b3] * s->w1[2][c3];
                     double phi[5] = {1.0, cx, cy, cz, c2};
                     for (int l = 0; l < 5; ++l) {
@@ -718,11 +814,13 @@ int orc_iterate(orc_state *s)
     p.nu = (double *)malloc(sizeof(double) * N);
     p.U = (double *)malloc(sizeof(double) * 3 * N);
     p.q = (double *)malloc(sizeof(double) * 3 * N);
+    p.esinv = (double *)malloc(sizeof(double) * 6 * N);
+    p.espre = (double *)malloc(sizeof(double) * N);
     double *lam = c->correction ? (double *)malloc(sizeof(double) * 5 * (size_t)N) : NULL;
     int err = cell_params(s, &p);
     if (!err && lam) err = cell_lambdas(s, &p, lam);
     if (err) {
-        free(p.rho); free(p.T); free(p.nu); free(p.U); free(p.q); free(lam);
+        free(p.rho); free(p.T); free(p.nu); free(p.U); free(p.q); free(p.esinv); free(p.espre); free(lam);
         return ORC_ERR;
     }
     int spec = has_specular(s);
@@ -736,6 +834,7 @@ int orc_iterate(orc_state *s)
     double *Wn = (double *)malloc(sizeof(double) * 5 * N);
     double *qn = (double *)malloc(sizeof(double) * 3 * N);
     double *flux = (double *)malloc(sizeof(double) * 6 * N);
+    double *Pn = (double *)calloc((size_t)6 * N, sizeof(double));
 
     for (int pass = 0; pass < 2; ++pass) {
         memset(acc, 0, sizeof(double) * (size_t)nth * 11 * N);
@@ -808,6 +907,13 @@ int orc_iterate(orc_state *s)
                                     A[0 * N + id] += 0.5 * cx * cc * wf;
                                     A[1 * N + id] += 0.5 * cy * cc * wf;
                                     A[2 * N + id] += 0.5 * cz * cc * wf;
+                                    /* the stress about the new bulk velocity */
+                                    A[3 * N + id] += cx * cx * wf;
+                                    A[4 * N + id] += cy * cy * wf;
+                                    A[5 * N + id] += cz * cz * wf;
+                                    A[6 * N + id] += cx * cy * wf;
+                                    A[7 * N + id] += cx * cz * wf;
+                                    A[8 * N + id] += cy * cz * wf;
                                 }
                             }
                 }
@@ -815,7 +921,7 @@ int orc_iterate(orc_state *s)
             }
         }
         /* fixed-order reduction over threads */
-        int nv = pass == 0 ? 11 : 3;
+        int nv = pass == 0 ? 11 : 9;
         for (int v = 0; v < nv; ++v)
             for (int id = 0; id < N; ++id) {
                 double t = 0;
@@ -823,8 +929,10 @@ int orc_iterate(orc_state *s)
                 if (pass == 0) {
                     if (v < 5) Wn[v * N + id] = t;
                     else flux[(v - 5) * N + id] = t;
-                } else {
+                } else if (v < 3) {
                     qn[v * N + id] = t;
+                } else {
+                    Pn[(v - 3) * N + id] = (s->solid[id] || !(Wn[id] > 0)) ? 0.0 : t / Wn[id];
                 }
             }
         if (pass == 0) {
@@ -870,12 +978,13 @@ int orc_iterate(orc_state *s)
         }
         memcpy(s->W, Wn, sizeof(double) * 5 * N);
         memcpy(s->q, qn, sizeof(double) * 3 * N);
+        memcpy(s->P, Pn, sizeof(double) * 6 * N);
         memcpy(s->rho_w, rw, sizeof(double) * 6 * N);
         free(rw);
         s->iter++;
     }
-    free(acc); free(Wn); free(qn); free(flux); free(specbuf);
-    free(p.rho); free(p.T); free(p.nu); free(p.U); free(p.q); free(lam);
+    free(acc); free(Wn); free(qn); free(flux); free(specbuf); free(Pn);
+    free(p.rho); free(p.T); free(p.nu); free(p.U); free(p.q); free(p.esinv); free(p.espre); free(lam);
     return err ? ORC_ERR : ORC_OK;
 }
 
@@ -907,6 +1016,13 @@ int orc_set_state(orc_state *s, const double *W, const double *q,
     memcpy(s->q, q, sizeof(double) * 3 * N);
     memcpy(s->rho_w, rho_w, sizeof(double) * 6 * N);
     s->M0 = M0;
+    /* the stress restarts at the equilibrium of the given state */
+    memset(s->P, 0, sizeof(double) * 6 * N);
+    for (int id = 0; id < N; ++id) {
+        double r, U[3], T;
+        if (s->solid[id] || primitives(s->W, N, id, &r, U, &T)) continue;
+        for (int k = 0; k < 3; ++k) s->P[k * N + id] = 0.5 * T;
+    }
     return ORC_OK;
 }
 
@@ -960,6 +1076,8 @@ int orc_sweep_one(const orc_state *s, int al, const double *spec_mirror,
     p.nu = (double *)malloc(sizeof(double) * N);
     p.U = (double *)malloc(sizeof(double) * 3 * N);
     p.q = (double *)malloc(sizeof(double) * 3 * N);
+    p.esinv = (double *)malloc(sizeof(double) * 6 * N);
+    p.espre = (double *)malloc(sizeof(double) * N);
     double *lam = c->correction ? (double *)malloc(sizeof(double) * 5 * (size_t)N) : NULL;
     int err = cell_params(s, &p);
     if (!err && lam) err = cell_lambdas(s, &p, lam);
@@ -976,7 +1094,7 @@ int orc_sweep_one(const orc_state *s, int al, const double *spec_mirror,
         if (nu_out) memcpy(nu_out, p.nu, sizeof(double) * N);
         free(feq);
     }
-    free(p.rho); free(p.T); free(p.nu); free(p.U); free(p.q); free(lam);
+    free(p.rho); free(p.T); free(p.nu); free(p.U); free(p.q); free(p.esinv); free(p.espre); free(lam);
     return err ? ORC_ERR : ORC_OK;
 }
 

@@ -81,6 +81,10 @@ def lib():
         L.orc_set_spacing.argtypes = [C.c_void_p, _P, _P, _P]
         L.orc_set_order.argtypes = [C.c_void_p, C.c_int]
         L.orc_set_velocity_axis.argtypes = [C.c_void_p, C.c_int, _P, _P]
+        L.orc_set_model.argtypes = [C.c_void_p, C.c_int]
+        L.orc_get_stress.argtypes = [C.c_void_p, _P]
+        L.orc_esbgk_gaussian.argtypes = [C.POINTER(C.c_int), C.POINTER(_P), C.c_double, _P, C.c_double,
+                                         _P, C.c_double, _P]
         _lib = L
     return _lib
 
@@ -116,6 +120,21 @@ def equilibrium(m, vmax, rho, U, T, q=(0.0, 0.0, 0.0), pr=2.0 / 3.0, correct=Tru
     st = lib().orc_equilibrium(mm, XI, WW, rho, _ptr(U), T, _ptr(q), pr, int(correct), _ptr(out))
     if st != 0:
         raise ValueError("non-physical equilibrium state")
+    return out.reshape(m[2], m[1], m[0])
+
+
+def esbgk_gaussian(m, vmax, rho, U, T, theta, pr=2.0 / 3.0):
+    """The ES-BGK Gaussian (no correction) for stress per unit mass theta
+    (xx, yy, zz, xy, xz, yz) on the uniform velocity grid, [mz, my, mx]."""
+    axes = [velocity_axis(m[d], vmax[d]) for d in range(3)]
+    xis = [np.ascontiguousarray(a[0]) for a in axes]
+    XI = (_P * 3)(*[_ptr(x) for x in xis])
+    mm = (C.c_int * 3)(*m)
+    out = np.empty(m[0] * m[1] * m[2])
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if lib().orc_esbgk_gaussian(mm, XI, rho, _ptr(U), T, _ptr(th), pr, _ptr(out)) != 0:
+        raise ValueError("non-physical ES-BGK state")
     return out.reshape(m[2], m[1], m[0])
 
 
@@ -166,6 +185,10 @@ class Oracle:
                 self._vax.append((xi, w))
                 if lib().orc_set_velocity_axis(self._h, d, _ptr(xi), _ptr(w)) != 0:
                     raise ValueError(f"bad velocity axis {d}")
+        model = getattr(case, "model", "shakhov")
+        if model != "shakhov":
+            if model != "esbgk" or lib().orc_set_model(self._h, 1) != 0:
+                raise ValueError(f"unknown model {model}")
         order = getattr(case, "order", 1)
         if order != 1 and lib().orc_set_order(self._h, order) != 0:
             raise ValueError("second order needs a uniform mesh (order 1 or 2)")
@@ -223,6 +246,13 @@ class Oracle:
         rho = np.empty(N); u = np.empty((3, N)); T = np.empty(N); q = np.empty((3, N))
         lib().orc_get_fields(self._h, _ptr(rho), _ptr(u), _ptr(T), _ptr(q))
         return {"rho": rho, "u": u, "T": T, "q": q}
+
+    def stress(self):
+        """ES-BGK: the stress per unit mass of the current iterate, 6 x N
+        (xx, yy, zz, xy, xz, yz)."""
+        P = np.empty((6, self.N))
+        lib().orc_get_stress(self._h, _ptr(P))
+        return P
 
     def total_mass(self) -> float:
         return lib().orc_total_mass(self._h)

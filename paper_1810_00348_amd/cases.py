@@ -80,6 +80,9 @@ class Case:
     # velocity nodes and quadrature weights per axis, (xi, w) pairs of
     # length m[d] (None: m[d] uniform nodes on [-vmax, vmax], trapezoid)
     velocity_axes: Optional[Tuple] = None
+    # collision model: "shakhov" (the paper's) or "esbgk" (ellipsoidal
+    # statistical BGK: anisotropic Gaussian, relaxation frequency Pr p / mu)
+    model: str = "shakhov"
 
     @property
     def ncells(self) -> int:

@@ -626,3 +626,65 @@ def test_graded_and_gauss_hermite_axes():
     f = np.exp(-(x / 1.3) ** 2)
     assert abs((g * f).sum() - 1.3 * math.sqrt(math.pi)) < 1e-13
     assert abs((g * x ** 4 * f).sum() - 0.75 * 1.3 ** 5 * math.sqrt(math.pi)) < 1e-12
+
+
+# ------------------------------------------------------------- ES-BGK
+
+def test_esbgk_gaussian_has_the_prescribed_moments(oracle_mod):
+    """On a fine wide grid the ES-BGK Gaussian has mass rho, mean U and
+    second central moments rho Lam with Lam = (T/2) I / Pr + (1 - 1/Pr) Theta,
+    T = (2/3) tr Theta (normalised units, R T = T/2)."""
+    th = np.array([0.6, 0.45, 0.5, 0.05, -0.03, 0.02])
+    T = 2.0 / 3.0 * th[:3].sum()
+    rho, U, pr = 1.3, np.array([0.2, -0.1, 0.3]), 2.0 / 3.0
+    m, V = (40, 40, 40), (7.0, 7.0, 7.0)
+    G = oracle_mod.esbgk_gaussian(m, V, rho, U, T, th, pr)
+    xi, w = oracle_mod.velocity_axis(40, 7.0)
+    Z, Y, X = np.meshgrid(xi, xi, xi, indexing="ij")
+    W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    c = (X - U[0], Y - U[1], Z - U[2])
+    Th = np.array([[th[0], th[3], th[4]], [th[3], th[1], th[5]], [th[4], th[5], th[2]]])
+    Lam = 0.5 * T / pr * np.eye(3) + (1 - 1 / pr) * Th
+    assert abs((W * G).sum() - rho) < 1e-12
+    for i in range(3):
+        assert abs((W * G * c[i]).sum()) < 1e-12
+        for j in range(3):
+            assert abs((W * G * c[i] * c[j]).sum() / rho - Lam[i, j]) < 1e-12, (i, j)
+    # an isotropic stress gives the Maxwellian
+    M = oracle_mod.esbgk_gaussian(m, V, rho, U, T, [T / 2, T / 2, T / 2, 0, 0, 0], pr)
+    c2 = c[0] ** 2 + c[1] ** 2 + c[2] ** 2
+    assert np.abs(M - rho * (math.pi * T) ** -1.5 * np.exp(-c2 / T)).max() < 1e-14
+
+
+def test_esbgk_at_unit_prandtl_number_is_bgk(oracle_mod):
+    base = cases.cavity((6, 5, 4), 10, kn=0.5, lid=0.3, pr=1.0)
+    a, b = oracle_mod.Oracle(base), oracle_mod.Oracle(dataclasses.replace(base, model="esbgk"))
+    for o in (a, b):
+        o.init_uniform()
+        o.iterate(3)
+    for x, y in zip(a.state(), b.state()):
+        assert np.abs(x - y).max() < 1e-13
+
+
+def test_esbgk_rest_state_and_stress_trace(oracle_mod):
+    rest = dataclasses.replace(cases.cavity((5, 4, 6), 8, kn=0.8, lid=0.0), model="esbgk")
+    o = oracle_mod.Oracle(rest)
+    o.init_uniform(1.0, (0, 0, 0), 1.0)
+    W0 = o.state()[0]
+    o.iterate(2)
+    assert np.abs(o.state()[0] - W0).max() < 1e-14
+    # driven cavity: the stored stress is the second moment about the new
+    # bulk velocity, so its trace is 3 T / 2 of the new state
+    case = dataclasses.replace(cases.cavity((6, 5, 4), 10, kn=0.5, lid=0.3), model="esbgk")
+    o = oracle_mod.Oracle(case)
+    o.init_fields(*cases.random_fields(case, seed=4))
+    o.iterate(2)
+    P = o.stress()
+    T = o.fields()["T"]
+    assert np.abs(P[:3].sum(axis=0) - 1.5 * T).max() < 1e-13
+    assert np.abs(P[3:]).max() > 1e-4      # shear develops
+    # and it differs from the Shakhov iterate at the same Prandtl number
+    s = oracle_mod.Oracle(dataclasses.replace(case, model="shakhov"))
+    s.init_fields(*cases.random_fields(case, seed=4))
+    s.iterate(2)
+    assert np.abs(s.fields()["u"][0] - o.fields()["u"][0]).max() > 1e-6
