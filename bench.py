@@ -257,6 +257,8 @@ def main():
                     help="solve the workload from the uniform start for up to ITERS iterations "
                          "(or to --tol), one progress line per iteration")
     ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--model", default="shakhov", choices=("shakhov", "esbgk"),
+                    help="collision model (esbgk: the ellipsoidal statistical BGK model)")
     ap.add_argument("--order", type=int, default=1, choices=(1, 2),
                     help="spatial order of the upwind sweep (2: the second-order extension)")
     ap.add_argument("--stretch", type=float, default=0.0,
@@ -304,9 +306,10 @@ def main():
         from paper_1810_00348_amd import cases as _cases
         centres = (None, None, None) if args.workload != "c4" else (2.5, 3.0, None)
         case = _cases.stretched(case, args.stretch, centres)
-    if args.order != 1:
+    if args.order != 1 or args.model != "shakhov":
         import dataclasses as _dc
-        case = _dc.replace(case, order=args.order, name=case.name + f"_order{args.order}")
+        tag = (f"_order{args.order}" if args.order != 1 else "") + ("_esbgk" if args.model != "shakhov" else "")
+        case = _dc.replace(case, order=args.order, model=args.model, name=case.name + tag)
     if args.solve > 0:
         solve(case, prec, args.solve, args.tol, describe(args.workload, case))
         return
@@ -340,6 +343,8 @@ def main():
         label += f"_stretch{args.stretch:g}"
     if args.order != 1:
         label += f"_order{args.order}"
+    if args.model != "shakhov":
+        label += f"_{args.model}"
     line = {
         "metric": "phase-space GPoint-updates/s per iteration",
         "value": round(value, 3),
@@ -357,6 +362,7 @@ def main():
             "workload": describe(args.workload, case),
             "velocity_groups": info["velocity_groups"],
             "upwind_order": case.order,
+            "model": case.model,
             "points_per_iteration": pts,
             "brick": info["brick"],
             "vel_per_lane": info["vel_per_lane"],

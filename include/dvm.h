@@ -134,6 +134,25 @@ dvm_status dvm_set_closed(dvm_ctx* ctx, int closed);
    DVM_ERR_ARG for bad sizes. */
 dvm_status dvm_set_spacing(dvm_ctx* ctx, const double* hx, const double* hy, const double* hz);
 
+/* Collision model: 0 Shakhov (default; Sec. 2.1), 1 ES-BGK -- the scheme
+   applies to other model equations too (Sec. 2.1).  ES-BGK target: the
+   Gaussian G = rho (2 pi)^{-3/2} det(Lam)^{-1/2} exp(-c^T Lam^{-1} c / 2)
+   with Lam = (T/2) I / Pr + (1 - 1/Pr) Theta (normalised units, R T = T/2),
+   Theta the stress per unit mass of the iterate (kept as state, computed
+   with the other moments about U^{n+1}), relaxation frequency Pr p / mu,
+   the same conservative correction.  Needs Pr >= 2/3 (Lam positive
+   definite) and a uniform mesh; the sweep has one exponential per phase-
+   space point more, the parameter pass one pass over the velocity set per
+   cell.  The stress starts (dvm_init_*) and restarts (dvm_set_state) at
+   the equilibrium (T/2) I of the state.  Before binding the workspace
+   (DVM_ERR_STATE after it); DVM_ERR_ARG otherwise. */
+dvm_status dvm_set_model(dvm_ctx* ctx, int model);
+
+/* ES-BGK: the stress per unit mass of the current iterate, 6 x ncells
+   doubles (xx, yy, zz, xy, xz, yz), into a host array.  DVM_ERR_STATE for
+   the Shakhov model or before an initial state. */
+dvm_status dvm_get_stress(dvm_ctx* ctx, double* stress);
+
 /* Velocity nodes and quadrature weights per axis (m[d] values each, host
    arrays copied by the call) in place of the uniform trapezoid axes -- the
    non-uniform velocity grids the paper recommends over very large uniform

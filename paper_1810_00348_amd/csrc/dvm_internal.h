@@ -23,7 +23,7 @@ enum {
     P_UX, P_UY, P_UZ,
     P_L0,       // 1 + lambda_0
     P_L1, P_L2, P_L3, P_L4,
-    P_QX, P_QY, P_QZ,  // sigma * q
+    P_QX, P_QY, P_QZ,  // sigma * q (ES-BGK: the off-diagonal Lam^{-1} entries xy, xz, yz)
     P_TWO_T,    // 2 / T
     P_INFO,     // the cell info word (bit pattern in the slot's low 32 bits)
     P_IDX,      // 1 / cell size along x (non-uniform meshes)
@@ -55,6 +55,7 @@ struct Consts {
     int correct;
     int closed;
     int order2;           // second-order upwind: wall fluxes take the face values
+    int esbgk;            // ES-BGK model in place of Shakhov's
     double kind_rho[8];   // fixed emission density (free stream), per kind
     int kind_wall[8];     // 1: density from non-penetration
 };
@@ -102,6 +103,9 @@ struct SweepArgs {
 hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, const double* q,
                          const double* rho_w, void* params, void* etab, int prec, int* flag,
                          hipStream_t st);
+// ES-BGK parameters from the conserved moments and the stress per unit mass
+hipError_t launch_params_es(const Consts& C, const DevPtrs& D, const double* W, const double* stress,
+                            const double* rho_w, void* params, void* etab, int prec, int* flag, hipStream_t st);
 hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind_state /*[NKIND][4]*/,
                            int nkind, void* ghat, double* ghat64, double* gout, int prec,
                            hipStream_t st);
@@ -109,9 +113,9 @@ hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* param
                             const double* ghat64, const double* gout, double* rho_w, int prec,
                             hipStream_t st);
 hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, int order2,
-                        const void* args, hipStream_t st);
+                        int esbgk, const void* args, hipStream_t st);
 hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
-                           const double* gout, double* Wn, double* qn, double* rwn,
+                           const double* gout, double* Wn, double* qn, double* rwn, double* stress_n,
                            double* blockmass, int nblocks, int* flag, hipStream_t st);
 hipError_t launch_scale_residual(const Consts& C, const DevPtrs& D, double M0,
                                  const double* blockmass, int nbm, double* Wn, double* qn,
@@ -122,6 +126,6 @@ hipError_t launch_residual_final(const double* respart, int nblocks, const doubl
 // acc[o][cell] (= or +=) sum over the ntiles records partial[o*ntiles + t][cell]
 hipError_t launch_fold(const double* partial, int ntiles, int N, int add, double* acc, hipStream_t st);
 hipError_t launch_selftest_reduce(const double* in, double* out, hipStream_t st);
-bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2 = 0);
+bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2 = 0, int esbgk = 0);
 
 }  // namespace dvm

@@ -254,6 +254,152 @@ hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, con
     return hipGetLastError();
 }
 
+// ES-BGK (the ellipsoidal statistical model; the scheme applies to model
+// equations other than Shakhov's, Sec. 2.1).  In the normalised units
+// (R T = T/2) the target is the Gaussian
+//   G = rho (2 pi)^{-3/2} det(Lam)^{-1/2} exp(-c^T Lam^{-1} c / 2),
+//   Lam = (T/2) I / Pr + (1 - 1/Pr) Theta,  Theta = the stress per unit mass,
+// relaxing with frequency Pr p / mu.  Its diagonal factors go to the tables
+// (z scaled by nu * prefactor); the off-diagonal entries of Lam^{-1} to the
+// cell record, for the cross factor exp(-(A_xy cx cy + A_xz cx cz + A_yz cy cz))
+// the sweep takes per point.  The correction multipliers need the discrete
+// moments of G, which does not factor over the axes: one pass over the whole
+// velocity set per cell (one exponential per node).
+template <typename S>
+__global__ __launch_bounds__(128) void params_es_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
+                                                        const double* __restrict__ stress,
+                                                        const double* __restrict__ rho_w,
+                                                        S* __restrict__ params, S* __restrict__ etab,
+                                                        int* __restrict__ flag)
+{
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= C.N) return;
+    const uint32_t info = D.cellinfo[cell];
+    S* P = params + (size_t)cell * PSTRIDE;
+    reinterpret_cast<uint32_t*>(P + P_INFO)[0] = info;
+    if (info & SOLID_BIT) return;
+    {
+        const int i = cell % C.nx, j = (cell / C.nx) % C.ny, k = cell / (C.nx * C.ny);
+        P[P_IDX] = (S)(1.0 / D.h[i]);
+        P[P_IDY] = (S)(1.0 / D.h[C.nx + j]);
+        P[P_IDZ] = (S)(1.0 / D.h[C.nx + C.ny + k]);
+        for (int s = 0; s < 6; ++s) {
+            const uint32_t code = (info >> (4 * s)) & 15u;
+            double rf = 0.0;
+            if (code != 0 && code != CODE_SPECULAR)
+                rf = C.kind_wall[code - 1] ? rho_w[(size_t)s * C.N + cell] : C.kind_rho[code - 1];
+            P[P_RHO_SIDE + s] = (S)rf;
+        }
+    }
+    const int N = C.N;
+    S* E = etab + (size_t)cell * C.MT;
+    const double rho = W[cell];
+    const double Ux = W[N + cell] / rho, Uy = W[2 * N + cell] / rho, Uz = W[3 * N + cell] / rho;
+    const double T = (W[4 * N + cell] - 0.5 * rho * (Ux * Ux + Uy * Uy + Uz * Uz)) / (0.75 * rho);
+    // Lam = (T/2) I / Pr + (1 - 1/Pr) Theta, in (xx, yy, zz, xy, xz, yz) order
+    double L[6];
+    for (int k = 0; k < 6; ++k) L[k] = (1.0 - 1.0 / C.pr) * stress[(size_t)k * N + cell];
+    for (int k = 0; k < 3; ++k) L[k] += 0.5 * T / C.pr;
+    // inverse through the adjugate of [[a d e] [d b f] [e f c]]
+    const double a = L[0], b = L[1], c = L[2], d = L[3], e = L[4], f = L[5];
+    const double ca = b * c - f * f, cb = a * c - e * e, cc = a * b - d * d;
+    const double cd = e * f - d * c, ce = d * f - e * b, cf = d * e - a * f;
+    const double det = a * ca + d * cd + e * ce;
+    if (!(rho > 0.0) || !(T > 0.0) || !isfinite(Ux) || !isfinite(Uy) || !isfinite(Uz) || !isfinite(T) ||
+        !(det > 0.0) || !(ca > 0.0) || !(cc > 0.0)) {
+        atomicOr(flag, 1);
+        for (int k = 0; k < P_INFO; ++k) P[k] = (S)0;
+        P[P_NU] = (S)1;
+        for (int k = 0; k < C.MT; ++k) E[k] = (S)0;
+        return;
+    }
+    const double Axx = ca / det, Ayy = cb / det, Azz = cc / det;
+    const double Axy = cd / det, Axz = ce / det, Ayz = cf / det;
+    const double nu = C.pr * rho * pow(T, 1.0 - C.omega) / C.kappa_kn;
+    const double pre = rho * pow(2.0 * M_PI, -1.5) / sqrt(det);
+    const double U3[3] = {Ux, Uy, Uz};
+    const double Ad[3] = {Axx, Ayy, Azz};
+    const int m3[3] = {C.mx, C.my, C.mz};
+    int off = 0;
+    for (int dd = 0; dd < 3; ++dd) {
+        const double scale = dd == 2 ? nu * pre : 1.0;
+        for (int q = 0; q < m3[dd]; ++q) {
+            const double cq = D.xi[dd * MAXM + q] - U3[dd];
+            E[off + q] = (S)(scale * exp(-0.5 * Ad[dd] * cq * cq));
+        }
+        off += m3[dd];
+    }
+    double lam[5] = {0, 0, 0, 0, 0};
+    if (C.correct) {
+        // discrete moments of G against the basis (1, cx, cy, cz, |c|^2)
+        double s0 = 0, sx = 0, sy = 0, sz = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
+        double sxc = 0, syc = 0, szc = 0, sc4 = 0;
+        for (int kz = 0; kz < C.mz; ++kz) {
+            const double cz = D.xi[2 * MAXM + kz] - Uz, wz = D.wt[2 * MAXM + kz];
+            for (int ky = 0; ky < C.my; ++ky) {
+                const double cy = D.xi[MAXM + ky] - Uy;
+                const double wyz = D.wt[MAXM + ky] * wz;
+                const double row = 0.5 * Ayy * cy * cy + 0.5 * Azz * cz * cz + Ayz * cy * cz;
+                const double B = Axy * cy + Axz * cz;
+                const double cyz2 = cy * cy + cz * cz;
+                for (int kx = 0; kx < C.mx; ++kx) {
+                    const double cx = D.xi[kx] - Ux;
+                    const double t = wyz * D.wt[kx] * pre * exp(-(0.5 * Axx * cx * cx + cx * B + row));
+                    const double c2 = cx * cx + cyz2;
+                    const double tx = t * cx, ty = t * cy, tz = t * cz, tc = t * c2;
+                    s0 += t;
+                    sx += tx;
+                    sy += ty;
+                    sz += tz;
+                    sxx += tx * cx;
+                    syy += ty * cy;
+                    szz += tz * cz;
+                    sxy += tx * cy;
+                    sxz += tx * cz;
+                    syz += ty * cz;
+                    sxc += tc * cx;
+                    syc += tc * cy;
+                    szc += tc * cz;
+                    sc4 += tc * c2;
+                }
+            }
+        }
+        const double sc2 = sxx + syy + szz;
+        double A[5][5] = {{s0, sx, sy, sz, sc2},
+                          {sx, sxx, sxy, sxz, sxc},
+                          {sy, sxy, syy, syz, syc},
+                          {sz, sxz, syz, szz, szc},
+                          {sc2, sxc, syc, szc, sc4}};
+        double bb[5] = {rho - s0, -sx, -sy, -sz, 1.5 * rho * T - sc2};
+        if (!chol5_solve(A, bb, lam)) atomicOr(flag, 2);
+    }
+    P[P_NU] = (S)nu;
+    P[P_UX] = (S)Ux;
+    P[P_UY] = (S)Uy;
+    P[P_UZ] = (S)Uz;
+    P[P_L0] = (S)(1.0 + lam[0]);
+    P[P_L1] = (S)lam[1];
+    P[P_L2] = (S)lam[2];
+    P[P_L3] = (S)lam[3];
+    P[P_L4] = (S)lam[4];
+    P[P_QX] = (S)Axy;
+    P[P_QY] = (S)Axz;
+    P[P_QZ] = (S)Ayz;
+    P[P_TWO_T] = (S)0;
+}
+
+hipError_t launch_params_es(const Consts& C, const DevPtrs& D, const double* W, const double* stress,
+                            const double* rho_w, void* params, void* etab, int prec, int* flag, hipStream_t st)
+{
+    const int tpb = 128;
+    const int nb = (C.N + tpb - 1) / tpb;
+    if (prec == 0)
+        params_es_kernel<double><<<nb, tpb, 0, st>>>(C, D, W, stress, rho_w, (double*)params, (double*)etab, flag);
+    else
+        params_es_kernel<float><<<nb, tpb, 0, st>>>(C, D, W, stress, rho_w, (float*)params, (float*)etab, flag);
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------------------------
 // Wall and free-stream emission shapes: the corrected equilibrium with unit
 // density, velocity u_k, temperature T_k and no heat flux, over the whole
@@ -370,10 +516,13 @@ __global__ __launch_bounds__(64) void wall_init_kernel(Consts C, DevPtrs D, cons
             if (!(xn < 0)) continue;
             const double cx = xv[0] - Ux, cy = xv[1] - Uy, cz = xv[2] - Uz;
             const double c2 = cx * cx + cy * cy + cz * cz;
-            const double poly = (double)P[P_L0] + (double)P[P_L1] * cx + (double)P[P_L2] * cy +
-                                (double)P[P_L3] * cz + (double)P[P_L4] * c2 +
-                                ((double)P[P_QX] * cx + (double)P[P_QY] * cy + (double)P[P_QZ] * cz) *
-                                    (c2 * (double)P[P_TWO_T] - 5.0);
+            double poly = (double)P[P_L0] + (double)P[P_L1] * cx + (double)P[P_L2] * cy +
+                          (double)P[P_L3] * cz + (double)P[P_L4] * c2;
+            if (C.esbgk)
+                poly *= exp(-((double)P[P_QX] * cx * cy + (double)P[P_QY] * cx * cz + (double)P[P_QZ] * cy * cz));
+            else
+                poly += ((double)P[P_QX] * cx + (double)P[P_QY] * cy + (double)P[P_QZ] * cz) *
+                        (c2 * (double)P[P_TWO_T] - 5.0);
             const double nfs = (double)E[a] * (double)E[C.mx + b] * (double)E[C.mx + C.my + c] * poly;
             const double w = D.wt[a] * D.wt[MAXM + b] * D.wt[2 * MAXM + c];
             flux += w * (-xn) * nfs / nu;
@@ -600,7 +749,10 @@ __device__ __forceinline__ void stb_nt(T* base, unsigned off, T v)
 // (f, F) pairs; a symmetry plane is an interior face (the mirror image is
 // the cell beyond it).  Three more raw moments, sum w xi_d (F_d - f), turn
 // the cell-value fluxes into face fluxes for the wall densities.
-template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false>
+// ES: the ES-BGK Gaussian in place of the Shakhov polynomial: no heat-flux
+// term, and the per-point cross factor exp(-(cx B + C)) of the anisotropic
+// Gaussian, B = A_xy cy + A_xz cz and C = A_yz cy cz fixed per lane and cell.
+template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __restrict__ params,
                                            const S* __restrict__ etab, const S* __restrict__ ghat,
                                            const double* __restrict__ lanetab, const int* __restrict__ bricks,
@@ -873,6 +1025,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 const S cyz2 = cy * cy + cz * cz;
                 const S Lyz = L0 + L2 * cy + L3 * cz;
                 const S Qyz = qy * cy + qz * cz;
+                // ES-BGK: qx, qy, qz hold A_xy, A_xz, A_yz
+                const S Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
                 // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
                 // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
                 S ayc = ay, azc = az, idx = (S)1, aynu = (S)0;
@@ -893,8 +1047,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 for (int v = 0; v < VL; ++v) {
                     const S cx = xix[v] - Ux;
                     const S c2 = cx * cx + cyz2;
-                    const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
-                    const S nfs = gyz * ldb(E, oa[v]) * poly;
+                    S nfs;
+                    if constexpr (ES) {
+                        const S poly = Lyz + L1 * cx + L4 * c2;
+                        const S arg = -(cx * Bes + Ces);
+                        S cross;
+                        if constexpr (sizeof(S) == 8)
+                            cross = exp(arg);
+                        else
+                            cross = __expf(arg);
+                        nfs = gyz * ldb(E, oa[v]) * poly * cross;
+                    } else {
+                        const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
+                        nfs = gyz * ldb(E, oa[v]) * poly;
+                    }
                     const S axv = NU ? ax[v] * idx : ax[v];
                     S f;
                     if constexpr (O2) {
@@ -1308,13 +1474,13 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
                               A.spec, A.partial, plane);
 }
 
-// second-order upwind (uniform meshes)
-template <typename S, int VL, int BX, int BY>
-__global__ __launch_bounds__(64) void sweep_kernel_o2(const SweepArgs<S> A)
+// second-order upwind and/or ES-BGK (uniform meshes, plain body)
+template <typename S, int VL, int BX, int BY, bool O2, bool ES>
+__global__ __launch_bounds__(64) void sweep_kernel_x(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
-    sweep_body<S, VL, BX, BY, false, true>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface,
-                                           A.zface, A.spec, A.partial, plane);
+    sweep_body<S, VL, BX, BY, false, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface,
+                                             A.yface, A.zface, A.spec, A.partial, plane);
 }
 
 // instantiated variants: (precision, VL, BX, BY)
@@ -1327,16 +1493,16 @@ __global__ __launch_bounds__(64) void sweep_kernel_o2(const SweepArgs<S> A)
 #define DVM_SWEEP_VARIANTS_NU(X) \
     X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
-// and for the second-order sweep
+// and for the second-order and ES-BGK sweeps
 #define DVM_SWEEP_VARIANTS_O2(X) \
     X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 
-bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2)
+bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2, int esbgk)
 {
 #define X(T, V, BXX, BYY) \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) return true;
-    if (order2) {
+    if (order2 || esbgk) {
         if (nonuniform) return false;
         DVM_SWEEP_VARIANTS_O2(X)
     } else if (nonuniform) {
@@ -1361,22 +1527,28 @@ hipError_t launch_sweep_t(int pipelined, const void* args, hipStream_t st)
 }
 
 template <typename T, int V, int BXX, int BYY>
-hipError_t launch_sweep_o2(const void* args, hipStream_t st)
+hipError_t launch_sweep_x(int order2, int esbgk, const void* args, hipStream_t st)
 {
     const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
-    const size_t lds = (size_t)2 * BYY * BXX * V * 64 * sizeof(T);  // f and F along z
-    sweep_kernel_o2<T, V, BXX, BYY><<<a.nblocks, 64, lds, st>>>(a);
+    // the plane of f, and with the second order the plane of F along z
+    const size_t lds = (size_t)(order2 ? 2 : 1) * BYY * BXX * V * 64 * sizeof(T);
+    if (order2 && esbgk)
+        sweep_kernel_x<T, V, BXX, BYY, true, true><<<a.nblocks, 64, lds, st>>>(a);
+    else if (order2)
+        sweep_kernel_x<T, V, BXX, BYY, true, false><<<a.nblocks, 64, lds, st>>>(a);
+    else
+        sweep_kernel_x<T, V, BXX, BYY, false, true><<<a.nblocks, 64, lds, st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, int order2,
-                        const void* args, hipStream_t st)
+                        int esbgk, const void* args, hipStream_t st)
 {
-    if (order2) {
+    if (order2 || esbgk) {
         if (nonuniform) return hipErrorInvalidValue;
 #define X(T, V, BXX, BYY)                                                     \
         if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) \
-            return launch_sweep_o2<T, V, BXX, BYY>(args, st);
+            return launch_sweep_x<T, V, BXX, BYY>(order2, esbgk, args, st);
         DVM_SWEEP_VARIANTS_O2(X)
 #undef X
         return hipErrorInvalidValue;
@@ -1404,8 +1576,8 @@ hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int non
 __global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, const double* __restrict__ partial,
                                                        int ntiles, const double* __restrict__ gout,
                                                        double* __restrict__ Wn, double* __restrict__ qn,
-                                                       double* __restrict__ rwn, double* __restrict__ blockmass,
-                                                       int* __restrict__ flag)
+                                                       double* __restrict__ rwn, double* __restrict__ stress_n,
+                                                       double* __restrict__ blockmass, int* __restrict__ flag)
 {
     __shared__ double red[256];
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1417,6 +1589,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, cons
             for (int v = 0; v < 5; ++v) Wn[(size_t)v * N + cell] = 0.0;
             for (int v = 0; v < 3; ++v) qn[(size_t)v * N + cell] = 0.0;
             for (int s = 0; s < 6; ++s) rwn[(size_t)s * N + cell] = 0.0;
+            if (C.esbgk)
+                for (int s = 0; s < 6; ++s) stress_n[(size_t)s * N + cell] = 0.0;
         } else {
             double m[13];
             for (int k = 0; k < 13; ++k) m[k] = 0.0;
@@ -1459,6 +1633,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, cons
                 const double val = m[10 + d] - 2.0 * UM - U[d] * trM + 2.0 * rho * U[d] * U2;
                 qn[(size_t)d * N + cell] = 0.5 * val;
             }
+            if (C.esbgk) {
+                // stress per unit mass about U^{n+1}: M_ij / rho - U_i U_j
+                stress_n[cell] = m[4] / rho - Ux * Ux;
+                stress_n[(size_t)N + cell] = m[5] / rho - Uy * Uy;
+                stress_n[(size_t)2 * N + cell] = m[6] / rho - Uz * Uz;
+                stress_n[(size_t)3 * N + cell] = m[7] / rho - Ux * Uy;
+                stress_n[(size_t)4 * N + cell] = m[8] / rho - Ux * Uz;
+                stress_n[(size_t)5 * N + cell] = m[9] / rho - Uy * Uz;
+            }
             for (int s = 0; s < 6; ++s) {
                 const uint32_t code = (info >> (4 * s)) & 15u;
                 double r = 0.0;
@@ -1484,10 +1667,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(Consts C, DevPtrs D, cons
 }
 
 hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
-                           const double* gout, double* Wn, double* qn, double* rwn, double* blockmass,
-                           int nblocks, int* flag, hipStream_t st)
+                           const double* gout, double* Wn, double* qn, double* rwn, double* stress_n,
+                           double* blockmass, int nblocks, int* flag, hipStream_t st)
 {
-    finalize_kernel<<<nblocks, 256, 0, st>>>(C, D, partial, ntiles, gout, Wn, qn, rwn, blockmass, flag);
+    finalize_kernel<<<nblocks, 256, 0, st>>>(C, D, partial, ntiles, gout, Wn, qn, rwn, stress_n, blockmass, flag);
     return hipGetLastError();
 }
 

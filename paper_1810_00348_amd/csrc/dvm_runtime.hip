@@ -75,6 +75,7 @@ struct dvm_ctx {
     int VL = 2, BX = 4, BY = 4, BZ = 8;
     int PF = 1;  // software-pipelined sweep body
     int order = 1;  // spatial order of the upwind scheme (1 or 2)
+    int model = 0;  // 0: Shakhov, 1: ES-BGK
     // velocity nodes and weights per axis (empty: uniform, trapezoid)
     std::vector<double> vnode[3], vweight[3];
     std::vector<double> h[3];  // cell sizes along x, y, z (empty: uniform)
@@ -98,7 +99,8 @@ struct dvm_ctx {
     bool bound = false;
     struct {
         size_t axes, spacing, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
-            partial, acc, xface, yface, zface, spec, xg, yg, zg, specg, blockmass, respart, out, flag, end;
+            partial, acc, xface, yface, zface, spec, xg, yg, zg, specg, stress, blockmass, respart, out, flag,
+            end;
     } off;
     size_t Ssz = 8;
     int nbF = 0;  // blocks of the per-cell kernels (256 threads)
@@ -154,19 +156,19 @@ void derive_schedule(dvm_ctx* c)
     int pf = (!f64 || vl == 4) ? 1 : 0;
     bx = env_int("DVM_BX", bx);
     by = env_int("DVM_BY", by);
-    const int o2 = c->order == 2;
-    if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2)) {
+    const int o2 = c->order == 2, es = c->model == 1;
+    if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) {
         // the shape is not built (for this mesh kind): the defaults' shape for VL
         bx = (f64 && vl == 4) ? 2 : 4;
         by = vl == 1 ? 4 : 2;
-        if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2)) { vl = 1; bx = 4; by = 4; }
+        if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) { vl = 1; bx = 4; by = 4; }
     }
     c->VL = vl;
     c->BX = bx;
     c->BY = by;
     c->BZ = env_int("DVM_BZ", 8);
-    // the second-order sweep has the plain body only
-    c->PF = o2 ? 0 : env_int("DVM_PF", pf) != 0;
+    // the second-order and ES-BGK sweeps have the plain body only
+    c->PF = (o2 || es) ? 0 : env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
     c->nby = (c->g.ny + c->BY - 1) / c->BY;
@@ -260,6 +262,8 @@ void layout(dvm_ctx* c)
     c->off.yg = take(o2 ? c->off.zface - c->off.yface : 0);
     c->off.zg = take(o2 ? c->off.spec - c->off.zface : 0);
     c->off.specg = take(o2 && c->spec_on ? S * 4 * (size_t)c->g.ny * c->g.nx * fst : 0);
+    // ES-BGK: the stress per unit mass, double-buffered like W
+    c->off.stress = take(c->model == 1 ? sizeof(double) * 2 * 6 * N : 0);
     c->off.blockmass = take(sizeof(double) * c->nbF);
     c->off.respart = take(sizeof(double) * 10 * c->nbF);
     c->off.out = take(sizeof(double) * 8);
@@ -288,6 +292,7 @@ Consts make_consts(const dvm_ctx* c)
     C.correct = c->gas.conservative_correction;
     C.closed = c->closed;
     C.order2 = c->order == 2;
+    C.esbgk = c->model == 1;
     for (int k = 0; k < 8; ++k) {
         C.kind_rho[k] = c->kind_rho[k];
         C.kind_wall[k] = c->kind_wall[k];
@@ -433,8 +438,13 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
 
     HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[0], st));
-    HIPCHK(launch_params(C, D, W + cur * 5 * N, q + cur * 3 * N, rw + cur * 6 * N, c->ws + c->off.params,
-                         c->ws + c->off.etab, c->prec, flag, st));
+    double* stress = c->model == 1 ? c->P<double>(c->off.stress) : nullptr;
+    if (c->model == 1)
+        HIPCHK(launch_params_es(C, D, W + cur * 5 * N, stress + cur * 6 * N, rw + cur * 6 * N,
+                                c->ws + c->off.params, c->ws + c->off.etab, c->prec, flag, st));
+    else
+        HIPCHK(launch_params(C, D, W + cur * 5 * N, q + cur * 3 * N, rw + cur * 6 * N, c->ws + c->off.params,
+                             c->ws + c->off.etab, c->prec, flag, st));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[1], st));
 
     // sweep: one launch per brick diagonal; with a specular plane the
@@ -482,11 +492,11 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
             if (c->prec == DVM_F64) {
                 SweepArgs<double> a;
                 fill(a);
-                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, &a, st);
+                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, &a, st);
             } else {
                 SweepArgs<float> a;
                 fill(a);
-                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, &a, st);
+                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, &a, st);
             }
             if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
         }
@@ -502,8 +512,8 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
     const bool folded = c->ngroups > 1;
     HIPCHK(launch_finalize(C, D, c->P<double>(folded ? c->off.acc : c->off.partial), folded ? 1 : c->ntiles,
                            c->P<double>(c->off.gout),
-                           W + nxt * 5 * N, q + nxt * 3 * N, rw + nxt * 6 * N, blockmass, c->nbF, flag,
-                           st));
+                           W + nxt * 5 * N, q + nxt * 3 * N, rw + nxt * 6 * N,
+                           stress ? stress + nxt * 6 * N : nullptr, blockmass, c->nbF, flag, st));
     HIPCHK(launch_scale_residual(C, D, c->M0, blockmass, c->nbF, W + nxt * 5 * N, q + nxt * 3 * N,
                                  rw + nxt * 6 * N, W + cur * 5 * N, respart, c->nbF, st));
     HIPCHK(launch_residual_final(respart, c->nbF, blockmass, c->nbF, out, flag, st));
@@ -520,6 +530,26 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
         c->t_final += d;
         c->t_iters++;
     }
+    return DVM_OK;
+}
+
+// ES-BGK: the equilibrium stress per unit mass, (T/2) I, of the conserved
+// moments W (5 x N, host) into the current stress slot
+dvm_status upload_equilibrium_stress(dvm_ctx* c, const double* Wh)
+{
+    if (c->model != 1) return DVM_OK;
+    const size_t N = c->N;
+    std::vector<double> P(6 * N, 0.0);
+    for (size_t i = 0; i < N; ++i) {
+        const double r = Wh[i];
+        if ((c->cellinfo[i] & SOLID_BIT) || !(r > 0)) continue;
+        const double ux = Wh[N + i] / r, uy = Wh[2 * N + i] / r, uz = Wh[3 * N + i] / r;
+        const double T = (Wh[4 * N + i] - 0.5 * r * (ux * ux + uy * uy + uz * uz)) / (0.75 * r);
+        for (int k = 0; k < 3; ++k) P[k * N + i] = 0.5 * T;
+    }
+    HIPCHK(hipMemcpyAsync(c->P<double>(c->off.stress) + (size_t)c->cur * 6 * N, P.data(), sizeof(double) * 6 * N,
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return DVM_OK;
 }
 
@@ -545,6 +575,7 @@ dvm_status upload_initial(dvm_ctx* c, const std::vector<double>& Wh)
     HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (hflag) return fail(DVM_ERR_NONPHYSICAL, "non-physical initial state (flag %d)", hflag);
+    if (upload_equilibrium_stress(c, Wh.data())) return DVM_ERR_DEVICE;
     double m = 0;
     for (size_t i = 0; i < N; ++i)
         if (!(c->cellinfo[i] & SOLID_BIT)) m += Wh[i] * cell_volume(c, i);
@@ -651,6 +682,7 @@ dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const
         }
     }
     if (any && c->order == 2) return fail(DVM_ERR_ARG, "the second-order sweep needs a uniform mesh");
+    if (any && c->model == 1) return fail(DVM_ERR_ARG, "the ES-BGK sweep needs a uniform mesh");
     c->nonuniform = any;
     derive_schedule(c);
     return DVM_OK;
@@ -686,6 +718,32 @@ dvm_status dvm_set_velocity_axes(dvm_ctx* c, const double* xi_x, const double* w
             c->vweight[d].clear();
         }
     }
+    return DVM_OK;
+}
+
+dvm_status dvm_set_model(dvm_ctx* c, int model)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "the model must be set before binding the workspace");
+    if (model != 0 && model != 1) return fail(DVM_ERR_ARG, "model must be 0 (Shakhov) or 1 (ES-BGK), got %d", model);
+    if (model == 1 && c->nonuniform) return fail(DVM_ERR_ARG, "the ES-BGK sweep needs a uniform mesh");
+    if (model == 1 && !(c->gas.pr >= 2.0 / 3.0 - 1e-12))
+        return fail(DVM_ERR_ARG, "ES-BGK needs Pr >= 2/3 (a positive-definite Gaussian), got %g", c->gas.pr);
+    c->model = model;
+    derive_schedule(c);
+    return DVM_OK;
+}
+
+dvm_status dvm_get_stress(dvm_ctx* c, double* P)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->model != 1) return fail(DVM_ERR_STATE, "the stress is kept for the ES-BGK model only");
+    if (!c->initialized) return fail(DVM_ERR_STATE, "no state yet");
+    if (!P) return fail(DVM_ERR_ARG, "NULL");
+    const size_t N = c->N;
+    HIPCHK(hipMemcpyAsync(P, c->P<double>(c->off.stress) + (size_t)c->cur * 6 * N, sizeof(double) * 6 * N,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return DVM_OK;
 }
 
@@ -907,6 +965,8 @@ dvm_status dvm_set_state(dvm_ctx* c, const double* W, const double* q, const dou
     HIPCHK(hipMemcpyAsync(c->P<double>(c->off.q), q, sizeof(double) * 3 * N, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(c->P<double>(c->off.rw), rho_w, sizeof(double) * 6 * N, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
+    // ES-BGK: the stress restarts at the equilibrium of the given state
+    if (upload_equilibrium_stress(c, W)) return DVM_ERR_DEVICE;
     c->M0 = M0;
     c->initialized = true;
     for (int v = 0; v < 5; ++v) c->res[v] = 0;

@@ -66,6 +66,10 @@ class Solver:
                 self._vax.append((xi, w))
                 args += [_ptr(xi), _ptr(w)]
             L.check(lib.dvm_set_velocity_axes(h, *args))
+        if case.model != "shakhov":
+            if case.model != "esbgk":
+                raise ValueError(f"unknown model {case.model}")
+            L.check(lib.dvm_set_model(h, 1))
         if case.order != 1:
             L.check(lib.dvm_set_order(h, int(case.order)))
         nbytes = C.c_size_t()
@@ -127,6 +131,12 @@ class Solver:
         rho = np.empty(N); u = np.empty((3, N)); T = np.empty(N); q = np.empty((3, N))
         L.check(L.lib().dvm_get_fields(self._h, _ptr(rho), _ptr(u), _ptr(T), _ptr(q)))
         return {"rho": rho, "u": u, "T": T, "q": q}
+
+    def stress(self):
+        """ES-BGK: stress per unit mass of the current iterate, 6 x N."""
+        P = np.empty((6, self.N))
+        L.check(L.lib().dvm_get_stress(self._h, _ptr(P)))
+        return P
 
     def state(self):
         N = self.N

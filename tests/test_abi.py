@@ -211,3 +211,30 @@ def test_velocity_axes_arguments(L):
     assert lib.dvm_set_velocity_axes(h, p(keep[0]), p(keep[1]), None, None, p(keep[0]), p(keep[1])) == 0
     assert lib.dvm_set_velocity_axes(h, None, None, None, None, None, None) == 0
     lib.dvm_destroy(h)
+
+
+def test_model_arguments(L):
+    import numpy as np
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    case = cases.cavity((6, 5, 4), 10, kn=1.0)
+    h = _ctx(L, case)
+    assert lib.dvm_set_model(h, 2) == -1
+    assert lib.dvm_set_model(h, 1) == 0
+    info = L.Info()
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.pipelined == 0
+    P = (C.c_double * (6 * case.ncells))()
+    assert lib.dvm_get_stress(h, P) == -2          # no state yet
+    hy = cases.stretched_axis(5, 1.0, 1.3)
+    assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(C.POINTER(C.c_double)), None) == -1
+    assert lib.dvm_set_model(h, 0) == 0
+    assert lib.dvm_get_stress(h, P) == -2          # Shakhov keeps no stress
+    lib.dvm_destroy(h)
+    low = cases.cavity((6, 5, 4), 10, kn=1.0, pr=0.5)
+    g = L.Grid(*low.n, *low.L)
+    vg = L.VGrid((C.c_int * 3)(*low.m), (C.c_double * 3)(*low.vmax))
+    gas = L.Gas(low.kn, low.omega, low.pr, 1)
+    h = C.c_void_p()
+    assert lib.dvm_create(C.byref(g), C.byref(vg), C.byref(gas), 0, None, C.byref(h)) == 0
+    assert lib.dvm_set_model(h, 1) == -1 and b"Pr" in lib.dvm_last_error()
+    lib.dvm_destroy(h)

@@ -429,3 +429,63 @@ def test_velocity_axes_match_oracle(oracle_mod, name):
     _, _, rwg, _ = s.state()
     _, _, rwo = o.state()
     assert np.abs(rwg - rwo).max() <= FP64_TOL * max(1e-300, np.abs(rwo).max())
+
+
+def _es_cases():
+    a = cases.cavity((13, 10, 19), 8, kn=0.3, lid=0.4, vmax=4.5)      # ragged bricks
+    b = cases.cavity((9, 11, 7), 9, kn=2.0, lid=0.2, vmax=5.0)         # odd M
+    c = cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=10, vmax=7.0, mach=2.0, kn=0.5)  # mirror, body
+    e = cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2)                  # 4 per lane, 2x2 bricks (FP64)
+    out = {k: dataclasses.replace(v, model="esbgk") for k, v in
+           {"ragged": a, "oddM": b, "cube_half": c, "cavity_m16": e}.items()}
+    out["order2"] = dataclasses.replace(out["ragged"], order=2)
+    return out
+
+
+@pytest.mark.parametrize("name", ["ragged", "oddM", "cube_half", "cavity_m16", "order2"])
+def test_esbgk_matches_oracle(oracle_mod, name):
+    """ES-BGK (FP64): fields, wall densities and the stress state against
+    the oracle's ES-BGK."""
+    case = _es_cases()[name]
+    init = cases.random_fields(case, seed=61) if name in ("ragged", "cavity_m16", "order2") else None
+    s, o = run_pair(case, 3, oracle_mod, init=init)
+    err = field_errors(s.fields(), o.fields())
+    print(name, err, s.info())
+    for k in ("rho", "ux", "uy", "uz", "T", "qx", "qy"):
+        assert err[k] <= FP64_TOL, (k, err)
+    _, _, rwg, _ = s.state()
+    _, _, rwo = o.state()
+    assert np.abs(rwg - rwo).max() <= FP64_TOL * np.abs(rwo).max()
+    Pg, Po = s.stress(), o.stress()
+    assert np.abs(Pg - Po).max() <= FP64_TOL * np.abs(Po).max()
+
+
+def test_esbgk_with_velocity_groups_and_fp32(oracle_mod):
+    case = dataclasses.replace(cases.cavity((9, 8, 7), 24, kn=0.5, lid=0.3, vmax=5.0), model="esbgk")
+    s, o = run_pair(case, 2, oracle_mod, init=cases.random_fields(case, seed=8), groups=3)
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "uy", "uz", "T"):
+        assert err[k] <= FP64_TOL, (k, err)
+    s32, o32 = run_pair(_es_cases()["cube_half"], 3, oracle_mod, precision="f32")
+    err = field_errors(s32.fields(), o32.fields())
+    for k in ("rho", "ux", "T"):
+        assert err[k] <= 2e-5, (k, err)
+
+
+def test_esbgk_converges_like_oracle(oracle_mod):
+    case = dataclasses.replace(cases.config("c1"), model="esbgk")
+    Solver = _solver()
+    s = Solver(case)
+    s.init_uniform()
+    n, r, ok = s.iterate(400, tol=1e-6)
+    o = oracle_mod.Oracle(case)
+    o.init_uniform()
+    k = 0
+    while k < 400:
+        k += 1
+        if o.iterate(1) <= 1e-6:
+            break
+    assert ok and n == k, (n, k)
+    err = field_errors(s.fields(), o.fields())
+    for key in ("rho", "ux", "uy", "T"):
+        assert err[key] <= 1e-9, (key, err)
