@@ -264,21 +264,22 @@ hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, con
 // cell record, for the cross factor exp(-(A_xy cx cy + A_xz cx cz + A_yz cy cz))
 // the sweep takes per point.  The correction multipliers need the discrete
 // moments of G, which does not factor over the axes: one pass over the whole
-// velocity set per cell (one exponential per node).
+// velocity set per cell (one exponential per node), shared by a wave.
 template <typename S>
-__global__ __launch_bounds__(128) void params_es_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
-                                                        const double* __restrict__ stress,
-                                                        const double* __restrict__ rho_w,
-                                                        S* __restrict__ params, S* __restrict__ etab,
-                                                        int* __restrict__ flag)
+__global__ __launch_bounds__(64) void params_es_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
+                                                       const double* __restrict__ stress,
+                                                       const double* __restrict__ rho_w,
+                                                       S* __restrict__ params, S* __restrict__ etab,
+                                                       int* __restrict__ flag)
 {
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= C.N) return;
+    // one wave per cell: the lanes share the pass over the velocity set
+    const int cell = blockIdx.x;
+    const int lane = threadIdx.x;
     const uint32_t info = D.cellinfo[cell];
     S* P = params + (size_t)cell * PSTRIDE;
-    reinterpret_cast<uint32_t*>(P + P_INFO)[0] = info;
+    if (lane == 0) reinterpret_cast<uint32_t*>(P + P_INFO)[0] = info;
     if (info & SOLID_BIT) return;
-    {
+    if (lane == 0) {
         const int i = cell % C.nx, j = (cell / C.nx) % C.ny, k = cell / (C.nx * C.ny);
         P[P_IDX] = (S)(1.0 / D.h[i]);
         P[P_IDY] = (S)(1.0 / D.h[C.nx + j]);
@@ -307,96 +308,96 @@ __global__ __launch_bounds__(128) void params_es_kernel(Consts C, DevPtrs D, con
     const double det = a * ca + d * cd + e * ce;
     if (!(rho > 0.0) || !(T > 0.0) || !isfinite(Ux) || !isfinite(Uy) || !isfinite(Uz) || !isfinite(T) ||
         !(det > 0.0) || !(ca > 0.0) || !(cc > 0.0)) {
-        atomicOr(flag, 1);
-        for (int k = 0; k < P_INFO; ++k) P[k] = (S)0;
-        P[P_NU] = (S)1;
-        for (int k = 0; k < C.MT; ++k) E[k] = (S)0;
+        if (lane == 0) {
+            atomicOr(flag, 1);
+            for (int k = 0; k < P_INFO; ++k) P[k] = (S)0;
+            P[P_NU] = (S)1;
+        }
+        for (int k = lane; k < C.MT; k += 64) E[k] = (S)0;
         return;
     }
     const double Axx = ca / det, Ayy = cb / det, Azz = cc / det;
     const double Axy = cd / det, Axz = ce / det, Ayz = cf / det;
     const double nu = C.pr * rho * pow(T, 1.0 - C.omega) / C.kappa_kn;
     const double pre = rho * pow(2.0 * M_PI, -1.5) / sqrt(det);
-    const double U3[3] = {Ux, Uy, Uz};
-    const double Ad[3] = {Axx, Ayy, Azz};
-    const int m3[3] = {C.mx, C.my, C.mz};
-    int off = 0;
-    for (int dd = 0; dd < 3; ++dd) {
-        const double scale = dd == 2 ? nu * pre : 1.0;
-        for (int q = 0; q < m3[dd]; ++q) {
-            const double cq = D.xi[dd * MAXM + q] - U3[dd];
-            E[off + q] = (S)(scale * exp(-0.5 * Ad[dd] * cq * cq));
-        }
-        off += m3[dd];
+    for (int k = lane; k < C.MT; k += 64) {
+        const int dd = k < C.mx ? 0 : k < C.mx + C.my ? 1 : 2;
+        const int q = k - (dd == 0 ? 0 : dd == 1 ? C.mx : C.mx + C.my);
+        const double Ad = dd == 0 ? Axx : dd == 1 ? Ayy : Azz;
+        const double Ud = dd == 0 ? Ux : dd == 1 ? Uy : Uz;
+        const double cq = D.xi[dd * MAXM + q] - Ud;
+        E[k] = (S)((dd == 2 ? nu * pre : 1.0) * exp(-0.5 * Ad * cq * cq));
     }
     double lam[5] = {0, 0, 0, 0, 0};
     if (C.correct) {
-        // discrete moments of G against the basis (1, cx, cy, cz, |c|^2)
-        double s0 = 0, sx = 0, sy = 0, sz = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
-        double sxc = 0, syc = 0, szc = 0, sc4 = 0;
-        for (int kz = 0; kz < C.mz; ++kz) {
-            const double cz = D.xi[2 * MAXM + kz] - Uz, wz = D.wt[2 * MAXM + kz];
-            for (int ky = 0; ky < C.my; ++ky) {
-                const double cy = D.xi[MAXM + ky] - Uy;
-                const double wyz = D.wt[MAXM + ky] * wz;
-                const double row = 0.5 * Ayy * cy * cy + 0.5 * Azz * cz * cz + Ayz * cy * cz;
-                const double B = Axy * cy + Axz * cz;
-                const double cyz2 = cy * cy + cz * cz;
-                for (int kx = 0; kx < C.mx; ++kx) {
-                    const double cx = D.xi[kx] - Ux;
-                    const double t = wyz * D.wt[kx] * pre * exp(-(0.5 * Axx * cx * cx + cx * B + row));
-                    const double c2 = cx * cx + cyz2;
-                    const double tx = t * cx, ty = t * cy, tz = t * cz, tc = t * c2;
-                    s0 += t;
-                    sx += tx;
-                    sy += ty;
-                    sz += tz;
-                    sxx += tx * cx;
-                    syy += ty * cy;
-                    szz += tz * cz;
-                    sxy += tx * cy;
-                    sxz += tx * cz;
-                    syz += ty * cz;
-                    sxc += tc * cx;
-                    syc += tc * cy;
-                    szc += tc * cz;
-                    sc4 += tc * c2;
-                }
+        // discrete moments of G against the basis (1, cx, cy, cz, |c|^2);
+        // lane l takes the (y, z) rows l, l + 64, ...
+        double sm[14];
+        for (int k = 0; k < 14; ++k) sm[k] = 0.0;
+        for (int r = lane; r < C.my * C.mz; r += 64) {
+            const int ky = r % C.my, kz = r / C.my;
+            const double cz = D.xi[2 * MAXM + kz] - Uz;
+            const double cy = D.xi[MAXM + ky] - Uy;
+            const double wyz = D.wt[MAXM + ky] * D.wt[2 * MAXM + kz];
+            const double row = 0.5 * Ayy * cy * cy + 0.5 * Azz * cz * cz + Ayz * cy * cz;
+            const double B = Axy * cy + Axz * cz;
+            const double cyz2 = cy * cy + cz * cz;
+            for (int kx = 0; kx < C.mx; ++kx) {
+                const double cx = D.xi[kx] - Ux;
+                const double t = wyz * D.wt[kx] * pre * exp(-(0.5 * Axx * cx * cx + cx * B + row));
+                const double c2 = cx * cx + cyz2;
+                const double tx = t * cx, ty = t * cy, tz = t * cz, tc = t * c2;
+                sm[0] += t;
+                sm[1] += tx;
+                sm[2] += ty;
+                sm[3] += tz;
+                sm[4] += tx * cx;
+                sm[5] += ty * cy;
+                sm[6] += tz * cz;
+                sm[7] += tx * cy;
+                sm[8] += tx * cz;
+                sm[9] += ty * cz;
+                sm[10] += tc * cx;
+                sm[11] += tc * cy;
+                sm[12] += tc * cz;
+                sm[13] += tc * c2;
             }
         }
-        const double sc2 = sxx + syy + szz;
-        double A[5][5] = {{s0, sx, sy, sz, sc2},
-                          {sx, sxx, sxy, sxz, sxc},
-                          {sy, sxy, syy, syz, syc},
-                          {sz, sxz, syz, szz, szc},
-                          {sc2, sxc, syc, szc, sc4}};
-        double bb[5] = {rho - s0, -sx, -sy, -sz, 1.5 * rho * T - sc2};
-        if (!chol5_solve(A, bb, lam)) atomicOr(flag, 2);
+        for (int k = 0; k < 14; ++k)
+            for (int o = 32; o > 0; o >>= 1) sm[k] += __shfl_xor(sm[k], o, 64);
+        const double sc2 = sm[4] + sm[5] + sm[6];
+        double A[5][5] = {{sm[0], sm[1], sm[2], sm[3], sc2},
+                          {sm[1], sm[4], sm[7], sm[8], sm[10]},
+                          {sm[2], sm[7], sm[5], sm[9], sm[11]},
+                          {sm[3], sm[8], sm[9], sm[6], sm[12]},
+                          {sc2, sm[10], sm[11], sm[12], sm[13]}};
+        double bb[5] = {rho - sm[0], -sm[1], -sm[2], -sm[3], 1.5 * rho * T - sc2};
+        if (!chol5_solve(A, bb, lam) && lane == 0) atomicOr(flag, 2);
     }
-    P[P_NU] = (S)nu;
-    P[P_UX] = (S)Ux;
-    P[P_UY] = (S)Uy;
-    P[P_UZ] = (S)Uz;
-    P[P_L0] = (S)(1.0 + lam[0]);
-    P[P_L1] = (S)lam[1];
-    P[P_L2] = (S)lam[2];
-    P[P_L3] = (S)lam[3];
-    P[P_L4] = (S)lam[4];
-    P[P_QX] = (S)Axy;
-    P[P_QY] = (S)Axz;
-    P[P_QZ] = (S)Ayz;
-    P[P_TWO_T] = (S)0;
+    if (lane == 0) {
+        P[P_NU] = (S)nu;
+        P[P_UX] = (S)Ux;
+        P[P_UY] = (S)Uy;
+        P[P_UZ] = (S)Uz;
+        P[P_L0] = (S)(1.0 + lam[0]);
+        P[P_L1] = (S)lam[1];
+        P[P_L2] = (S)lam[2];
+        P[P_L3] = (S)lam[3];
+        P[P_L4] = (S)lam[4];
+        P[P_QX] = (S)Axy;
+        P[P_QY] = (S)Axz;
+        P[P_QZ] = (S)Ayz;
+        P[P_TWO_T] = (S)0;
+    }
 }
 
 hipError_t launch_params_es(const Consts& C, const DevPtrs& D, const double* W, const double* stress,
                             const double* rho_w, void* params, void* etab, int prec, int* flag, hipStream_t st)
 {
-    const int tpb = 128;
-    const int nb = (C.N + tpb - 1) / tpb;
     if (prec == 0)
-        params_es_kernel<double><<<nb, tpb, 0, st>>>(C, D, W, stress, rho_w, (double*)params, (double*)etab, flag);
+        params_es_kernel<double><<<C.N, 64, 0, st>>>(C, D, W, stress, rho_w, (double*)params, (double*)etab, flag);
     else
-        params_es_kernel<float><<<nb, tpb, 0, st>>>(C, D, W, stress, rho_w, (float*)params, (float*)etab, flag);
+        params_es_kernel<float><<<C.N, 64, 0, st>>>(C, D, W, stress, rho_w, (float*)params, (float*)etab, flag);
     return hipGetLastError();
 }
 
