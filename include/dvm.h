@@ -153,6 +153,12 @@ dvm_status dvm_set_model(dvm_ctx* ctx, int model);
    the Shakhov model or before an initial state. */
 dvm_status dvm_get_stress(dvm_ctx* ctx, double* stress);
 
+/* ES-BGK: replace the stress of the current iterate (same layout; after
+   dvm_init_* or dvm_set_state, which reset it to the equilibrium), e.g. to
+   carry a state over between FP32 and FP64 contexts.  DVM_ERR_STATE for the
+   Shakhov model or before a state; DVM_ERR_ARG for non-finite values. */
+dvm_status dvm_set_stress(dvm_ctx* ctx, const double* stress);
+
 /* Velocity nodes and quadrature weights per axis (m[d] values each, host
    arrays copied by the call) in place of the uniform trapezoid axes -- the
    non-uniform velocity grids the paper recommends over very large uniform

@@ -64,6 +64,7 @@ EXPORTS = {
     "dvm_set_order": ([C.c_void_p, C.c_int], C.c_int),
     "dvm_set_model": ([C.c_void_p, C.c_int], C.c_int),
     "dvm_get_stress": ([C.c_void_p, _P], C.c_int),
+    "dvm_set_stress": ([C.c_void_p, _P], C.c_int),
     "dvm_set_velocity_axes": ([C.c_void_p, _P, _P, _P, _P, _P, _P], C.c_int),
     "dvm_required_workspace": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "dvm_bind_workspace": ([C.c_void_p, C.c_void_p, C.c_size_t], C.c_int),

@@ -747,6 +747,21 @@ dvm_status dvm_get_stress(dvm_ctx* c, double* P)
     return DVM_OK;
 }
 
+dvm_status dvm_set_stress(dvm_ctx* c, const double* P)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->model != 1) return fail(DVM_ERR_STATE, "the stress is kept for the ES-BGK model only");
+    if (!c->initialized) return fail(DVM_ERR_STATE, "set a state first");
+    if (!P) return fail(DVM_ERR_ARG, "NULL");
+    const size_t N = c->N;
+    for (size_t i = 0; i < 6 * N; ++i)
+        if (!isfinite(P[i])) return fail(DVM_ERR_ARG, "stress value %zu is not finite", i);
+    HIPCHK(hipMemcpyAsync(c->P<double>(c->off.stress) + (size_t)c->cur * 6 * N, P, sizeof(double) * 6 * N,
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DVM_OK;
+}
+
 dvm_status dvm_set_order(dvm_ctx* c, int order)
 {
     if (check_ctx(c)) return DVM_ERR_ARG;

@@ -138,6 +138,10 @@ class Solver:
         L.check(L.lib().dvm_get_stress(self._h, _ptr(P)))
         return P
 
+    def set_stress(self, P):
+        P = np.ascontiguousarray(P, dtype=np.float64).reshape(6, self.N)
+        L.check(L.lib().dvm_set_stress(self._h, _ptr(P)))
+
     def state(self):
         N = self.N
         W = np.empty((5, N)); q = np.empty((3, N)); rw = np.empty((6, N)); M0 = C.c_double()
@@ -181,8 +185,8 @@ def solve_fp32_then_fp64(case: Case, tol: float = 1e-6, max_iters: int = 4000, s
                          device: str = "cuda:0"):
     """Iterate with f in FP32 until the residual reaches switch_factor * tol
     (or tol itself, or stops improving), then continue from the same state
-    (W, q, wall densities, reference mass -- all FP64) with f in FP64 until
-    tol.
+    (W, q, wall densities, reference mass and, for ES-BGK, the stress -- all
+    FP64) with f in FP64 until tol.
 
     FP32 storage has a noise floor in the relative residual of a field whose
     norm is small against the others (the spanwise momentum of the cavity:
@@ -216,9 +220,12 @@ def solve_fp32_then_fp64(case: Case, tol: float = 1e-6, max_iters: int = 4000, s
     if not ok:
         t1 = time.perf_counter()
         state = s.state()
+        stress = s.stress() if case.model == "esbgk" else None
         del s
         s = Solver(case, precision="f64", device=device)
         s.set_state(*state)
+        if stress is not None:
+            s.set_stress(stress)
         n, r, ok = s.iterate(max(1, max_iters - it32), tol=tol)
         torch.cuda.synchronize()
         out["f64_iters"] = n

@@ -229,6 +229,7 @@ def test_model_arguments(L):
     assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(C.POINTER(C.c_double)), None) == -1
     assert lib.dvm_set_model(h, 0) == 0
     assert lib.dvm_get_stress(h, P) == -2          # Shakhov keeps no stress
+    assert lib.dvm_set_stress(h, P) == -2
     lib.dvm_destroy(h)
     low = cases.cavity((6, 5, 4), 10, kn=1.0, pr=0.5)
     g = L.Grid(*low.n, *low.L)

@@ -489,3 +489,18 @@ def test_esbgk_converges_like_oracle(oracle_mod):
     err = field_errors(s.fields(), o.fields())
     for key in ("rho", "ux", "uy", "T"):
         assert err[key] <= 1e-9, (key, err)
+
+
+def test_esbgk_fp32_then_fp64_reaches_the_fp64_solution():
+    """The FP32-then-FP64 solve carries the ES-BGK stress across."""
+    _solver()
+    from paper_1810_00348_amd.solver import Solver, solve_fp32_then_fp64
+    case = dataclasses.replace(cases.cavity(12, 12, kn=1.0, lid=0.3), model="esbgk")
+    s = Solver(case, precision="f64")
+    s.init_uniform()
+    n64, r64, ok64 = s.iterate(400, tol=1e-7)
+    m = solve_fp32_then_fp64(case, tol=1e-7, max_iters=400)
+    assert ok64 and m["converged"], (r64, m["residual"])
+    err = field_errors(m["fields"], s.fields())
+    for k in ("rho", "ux", "uy", "T"):
+        assert err[k] <= 1e-5, (k, err)
