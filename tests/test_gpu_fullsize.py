@@ -1,0 +1,131 @@
+"""The benchmark workloads at their full sizes, in the launch configuration
+bench.py times (default schedule chosen by the library), checked through
+properties that hold at any size, and the full C2 spatial grid against the
+oracle at a reduced velocity grid (the oracle's cost of one iteration at the
+full 32^3 velocities is minutes of CPU).
+
+Properties: the cavities are mirror-symmetric about the mid-plane normal to
+the lid's spanwise direction (z), the half-domain cube about its centre
+plane in y, so after any number of iterations the fields are mirror images
+(u_z resp. u_y odd) up to rounding; the velocity-group schedule reproduces
+the one-group iterate up to the order of the FP64 moment sums; the closed
+cavity keeps its mass.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1810_00348_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_00348_amd.solver import Solver
+    return Solver
+
+
+def _mirror_error(f, n, axis, odd):
+    """max |x - mirror(x)| / max |x| per field; axis 0 = z, 1 = y of [nz, ny, nx]."""
+    nx, ny, nz = n
+    out = {}
+    for name, arr in (("rho", f["rho"]), ("T", f["T"]), ("ux", f["u"][0]), ("uy", f["u"][1]), ("uz", f["u"][2])):
+        a = arr.reshape(nz, ny, nx)
+        sign = -1.0 if name == odd else 1.0
+        m = np.flip(a, axis=axis)
+        scale = max(np.abs(a).max(), 1e-300)
+        out[name] = np.abs(a - sign * m).max() / scale
+    return out
+
+
+def test_c2_full_size_symmetry_groups_and_mass():
+    """C2 (64^3 x 32^3, FP64, the bench's schedule): two iterations from
+    rest are z-mirror symmetric, the closed cavity keeps its mass, and a
+    four-group velocity schedule gives the same iterate."""
+    Solver = _solver()
+    case = cases.config("c2")
+    s = Solver(case, precision="f64")
+    info = s.info()
+    print(info, flush=True)
+    assert info["velocity_groups"] == 1 and info["sweep_kernel"] == "sweep_kernel_pf"
+    s.init_uniform()
+    s.iterate(2)
+    f = s.fields()
+    err = _mirror_error(f, case.n, 0, "uz")
+    print(err, flush=True)
+    for k, v in err.items():
+        assert v <= 1e-12, (k, err)
+    W, _, _, M0 = s.state()
+    dv = (1.0 / 64) ** 3
+    assert abs(W[0].sum() * dv - M0) <= 1e-12 * M0
+    g = Solver(case, precision="f64", velocity_groups=4)
+    assert g.info()["velocity_groups"] == 4
+    g.init_uniform()
+    g.iterate(2)
+    fg = g.fields()
+    for key in ("rho", "T"):
+        assert np.abs(fg[key] - f[key]).max() <= 1e-13 * np.abs(f[key]).max(), key
+    assert np.abs(fg["u"] - f["u"]).max() <= 1e-12 * np.abs(f["u"]).max()
+
+
+def test_c3_full_size_fp32_symmetry():
+    """C3 (96^3 x 28^3, FP32 storage, 4 per lane with empty slots)."""
+    Solver = _solver()
+    case = cases.config("c3")
+    s = Solver(case, precision="f32")
+    print(s.info(), flush=True)
+    s.init_uniform()
+    s.iterate(2)
+    err = _mirror_error(s.fields(), case.n, 0, "uz")
+    print(err, flush=True)
+    for k in ("rho", "T", "ux", "uy"):
+        assert err[k] <= 2e-6, (k, err)
+    assert err["uz"] <= 2e-4, err      # u_z is ~1e-3 of the flow: FP32 noise relative to a small field
+
+
+def test_c4_full_size_fp32_symmetry():
+    """C4 (half-domain cube 64x48x48 x 48^3, Ma 5, FP32 storage, specular
+    plane): y-mirror symmetric about the cube's centre plane."""
+    Solver = _solver()
+    case = cases.config("c4")
+    s = Solver(case, precision="f32")
+    print(s.info(), flush=True)
+    s.init_uniform()
+    s.iterate(2)
+    f = s.fields()
+    solid = case.solid.astype(bool)
+    err = _mirror_error(f, case.n, 1, "uy")
+    print(err, flush=True)
+    for k in ("rho", "T", "ux", "uz"):
+        assert err[k] <= 2e-6, (k, err)
+    assert err["uy"] <= 2e-5, err
+    assert np.isfinite(f["rho"].reshape(solid.shape)[~solid]).all()
+
+
+def test_c2_spatial_grid_matches_oracle(oracle_mod):
+    """The full C2 spatial grid (64^3 cells, the bench's brick schedule and
+    diagonal launches) with 16^3 velocities: one iteration from seeded random
+    fields, every cell against the oracle (FP64)."""
+    Solver = _solver()
+    case = dataclasses.replace(cases.config("c2"), m=(16, 16, 16), name="c2_grid_v16")
+    init = cases.random_fields(case, seed=77)
+    s = Solver(case, precision="f64")
+    s.init_fields(*init)
+    s.iterate(1)
+    o = oracle_mod.Oracle(case)
+    o.init_fields(*init)
+    print("oracle iteration on", case.n, case.m, "threads", o.threads, flush=True)
+    o.iterate(1)
+    g, r = s.fields(), o.fields()
+    for key in ("rho", "T"):
+        e = np.abs(g[key] - r[key]).max() / np.abs(r[key]).max()
+        assert e <= 1e-10, (key, e)
+    e = np.abs(g["u"] - r["u"]).max() / np.abs(r["u"]).max()
+    assert e <= 1e-10, e
+    _, _, rwg, _ = s.state()
+    _, _, rwo = o.state()
+    assert np.abs(rwg - rwo).max() <= 1e-10 * np.abs(rwo).max()
