@@ -25,15 +25,20 @@ def _solver():
 
 
 def field_errors(g, r):
+    """Vector components are measured against their own maximum, floored at
+    1e-3 of the largest component and at 1e-4 (in units of the reference
+    thermal speed sqrt(2 R T0), resp. rho0 (2 R T0)^{3/2} for q): a component
+    that vanishes by symmetry, or a gas that has nearly come to rest, holds
+    rounding noise on both sides and is measured against the flow or the
+    thermal scale instead."""
     out = {}
     for name in ("rho", "T"):
         out[name] = np.abs(g[name] - r[name]).max() / np.abs(r[name]).max()
-    for d, name in enumerate(("ux", "uy", "uz")):
-        den = np.abs(r["u"][d]).max()
-        out[name] = np.abs(g["u"][d] - r["u"][d]).max() / den if den > 0 else np.abs(g["u"][d]).max()
-    for d, name in enumerate(("qx", "qy", "qz")):
-        den = np.abs(r["q"][d]).max()
-        out[name] = np.abs(g["q"][d] - r["q"][d]).max() / den if den > 0 else np.abs(g["q"][d]).max()
+    for key, names in (("u", ("ux", "uy", "uz")), ("q", ("qx", "qy", "qz"))):
+        big = np.abs(r[key]).max()
+        for d, name in enumerate(names):
+            den = max(np.abs(r[key][d]).max(), 1e-3 * big, 1e-4)
+            out[name] = np.abs(g[key][d] - r[key][d]).max() / den if den > 0 else np.abs(g[key][d]).max()
     return out
 
 
@@ -504,3 +509,58 @@ def test_esbgk_fp32_then_fp64_reaches_the_fp64_solution():
     err = field_errors(m["fields"], s.fields())
     for k in ("rho", "ux", "uy", "T"):
         assert err[k] <= 1e-5, (k, err)
+
+
+def _degenerate_cases():
+    s = np.zeros((5, 5, 5), np.uint8)
+    s[:] = 1
+    s[2, 2, 2] = 0
+    free = [cases.Face("free", u=(0.5, 0.0, 0.0), T=1.0, rho=1.0) for _ in range(6)]
+    lone = cases.Case(name="lone", n=(5, 5, 5), L=(2.5, 2.5, 2.5), m=(6, 6, 6), vmax=(5.0, 5.0, 5.0), kn=0.5,
+                      faces=free, closed=False, solid=s, init_u=(0.5, 0.0, 0.0))
+    return {
+        "one_cell": cases.cavity((1, 1, 1), 6, kn=0.5, lid=0.3),
+        "line_y": cases.cavity((1, 7, 1), 6, kn=0.5, lid=0.3),
+        "m2_nocorr": dataclasses.replace(cases.cavity((5, 4, 3), 2, kn=1.0, lid=0.2, vmax=1.0), correction=False),
+        "aniso_m": cases.cavity((5, 4, 6), (6, 10, 4), kn=0.7, lid=0.3),
+        "kn_large": cases.cavity((6, 5, 4), 8, kn=1e4, lid=0.3),
+        "kn_small": cases.cavity((6, 5, 4), 8, kn=1e-3, lid=0.3),
+        "wide_m": cases.cavity((3, 3, 3), (96, 4, 4), kn=0.5, lid=0.3, vmax=6.0),
+        "lone_fluid_cell": lone,
+    }
+
+
+@pytest.mark.parametrize("name", ["one_cell", "line_y", "m2_nocorr", "aniso_m", "kn_large", "kn_small",
+                                  "wide_m", "lone_fluid_cell"])
+def test_degenerate_cases_match_oracle(oracle_mod, name):
+    """Single cell, a one-cell-wide line, two velocity nodes per axis (no
+    correction: its system is singular there), different node counts per
+    axis, free-molecular and near-continuum Knudsen numbers, 96 nodes along
+    one axis, and one fluid cell enclosed by solid."""
+    case = _degenerate_cases()[name]
+    s, o = run_pair(case, 2, oracle_mod)
+    err = field_errors(s.fields(), o.fields())
+    print(name, err, s.info())
+    fl = case.solid_flat() == 0 if case.solid is not None else slice(None)
+    # near the continuum limit (nu / (|xi| / h) ~ 1e2 here) an iteration
+    # changes f^S by O(|xi| tau / h), so rounding of the equilibrium (tables
+    # and raw moments on the GPU, direct sums in the oracle) is amplified by
+    # that ratio in the small velocity components
+    tol = FP64_TOL if name != "kn_small" else 2e-9
+    for k in ("rho", "ux", "uy", "uz", "T"):
+        assert err[k] <= tol, (k, err)
+    assert np.isfinite(s.fields()["rho"][fl]).all()
+
+
+def test_two_nodes_per_axis_with_correction_is_rejected(oracle_mod):
+    """With two nodes per axis the five-moment correction system is singular:
+    the oracle refuses the case and the HIP path reports it."""
+    case = cases.cavity((5, 4, 3), 2, kn=1.0, lid=0.2, vmax=1.0)
+    with pytest.raises(Exception):
+        oracle_mod.Oracle(case)
+    Solver = _solver()
+    from paper_1810_00348_amd import _lib as L
+    with pytest.raises(L.DvmError):
+        s = Solver(case)
+        s.init_uniform()
+        s.iterate(1)
