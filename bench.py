@@ -209,10 +209,17 @@ def time_to_residual(workloads, tol=1e-6, max_iters=3000):
     """Wall time to the residual tolerance from the uniform start (the full
     dvm_iterate loop including its per-iteration residual read-back): FP64
     storage, and FP32 storage until its noise floor followed by FP64 from the
-    same state; per-field max |x - x64| / max |x64| of the two solutions."""
+    same state; per-field max |x - x64| / max |x64| of the two solutions.
+    Then both again from the learned warm start (the committed network's
+    prediction, its time included)."""
     import numpy as np
     import torch
+    from paper_1810_00348_amd import warmstart as W
     from paper_1810_00348_amd.solver import Solver, solve_fp32_then_fp64
+    theta, chan_std, _ = W.load_weights(os.path.join(os.path.dirname(W.__file__), "data", "warmstart_unet.npz"))
+    big = max(max(case.n) for _, case in workloads)
+    net = W.WarmStartNet(max_grid=(big, big, big))
+    net.set_params(theta)
     for name, case in workloads:
         row = {"workload": name, "case": case.name, "points_per_iteration": case.points, "tol": tol}
         s = Solver(case, precision="f64")
@@ -238,6 +245,25 @@ def time_to_residual(workloads, tol=1e-6, max_iters=3000):
             err[key] = float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
         row["mixed_vs_f64_converged"] = err
         row["speedup_time_to_residual"] = round(row["f64"]["seconds"] / m["seconds"], 3)
+        torch.cuda.empty_cache()
+        # learned warm start: FP64, and FP32 then FP64
+        w = W.warm_started_solve(net, case, chan_std, tol=tol, max_iters=max_iters)
+        row["warm_f64"] = {"iters": w["iters"], "seconds": round(w["seconds"], 3), "converged": w["converged"],
+                           "fallback": w["fallback"]}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pred = W.predict(net, case, chan_std)
+        t_pred = time.perf_counter() - t0
+        mw = solve_fp32_then_fp64(case, tol, max_iters, init=pred, target_mass=1.0)
+        row["warm_f32_then_f64"] = {"iters": mw["iters"], "f32_iters": mw["f32_iters"], "f64_iters": mw["f64_iters"],
+                                    "seconds": round(mw["seconds"] + t_pred, 3), "converged": mw["converged"]}
+        a = mw["fields"]
+        row["warm_mixed_vs_f64_converged"] = {
+            key: float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+            for key, x, y in (("rho", a["rho"], f64["rho"]), ("ux", a["u"][0], f64["u"][0]),
+                              ("uy", a["u"][1], f64["u"][1]), ("uz", a["u"][2], f64["u"][2]),
+                              ("T", a["T"], f64["T"]))}
+        row["speedup_warm_mixed"] = round(row["f64"]["seconds"] / row["warm_f32_then_f64"]["seconds"], 3)
         torch.cuda.empty_cache()
         print(json.dumps(row), flush=True)
 

@@ -182,7 +182,7 @@ def selftest_wave_reduce(x: np.ndarray) -> np.ndarray:
 
 def solve_fp32_then_fp64(case: Case, tol: float = 1e-6, max_iters: int = 4000, switch_factor: float = 20.0,
                          window: int = 10, progress: float = 0.8, stall_below: float = 1e-3,
-                         device: str = "cuda:0"):
+                         device: str = "cuda:0", init=None, target_mass: float = 0.0):
     """Iterate with f in FP32 until the residual reaches switch_factor * tol
     (or tol itself, or stops improving), then continue from the same state
     (W, q, wall densities, reference mass and, for ES-BGK, the stress -- all
@@ -195,12 +195,19 @@ def solve_fp32_then_fp64(case: Case, tol: float = 1e-6, max_iters: int = 4000, s
     of the last ``window`` iterations is not below ``progress`` times the best
     of the window before.
 
+    init = (rho, u, T) starts from those fields (e.g. a learned prediction,
+    with target_mass the total mass to rescale them to) instead of the
+    uniform state.
+
     Returns a dict with the iterations and wall seconds of each phase."""
     import time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = Solver(case, precision="f32", device=device)
-    s.init_uniform()
+    if init is None:
+        s.init_uniform()
+    else:
+        s.init_fields(*init, target_mass=target_mass)
     hist = []
     it32 = 0
     ok = False
