@@ -1177,7 +1177,12 @@ extern __shared__ __align__(16) unsigned char dvm_sweep_lds[];
 // upwind operand from LDS.  Moments are accumulated from the node weight and
 // abscissa (three more multiplies per velocity instead of four per-velocity
 // weight products held in registers).
-template <typename S, int VL, int BX, int BY, bool NU>
+// O2 / ES: the second-order sweep and the ES-BGK Gaussian, as in the plain
+// body; with O2 the (f, F) pairs of the faces are prefetched together, the
+// first plane's F along z is staged into the second LDS plane with its f,
+// and the row-behind-the-face f that rebuilds F along y is prefetched for
+// the second row.
+template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false>
 __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __restrict__ params,
                                               const S* __restrict__ etab, const S* __restrict__ ghat,
                                               const double* __restrict__ lanetab, const int* __restrict__ bricks,
@@ -1222,8 +1227,24 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     const S* zin = zface + ((size_t)(o * 2 + ((K - 1) & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
     S* zout = zface + ((size_t)(o * 2 + (K & 1)) * ny * nx + (size_t)jr0 * nx + ir0) * fstride;
     S* sbuf = A.spec_on ? spec + (size_t)(o & 3) * ny * nx * fstride : nullptr;
+    const S* xgin = nullptr; S* xgout = nullptr;
+    const S* ygin = nullptr; S* ygout = nullptr;
+    const S* zgin = nullptr; S* zgout = nullptr;
+    S* sgbuf = nullptr;
+    if constexpr (O2) {
+        xgin = A.xgface + (xin - xface);
+        xgout = A.xgface + (xout - xface);
+        ygin = A.ygface + (yin - yface);
+        ygout = A.ygface + (yout - yface);
+        zgin = A.zgface + (zin - zface);
+        zgout = A.zgface + (zout - zface);
+        sgbuf = A.spec_on ? A.specg + (size_t)(o & 3) * ny * nx * fstride : nullptr;
+    }
 
     auto lds = [&](int jj, int ii, int v) -> S& { return plane[((jj * BX + ii) * VL + v) * 64 + lane]; };
+    auto ldz = [&](int jj, int ii, int v) -> S& {
+        return plane[((BY * BX + jj * BX + ii) * VL + v) * 64 + lane];
+    };
 
     // ---- lane constants
     const double* lt = lanetab + ((size_t)o * A.slots + slot) * A.lstride;
@@ -1261,13 +1282,21 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 const S* src = zin + ((size_t)jj * nx + ii) * fstride;
 #pragma unroll
                 for (int v = 0; v < VL; ++v) lds(jj, ii, v) = ldb(src, lofs + v * SB);
+                if constexpr (O2) {
+                    const S* gsrc = zgin + ((size_t)jj * nx + ii) * fstride;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) ldz(jj, ii, v) = ldb(gsrc, lofs + v * SB);
+                }
             }
     }
 
     // ---- loads of the next cell, issued one cell ahead
     S eb_n = (S)0, ec_n = (S)0, ex_n[VL], fx_n[VL], fy_n[VL];
+    // second order: F of the x / y faces; for the second row fy_n holds the
+    // f of the row behind the y face (the same face value the first row took)
+    S gx_n[VL], gy_n[VL];
 #pragma unroll
-    for (int v = 0; v < VL; ++v) ex_n[v] = fx_n[v] = fy_n[v] = (S)0;
+    for (int v = 0; v < VL; ++v) ex_n[v] = fx_n[v] = fy_n[v] = gx_n[v] = gy_n[v] = (S)0;
     // the next cell's record is read one cell ahead as well: its info word
     // and 1/tau (which also bring the record's first cache lines into the
     // scalar cache for the rest of its loads)
@@ -1287,30 +1316,46 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             const S* src = xin + ((size_t)kk * ny + jj) * fstride;
 #pragma unroll
             for (int v = 0; v < VL; ++v) fx_n[v] = ldb(src, lofs + v * SB);
+            if constexpr (O2) {
+                const S* gsrc = xgin + ((size_t)kk * ny + jj) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) gx_n[v] = ldb(gsrc, lofs + v * SB);
+            }
         }
-        if (jj == 0 && jr0 > 0) {
+        if ((jj == 0 || (O2 && jj == 1)) && jr0 > 0) {
             const S* src = yin + ((size_t)kk * nx + ii) * fstride;
 #pragma unroll
             for (int v = 0; v < VL; ++v) fy_n[v] = ldb(src, lofs + v * SB);
+        }
+        if constexpr (O2) {
+            if (jj == 0 && jr0 > 0) {
+                const S* gsrc = ygin + ((size_t)kk * nx + ii) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) gy_n[v] = ldb(gsrc, lofs + v * SB);
+            }
         }
     };
 
     const int ncell = iend * jend * kend;
     int ii = 0, jj = 0, kk = 0;
     prefetch(0, 0, 0);
-    S prev[VL];
+    S prev[VL], prevF[VL];
 #pragma unroll
-    for (int v = 0; v < VL; ++v) prev[v] = (S)0;
+    for (int v = 0; v < VL; ++v) prev[v] = prevF[v] = (S)0;
+    uint32_t ybnd = 0;  // second order: plane cells whose y upwind side is a boundary
     for (int n = 0; n < ncell; ++n) {
         const S eb = eb_n, ec = ec_n, nu = nu_n;
         const uint32_t info = info_n;
-        S ex[VL], fxp[VL], fyp[VL];
+        S ex[VL], fxp[VL], fyp[VL], gxp[VL], gyp[VL];
 #pragma unroll
         for (int v = 0; v < VL; ++v) {
             ex[v] = ex_n[v];
             fxp[v] = fx_n[v];
             fyp[v] = fy_n[v];
+            gxp[v] = gx_n[v];
+            gyp[v] = gy_n[v];
         }
+        if (O2 && ii == 0 && jj == 0) ybnd = 0;
         int ni = ii + 1, nj = jj, nk = kk;
         if (ni == iend) {
             ni = 0;
@@ -1325,11 +1370,22 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         const S* P = params + (size_t)cell * PSTRIDE;
         if (!(info & SOLID_BIT)) {
             S fx[VL], fy[VL], fz[VL];
+            S ux[VL], uy[VL], uz[VL];
+            bool ixf = false, iyf = false, izf = false;
             {
                 const uint32_t code = (info >> shX) & 15u;
                 if (code == 0) {
+                    if constexpr (O2) {
+                        ixf = true;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fx[v] = ii > 0 ? prev[v] : fxp[v];
+                        for (int v = 0; v < VL; ++v) {
+                            ux[v] = ii > 0 ? S(prev[v]) : S(fxp[v]);
+                            fx[v] = (ii > 0 ? S(prevF[v]) : S(gxp[v])) + (S)0.5 * ux[v];
+                        }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) fx[v] = ii > 0 ? prev[v] : fxp[v];
+                    }
                 } else {
                     const S rf = P[P_RHO_SIDE + sideX];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
@@ -1339,8 +1395,30 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             }
             {
                 const uint32_t code = (info >> shY) & 15u;
+                if constexpr (O2) {
+                    if (code != 0) ybnd |= 1u << (jj * BX + ii);
+                }
                 if (code == 0) {
-                    if (jj > 0) {
+                    if constexpr (O2) {
+                        iyf = true;
+                        if (jj > 0) {
+                            // F of the row behind, rebuilt from its own upwind row
+                            const bool edge = (ybnd >> ((jj - 1) * BX + ii)) & 1u;
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) {
+                                const S fu = lds(jj - 1, ii, v);
+                                const S f2 = jj >= 2 ? S(lds(jj - 2, ii, v)) : S(fyp[v]);
+                                uy[v] = fu;
+                                fy[v] = (edge ? fu : (S)1.5 * fu - (S)0.5 * f2) + (S)0.5 * fu;
+                            }
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) {
+                                uy[v] = fyp[v];
+                                fy[v] = gyp[v] + (S)0.5 * fyp[v];
+                            }
+                        }
+                    } else if (jj > 0) {
 #pragma unroll
                         for (int v = 0; v < VL; ++v) fy[v] = lds(jj - 1, ii, v);
                     } else {
@@ -1356,7 +1434,26 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             }
             {
                 const uint32_t code = (info >> shZ) & 15u;
-                if (code == 0) {
+                if (O2 && code == 0) {
+                    izf = true;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) {
+                        uz[v] = lds(jj, ii, v);
+                        fz[v] = ldz(jj, ii, v) + (S)0.5 * uz[v];
+                    }
+                } else if (O2 && code == CODE_SPECULAR) {
+                    // the mirror image beyond the symmetry plane
+                    izf = true;
+                    const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
+                    const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
+                    const S* src = sbuf + ((size_t)j * nx + i) * fstride;
+                    const S* gsrc = sgbuf + ((size_t)j * nx + i) * fstride;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) {
+                        uz[v] = ldb(src, lofs + v * SB);
+                        fz[v] = ldb(gsrc, lofs + v * SB) + (S)0.5 * uz[v];
+                    }
+                } else if (code == 0) {
 #pragma unroll
                     for (int v = 0; v < VL; ++v) fz[v] = lds(jj, ii, v);
                 } else if (code == CODE_SPECULAR) {
@@ -1381,6 +1478,8 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             const S cyz2 = cy * cy + cz * cz;
             const S Lyz = L0 + L2 * cy + L3 * cz;
             const S Qyz = qy * cy + qz * cz;
+            // ES-BGK: qx, qy, qz hold A_xy, A_xz, A_yz
+            const S Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
             // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
             // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
             S ayc = ay, azc = az, idx = (S)1, aynu = (S)0;
@@ -1391,15 +1490,46 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 aynu = ayc + azc + nu;
             }
             double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+            double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // second order: sum w (F_d - f)
+            S Fy[VL], Fz[VL];
+            const S kx = O2 && ixf ? (S)1.5 : (S)1, ky = O2 && iyf ? (S)1.5 : (S)1;
+            const S kz = O2 && izf ? (S)1.5 : (S)1;
+            const S ayk = ayc * ky, azk = azc * kz;
 #pragma unroll
             for (int v = 0; v < VL; ++v) {
                 const S cx = xix[v] - Ux;
                 const S c2 = cx * cx + cyz2;
-                const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
-                const S nfs = gyz * ex[v] * poly;
+                S nfs;
+                if constexpr (ES) {
+                    const S arg = -(cx * Bes + Ces);
+                    S cross;
+                    if constexpr (sizeof(S) == 8)
+                        cross = exp(arg);
+                    else
+                        cross = __expf(arg);
+                    nfs = gyz * ex[v] * (Lyz + L1 * cx + L4 * c2) * cross;
+                } else {
+                    const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
+                    nfs = gyz * ex[v] * poly;
+                }
                 const S axv = NU ? ax[v] * idx : ax[v];
                 const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
-                const S f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
+                S f;
+                if constexpr (O2) {
+                    f = num * fast_rcp(axv * kx + ayk + azk + nu);
+                    const S dx = ixf ? (S)0.5 * (f - ux[v]) : (S)0;
+                    const S dy = iyf ? (S)0.5 * (f - uy[v]) : (S)0;
+                    const S dz = izf ? (S)0.5 * (f - uz[v]) : (S)0;
+                    prevF[v] = f + dx;
+                    Fy[v] = f + dy;
+                    Fz[v] = f + dz;
+                    ldz(jj, ii, v) = Fz[v];
+                    e0 += wd[v] * xd[v] * (double)dx;
+                    e1 += wd[v] * (double)dy;
+                    e2 += wd[v] * (double)dz;
+                } else {
+                    f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
+                }
                 prev[v] = f;
                 lds(jj, ii, v) = f;
                 const double t0 = wd[v] * (double)f;
@@ -1415,16 +1545,31 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 S* dst = xout + ((size_t)kk * ny + jj) * fstride;
 #pragma unroll
                 for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+                if constexpr (O2) {
+                    S* g = xgout + ((size_t)kk * ny + jj) * fstride;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, prevF[v]);
+                }
             }
             if (jj == BY - 1 && wy) {
                 S* dst = yout + ((size_t)kk * nx + ii) * fstride;
 #pragma unroll
                 for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+                if constexpr (O2) {
+                    S* g = ygout + ((size_t)kk * nx + ii) * fstride;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, Fy[v]);
+                }
             }
             if (kk == A.bz - 1 && wz) {
                 S* dst = zout + ((size_t)jj * nx + ii) * fstride;
 #pragma unroll
                 for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+                if constexpr (O2) {
+                    S* g = zgout + ((size_t)jj * nx + ii) * fstride;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, Fz[v]);
+                }
             }
             if (sbuf != nullptr && !pz && kr0 + kk == nz - 1) {
                 const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
@@ -1432,9 +1577,14 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 S* dst = sbuf + ((size_t)j * nx + i) * fstride;
 #pragma unroll
                 for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+                if constexpr (O2) {
+                    S* g = sgbuf + ((size_t)j * nx + i) * fstride;
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, Fz[v]);
+                }
             }
 
-            double m[13];
+            double m[O2 ? 16 : 13];
             m[0] = u0;
             m[1] = u1;
             m[2] = xiy_d * u0;
@@ -1449,7 +1599,15 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             const double t2 = u2 + yz2 * u0;
             m[11] = xiy_d * t2;
             m[12] = xiz_d * t2;
-            const double tot = wave_reduce13(m);
+            double tot;
+            if constexpr (O2) {
+                m[13] = e0;
+                m[14] = xiy_d * e1;
+                m[15] = xiz_d * e2;
+                tot = wave_reduce16(m);
+            } else {
+                tot = wave_reduce13(m);
+            }
             if (writer) stb_nt(part + (size_t)cell * PREC, oridx, tot);
         }
         ii = ni;
@@ -1473,6 +1631,15 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
     sweep_body<S, VL, BX, BY, NU>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
                               A.spec, A.partial, plane);
+}
+
+// second-order upwind and/or ES-BGK (uniform meshes), pipelined body
+template <typename S, int VL, int BX, int BY, bool O2, bool ES>
+__global__ __launch_bounds__(64) void sweep_kernel_pfx(const SweepArgs<S> A)
+{
+    S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
+    sweep_body_pf<S, VL, BX, BY, false, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface,
+                                                A.yface, A.zface, A.spec, A.partial, plane);
 }
 
 // second-order upwind and/or ES-BGK (uniform meshes, plain body)
@@ -1528,11 +1695,20 @@ hipError_t launch_sweep_t(int pipelined, const void* args, hipStream_t st)
 }
 
 template <typename T, int V, int BXX, int BYY>
-hipError_t launch_sweep_x(int order2, int esbgk, const void* args, hipStream_t st)
+hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, const void* args, hipStream_t st)
 {
     const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
     // the plane of f, and with the second order the plane of F along z
     const size_t lds = (size_t)(order2 ? 2 : 1) * BYY * BXX * V * 64 * sizeof(T);
+    if (pipelined) {
+        if (order2 && esbgk)
+            sweep_kernel_pfx<T, V, BXX, BYY, true, true><<<a.nblocks, 64, lds, st>>>(a);
+        else if (order2)
+            sweep_kernel_pfx<T, V, BXX, BYY, true, false><<<a.nblocks, 64, lds, st>>>(a);
+        else
+            sweep_kernel_pfx<T, V, BXX, BYY, false, true><<<a.nblocks, 64, lds, st>>>(a);
+        return hipGetLastError();
+    }
     if (order2 && esbgk)
         sweep_kernel_x<T, V, BXX, BYY, true, true><<<a.nblocks, 64, lds, st>>>(a);
     else if (order2)
@@ -1549,7 +1725,7 @@ hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int non
         if (nonuniform) return hipErrorInvalidValue;
 #define X(T, V, BXX, BYY)                                                     \
         if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) \
-            return launch_sweep_x<T, V, BXX, BYY>(order2, esbgk, args, st);
+            return launch_sweep_x<T, V, BXX, BYY>(pipelined, order2, esbgk, args, st);
         DVM_SWEEP_VARIANTS_O2(X)
 #undef X
         return hipErrorInvalidValue;

@@ -167,8 +167,7 @@ void derive_schedule(dvm_ctx* c)
     c->BX = bx;
     c->BY = by;
     c->BZ = env_int("DVM_BZ", 8);
-    // the second-order and ES-BGK sweeps have the plain body only
-    c->PF = (o2 || es) ? 0 : env_int("DVM_PF", pf) != 0;
+    c->PF = env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
     c->nby = (c->g.ny + c->BY - 1) / c->BY;

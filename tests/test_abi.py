@@ -167,7 +167,8 @@ def test_velocity_groups_arguments_and_workspace(L):
 
 def test_order_arguments(L):
     """dvm_set_order: 1 or 2, uniform meshes only, before binding; the
-    second order uses the plain sweep body and doubles the face buffers."""
+    second order keeps the schedule (pipelined body at 4 per lane) and
+    doubles the face buffers."""
     import numpy as np
     from paper_1810_00348_amd import cases
     lib = L.lib()
@@ -179,7 +180,7 @@ def test_order_arguments(L):
     assert lib.dvm_set_order(h, 2) == 0
     info = L.Info()
     assert lib.dvm_get_info(h, C.byref(info)) == 0
-    assert info.pipelined == 0 and (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 2, 2)
+    assert info.pipelined == 1 and (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 2, 2)
     n2 = C.c_size_t()
     assert lib.dvm_required_workspace(h, C.byref(n2)) == 0
     assert n2.value > n1.value
@@ -222,7 +223,8 @@ def test_model_arguments(L):
     assert lib.dvm_set_model(h, 2) == -1
     assert lib.dvm_set_model(h, 1) == 0
     info = L.Info()
-    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.pipelined == 0
+    # the usual schedule: 5 nodes per x half in FP64 -> 2 per lane, plain body
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and (info.vel_per_lane, info.pipelined) == (2, 0)
     P = (C.c_double * (6 * case.ncells))()
     assert lib.dvm_get_stress(h, P) == -2          # no state yet
     hy = cases.stretched_axis(5, 1.0, 1.3)

@@ -348,16 +348,22 @@ def test_second_order_matches_oracle(oracle_mod, name):
     assert np.abs(rwg - rwo).max() <= FP64_TOL * np.abs(rwo).max()
 
 
+@pytest.mark.parametrize("pf", [0, 1])
 @pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2)])
-@pytest.mark.parametrize("name", ["ragged", "cube_half"])
-def test_second_order_sweep_variants(oracle_mod, monkeypatch, name, vl, bx, by):
+@pytest.mark.parametrize("name", ["ragged", "cube_half", "es_cube_half"])
+def test_second_order_sweep_variants(oracle_mod, monkeypatch, name, vl, bx, by, pf):
+    """Plain and pipelined bodies of the second-order sweep (and of the
+    second-order ES-BGK sweep) at every built shape."""
     monkeypatch.setenv("DVM_VL", str(vl))
     monkeypatch.setenv("DVM_BX", str(bx))
     monkeypatch.setenv("DVM_BY", str(by))
-    case = _o2_cases()[name]
+    monkeypatch.setenv("DVM_PF", str(pf))
+    case = _o2_cases()[name] if name != "es_cube_half" else dataclasses.replace(_o2_cases()["cube_half"],
+                                                                               model="esbgk")
     s, o = run_pair(case, 2, oracle_mod)
     info = s.info()
     assert (info["vel_per_lane"], info["brick"][0], info["brick"][1]) == (vl, bx, by), info
+    assert info["sweep_kernel"] == ("sweep_kernel_pf" if pf else "sweep_kernel"), info
     err = field_errors(s.fields(), o.fields())
     for k in ("rho", "ux", "uy", "uz", "T"):
         assert err[k] <= FP64_TOL, (k, err)
@@ -564,3 +570,21 @@ def test_two_nodes_per_axis_with_correction_is_rejected(oracle_mod):
         s = Solver(case)
         s.init_uniform()
         s.iterate(1)
+
+
+@pytest.mark.parametrize("pf", [0, 1])
+@pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2)])
+def test_esbgk_sweep_variants(oracle_mod, monkeypatch, vl, bx, by, pf):
+    monkeypatch.setenv("DVM_VL", str(vl))
+    monkeypatch.setenv("DVM_BX", str(bx))
+    monkeypatch.setenv("DVM_BY", str(by))
+    monkeypatch.setenv("DVM_PF", str(pf))
+    case = _es_cases()["ragged"]
+    s, o = run_pair(case, 2, oracle_mod, init=cases.random_fields(case, seed=62))
+    info = s.info()
+    assert (info["vel_per_lane"], info["brick"][0], info["brick"][1], info["sweep_kernel"]) == \
+        (vl, bx, by, "sweep_kernel_pf" if pf else "sweep_kernel"), info
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "uy", "uz", "T"):
+        assert err[k] <= FP64_TOL, (k, err)
+    assert np.abs(s.stress() - o.stress()).max() <= FP64_TOL * np.abs(o.stress()).max()
