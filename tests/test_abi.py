@@ -223,8 +223,9 @@ def test_model_arguments(L):
     assert lib.dvm_set_model(h, 2) == -1
     assert lib.dvm_set_model(h, 1) == 0
     info = L.Info()
-    # the usual schedule: 5 nodes per x half in FP64 -> 2 per lane, plain body
-    assert lib.dvm_get_info(h, C.byref(info)) == 0 and (info.vel_per_lane, info.pipelined) == (2, 0)
+    # the usual schedule: 5 nodes per x half in FP64 -> 1 per lane (2 would
+    # leave a sixth of the slots empty), plain body
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and (info.vel_per_lane, info.pipelined) == (1, 0)
     P = (C.c_double * (6 * case.ncells))()
     assert lib.dvm_get_stress(h, P) == -2          # no state yet
     hy = cases.stretched_axis(5, 1.0, 1.3)
