@@ -56,6 +56,7 @@ struct Consts {
     int closed;
     int order2;           // second-order upwind: wall fluxes take the face values
     int esbgk;            // ES-BGK model in place of Shakhov's
+    int xuniform;         // the x velocity axis is uniform (nodes a fixed step apart)
     double kind_rho[8];   // fixed emission density (free stream), per kind
     int kind_wall[8];     // 1: density from non-penetration
 };

@@ -334,6 +334,13 @@ __global__ __launch_bounds__(64) void params_es_kernel(Consts C, DevPtrs D, cons
         // lane l takes the (y, z) rows l, l + 64, ...
         double sm[14];
         for (int k = 0; k < 14; ++k) sm[k] = 0.0;
+        // On a uniform x axis the exponent q(a) = Axx cx^2 / 2 + cx B + row is
+        // quadratic in the node index, so exp(-q) follows from two products
+        // per node: g(a+1) = g(a) r(a), r(a+1) = r(a) s with s = exp(-Axx h^2)
+        // -- used on a row when neither end's exp(-q) nor any step factor
+        // leaves the double range (else one exponential per node).
+        const double hx = C.xuniform ? D.xi[1] - D.xi[0] : 0.0;
+        const double sx = exp(-Axx * hx * hx);
         for (int r = lane; r < C.my * C.mz; r += 64) {
             const int ky = r % C.my, kz = r / C.my;
             const double cz = D.xi[2 * MAXM + kz] - Uz;
@@ -342,26 +349,55 @@ __global__ __launch_bounds__(64) void params_es_kernel(Consts C, DevPtrs D, cons
             const double row = 0.5 * Ayy * cy * cy + 0.5 * Azz * cz * cz + Ayz * cy * cz;
             const double B = Axy * cy + Axz * cz;
             const double cyz2 = cy * cy + cz * cz;
+            const double c0 = D.xi[0] - Ux, c1 = D.xi[C.mx - 1] - Ux;
+            const double q0 = 0.5 * Axx * c0 * c0 + c0 * B + row;
+            const double q1 = 0.5 * Axx * c1 * c1 + c1 * B + row;
+            const double d0 = Axx * hx * (c0 + 0.5 * hx) + hx * B;  // q(1) - q(0)
+            const double d1 = d0 + Axx * hx * hx * (C.mx - 2);      // q(M-1) - q(M-2)
+            const bool rec = C.xuniform && fabs(q0) < 600.0 && fabs(q1) < 600.0 && fabs(d0) < 600.0 &&
+                             fabs(d1) < 600.0;
+            double g = rec ? exp(-q0) : 0.0, rr = rec ? exp(-d0) : 0.0;
+            // the row's sums of w e cx^p, p = 0..4; the y and z factors of
+            // the monomials are applied once per row
+            double r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0;
             for (int kx = 0; kx < C.mx; ++kx) {
                 const double cx = D.xi[kx] - Ux;
-                const double t = wyz * D.wt[kx] * pre * exp(-(0.5 * Axx * cx * cx + cx * B + row));
-                const double c2 = cx * cx + cyz2;
-                const double tx = t * cx, ty = t * cy, tz = t * cz, tc = t * c2;
-                sm[0] += t;
-                sm[1] += tx;
-                sm[2] += ty;
-                sm[3] += tz;
-                sm[4] += tx * cx;
-                sm[5] += ty * cy;
-                sm[6] += tz * cz;
-                sm[7] += tx * cy;
-                sm[8] += tx * cz;
-                sm[9] += ty * cz;
-                sm[10] += tc * cx;
-                sm[11] += tc * cy;
-                sm[12] += tc * cz;
-                sm[13] += tc * c2;
+                double e;
+                if (rec) {
+                    e = g;
+                    g *= rr;
+                    rr *= sx;
+                } else {
+                    e = exp(-(0.5 * Axx * cx * cx + cx * B + row));
+                }
+                const double t0 = D.wt[kx] * e, t1 = t0 * cx, t2 = t1 * cx, t3 = t2 * cx;
+                r0 += t0;
+                r1 += t1;
+                r2 += t2;
+                r3 += t3;
+                r4 += t3 * cx;
             }
+            const double f = wyz * pre;
+            r0 *= f;
+            r1 *= f;
+            r2 *= f;
+            r3 *= f;
+            r4 *= f;
+            // sums over the row of t, t cx, t cy, t cz, ... with t = w G
+            sm[0] += r0;
+            sm[1] += r1;
+            sm[2] += cy * r0;
+            sm[3] += cz * r0;
+            sm[4] += r2;
+            sm[5] += cy * cy * r0;
+            sm[6] += cz * cz * r0;
+            sm[7] += cy * r1;
+            sm[8] += cz * r1;
+            sm[9] += cy * cz * r0;
+            sm[10] += r3 + cyz2 * r1;             // cx |c|^2
+            sm[11] += cy * (r2 + cyz2 * r0);      // cy |c|^2
+            sm[12] += cz * (r2 + cyz2 * r0);      // cz |c|^2
+            sm[13] += r4 + 2.0 * cyz2 * r2 + cyz2 * cyz2 * r0;  // |c|^4
         }
         for (int k = 0; k < 14; ++k)
             for (int o = 32; o > 0; o >>= 1) sm[k] += __shfl_xor(sm[k], o, 64);

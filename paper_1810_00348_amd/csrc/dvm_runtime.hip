@@ -292,6 +292,7 @@ Consts make_consts(const dvm_ctx* c)
     C.closed = c->closed;
     C.order2 = c->order == 2;
     C.esbgk = c->model == 1;
+    C.xuniform = c->vnode[0].empty() ? 1 : 0;
     for (int k = 0; k < 8; ++k) {
         C.kind_rho[k] = c->kind_rho[k];
         C.kind_wall[k] = c->kind_wall[k];
