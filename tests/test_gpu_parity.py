@@ -450,10 +450,12 @@ def _es_cases():
     out = {k: dataclasses.replace(v, model="esbgk") for k, v in
            {"ragged": a, "oddM": b, "cube_half": c, "cavity_m16": e}.items()}
     out["order2"] = dataclasses.replace(out["ragged"], order=2)
+    gr = cases.graded_velocity_axis(10, 5.0, 1.2)
+    out["graded_axes"] = dataclasses.replace(out["cube_half"], velocity_axes=(gr, gr, gr))   # no x recurrence
     return out
 
 
-@pytest.mark.parametrize("name", ["ragged", "oddM", "cube_half", "cavity_m16", "order2"])
+@pytest.mark.parametrize("name", ["ragged", "oddM", "cube_half", "cavity_m16", "order2", "graded_axes"])
 def test_esbgk_matches_oracle(oracle_mod, name):
     """ES-BGK (FP64): fields, wall densities and the stress state against
     the oracle's ES-BGK."""
