@@ -166,7 +166,9 @@ void derive_schedule(dvm_ctx* c)
     c->VL = vl;
     c->BX = bx;
     c->BY = by;
-    c->BZ = env_int("DVM_BZ", 8);
+    // cells per brick column: 12 for the 2x2 FP64 bricks (measured on the
+    // cavity 64^3 x 32^3: +2.8 % over 8, 16 is slower), 8 otherwise
+    c->BZ = env_int("DVM_BZ", (f64 && vl == 4 && bx == 2 && by == 2) ? 12 : 8);
     c->PF = env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
