@@ -205,6 +205,52 @@ def solve(case, prec, max_iters, tol, desc):
     print(json.dumps(out), flush=True)
 
 
+def warmstart_kernels(n, steps, warmup):
+    """The warm-start U-Net's BF16 MFMA convolutions against the dense BF16
+    peak: algorithmic FLOPs 2 * voxels * taps * c_in * c_out per convolution
+    (levels n^3, (n/2)^3, (n/4)^3), forward alone and one training step
+    (forward, input and weight gradients: three times the forward FLOPs)."""
+    import numpy as np
+    import torch
+    from paper_1810_00348_amd import warmstart as W
+    net = W.WarmStartNet(max_grid=(n, n, n))
+    net.set_params(W.init_theta(7))
+    level = {"e1a": 0, "e1b": 0, "e2a": 1, "e2b": 1, "b1": 2, "b2": 2, "d2a": 1, "d2b": 1, "d1a": 0,
+             "d1b": 0, "out": 0}
+    fl = sum(2.0 * (n ** 3 / 8 ** level[name]) * taps * ci * co for name, ci, co, taps, _ in W.layer_table())
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal((n, n, n, W.NET_IN)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((n, n, n, W.NET_OUT)).astype(np.float32)).cuda()
+    m = torch.ones((n, n, n), dtype=torch.float32, device="cuda")
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    def train():
+        net.zero_grad()
+        net.forward(x)
+        net.backward_mse(t, m)
+        net.adam_step(1e-4)
+
+    tf = timed(lambda: net.forward(x))
+    tt = timed(train)
+    out = {"metric": "warm-start U-Net BF16 MFMA throughput", "grid": n, "steps": steps,
+           "forward_ms": round(tf * 1e3, 3), "train_step_ms": round(tt * 1e3, 3),
+           "forward_gflop": round(fl / 1e9, 2),
+           "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": 2500.0,
+                        "achieved_forward": round(fl / tf / 1e12, 2), "achieved_train": round(3 * fl / tt / 1e12, 2),
+                        "frac_forward": round(fl / tf / 1e12 / 2500.0, 4),
+                        "frac_train": round(3 * fl / tt / 1e12 / 2500.0, 4)}}
+    print(json.dumps(out), flush=True)
+
+
 def time_to_residual(workloads, tol=1e-6, max_iters=3000):
     """Wall time to the residual tolerance from the uniform start (the full
     dvm_iterate loop including its per-iteration residual read-back): FP64
@@ -283,6 +329,8 @@ def main():
                     help="solve the workload from the uniform start for up to ITERS iterations "
                          "(or to --tol), one progress line per iteration")
     ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--warmstart", type=int, default=0, metavar="GRID",
+                    help="time the warm-start U-Net (forward, and one training step) on a GRID^3 grid")
     ap.add_argument("--model", default="shakhov", choices=("shakhov", "esbgk"),
                     help="collision model (esbgk: the ellipsoidal statistical BGK model)")
     ap.add_argument("--order", type=int, default=1, choices=(1, 2),
@@ -314,6 +362,10 @@ def main():
         print("bench.py: this build runs on one GPU only (the sweep shards by velocity across "
               "GPUs by design, but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.warmstart > 0:
+        warmstart_kernels(args.warmstart, args.steps, args.warmup)
+        return
 
     if args.time_to_residual:
         from paper_1810_00348_amd import cases

@@ -194,15 +194,26 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const WgradArgs A)
     }
 }
 
-// bias gradient: gb[o] += sum_v gy[v][o]
+// bias gradient: gb[o] += sum_v gy[v][o].  The block's threads cover
+// rows = 256 / gys voxels of all gys (padded) channels at a time, so that
+// consecutive threads read consecutive channels of a voxel; the rows'
+// partial sums are combined in LDS, one atomic per channel and block.
 __global__ __launch_bounds__(256) void bgrad_kernel(const bf16* gy, int gys, int co, int V, int vchunk, float* gb)
 {
-    const int o = threadIdx.x;
-    if (o >= co) return;
+    __shared__ float red[256];
+    const int t = threadIdx.x;
+    const int rows = 256 / gys;
+    const int o = t % gys, r = t / gys;
     const int vbeg = blockIdx.x * vchunk, vend = min(V, vbeg + vchunk);
     float s = 0.f;
-    for (int v = vbeg; v < vend; ++v) s += bf2f(gy[(size_t)v * gys + o]);
-    atomicAdd(&gb[o], s);
+    if (r < rows)
+        for (int v = vbeg + r; v < vend; v += rows) s += bf2f(gy[(size_t)v * gys + o]);
+    red[t] = s;
+    __syncthreads();
+    if (r == 0 && o < co) {
+        for (int k = 1; k < rows; ++k) s += red[k * gys + o];
+        atomicAdd(&gb[o], s);
+    }
 }
 
 // pre-activation gradient (BF16, padded channels zero): g * (act > 0) for a
