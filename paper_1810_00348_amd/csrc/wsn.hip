@@ -146,6 +146,13 @@ struct WgradArgs {
 
 __global__ __launch_bounds__(64) void wgrad_kernel(const WgradArgs A)
 {
+    // Per step of 32 voxels the wave loads the gradient tile gy[32 v][16 o]
+    // and the shifted input tile x[32 v + tap][16 i] with 16-byte loads along
+    // the channels (lanes 2v and 2v+1 take the two halves of voxel v), and
+    // transposes both through LDS into the MFMA's K = voxel order.
+    constexpr int LS = 40;  // LDS row stride (bf16): 80-byte rows, 16-byte aligned
+    __shared__ __align__(16) bf16 sa[16 * LS];
+    __shared__ __align__(16) bf16 sb[16 * LS];
     const int lane = threadIdx.x;
     int t = blockIdx.x;
     const int cit = t % A.citiles;
@@ -156,40 +163,44 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const WgradArgs A)
     const int vbeg = blockIdx.y * A.vchunk;
     const int vend = min(V, vbeg + A.vchunk);
     const int r = lane & 15, g = lane >> 4;
-    const int o = cot * 16 + r;   // A row (output channel)
-    const int i = cit * 16 + r;   // B column (input channel)
+    const int o0 = cot * 16, i0 = cit * 16;
+    const int lv = lane >> 1, hh = lane & 1;   // this lane's voxel in the step, channel half
     int dz, dy, dx;
     tap_offset(A.taps, tap, dz, dy, dx);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int vb = vbeg; vb < vend; vb += 32) {
-        bf16 av[8], bv[8];
+        const int v = vb + lv;
+        uint4 ua = make_uint4(0, 0, 0, 0), ub = make_uint4(0, 0, 0, 0);
+        if (v < vend) {
+            if (o0 + 8 * hh < A.coutp)
+                ua = *reinterpret_cast<const uint4*>(A.gy + (size_t)v * A.gys + o0 + 8 * hh);
+            const int ww = v % A.W, yh = (v / A.W) % A.H, zd = v / (A.W * A.H);
+            const int zz = zd + dz, yy = yh + dy, xx = ww + dx;
+            if (i0 + 8 * hh < A.cinp && zz >= 0 && zz < A.D && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+                ub = *reinterpret_cast<const uint4*>(A.x + (size_t)((zz * A.H + yy) * A.W + xx) * A.xs + i0 + 8 * hh);
+        }
+        bf16 ea[8], eb[8];
+        __builtin_memcpy(ea, &ua, 16);
+        __builtin_memcpy(eb, &ub, 16);
+        __syncthreads();  // the previous step's reads are done
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int v = vb + 8 * g + e;
-            bf16 aa = 0, bb = 0;
-            if (v < vend) {
-                if (o < A.coutp) aa = A.gy[(size_t)v * A.gys + o];
-                const int ww = v % A.W, hh = (v / A.W) % A.H, dd = v / (A.W * A.H);
-                const int zz = dd + dz, yy = hh + dy, xx = ww + dx;
-                if (i < A.cinp && zz >= 0 && zz < A.D && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
-                    bb = A.x[(size_t)((zz * A.H + yy) * A.W + xx) * A.xs + i];
-            }
-            av[e] = aa;
-            bv[e] = bb;
+            sa[(8 * hh + e) * LS + lv] = ea[e];
+            sb[(8 * hh + e) * LS + lv] = eb[e];
         }
-        uint4 ua, ub;
-        __builtin_memcpy(&ua, av, 16);
-        __builtin_memcpy(&ub, bv, 16);
-        const bf16x8 a = __builtin_bit_cast(bf16x8, ua);
-        const bf16x8 b = __builtin_bit_cast(bf16x8, ub);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        __syncthreads();
+        // lane (r, g): channel r of the tile, voxels 8g .. 8g+7 of the step
+        const uint4 qa = *reinterpret_cast<const uint4*>(sa + r * LS + 8 * g);
+        const uint4 qb = *reinterpret_cast<const uint4*>(sb + r * LS + 8 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, qa),
+                                                       __builtin_bit_cast(bf16x8, qb), acc, 0, 0, 0);
     }
     // lane holds rows (output channels) 4g..4g+3 of column (input channel) r
-    const int ic = cit * 16 + r;
+    const int ic = i0 + r;
     if (ic >= A.ci) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int oc = cot * 16 + 4 * g + e;
+        const int oc = o0 + 4 * g + e;
         if (oc < A.co) atomicAdd(&A.grad[((size_t)tap * A.co + oc) * A.ci + ic], acc[e]);
     }
 }
