@@ -84,22 +84,51 @@ struct ConvArgs {
     int cout_valid;
 };
 
+// NT output-channel tiles per wave share each A fragment (one input load
+// feeds NT matrix-core steps).
+template <int NT>
 __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int V = A.D * A.H * A.W;
     const int v0 = (blockIdx.x * 4 + wv) * 16;
     if (v0 >= V) return;
-    const int co0 = blockIdx.y * 16;
+    const int co0 = blockIdx.y * 16 * NT;
     const int r = lane & 15, g = lane >> 4;
     const int va = v0 + r;
     const int wa = va % A.W, ha = (va / A.W) % A.H, da = va / (A.W * A.H);
-    const int col = co0 + r;
     const int K = A.taps * A.cinp;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    floatx4 acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = {0.f, 0.f, 0.f, 0.f};
+    if (A.cinp % 32 == 0) {
+        // every 32-wide K step lies in one tap: the tap's neighbour and
+        // weight rows are set up once, the channel steps only add offsets
+        for (int tap = 0; tap < A.taps; ++tap) {
+            int dz, dy, dx;
+            tap_offset(A.taps, tap, dz, dy, dx);
+            const int zz = da + dz, yy = ha + dy, xx = wa + dx;
+            const bool ok = va < V && zz >= 0 && zz < A.D && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W;
+            const bf16* xp = A.x + (size_t)(ok ? (zz * A.H + yy) * A.W + xx : 0) * A.xs + 8 * g;
+            const bf16* wp = A.w + ((size_t)tap * A.coutp + co0 + r) * A.cinp + 8 * g;
+            for (int c0 = 0; c0 < A.cinp; c0 += 32) {
+                const bf16x8 a = ok ? load8(xp + c0) : zero8();
+                bf16x8 b[NT];
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    b[n] = co0 + 16 * n + r < A.coutp ? load8(wp + (size_t)16 * n * A.cinp + c0) : zero8();
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], acc[n], 0, 0, 0);
+            }
+        }
+    } else
     for (int kb = 0; kb < K; kb += 32) {
         const int k = kb + 8 * g;
-        bf16x8 a = zero8(), b = zero8();
+        bf16x8 a = zero8();
+        bf16x8 b[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) b[n] = zero8();
         if (k < K) {
             const int tap = k / A.cinp, c0 = k - tap * A.cinp;
             int dz, dy, dx;
@@ -107,22 +136,30 @@ __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A)
             const int zz = da + dz, yy = ha + dy, xx = wa + dx;
             if (va < V && zz >= 0 && zz < A.D && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
                 a = load8(A.x + (size_t)((zz * A.H + yy) * A.W + xx) * A.xs + c0);
-            if (col < A.coutp) b = load8(A.w + ((size_t)tap * A.coutp + col) * A.cinp + c0);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    }
-    // lane holds rows 4g..4g+3 of column r
-    const int c = co0 + r;
-    if (c >= A.cout_valid) return;
-    const float bb = A.bias ? A.bias[c] : 0.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int v = v0 + 4 * g + i;
-        if (v >= V) continue;
-        float val = acc[i] + bb;
-        if (A.relu) val = fmaxf(val, 0.f);
-        if (A.yf) A.yf[(size_t)v * A.yfs + c] = val;
-        if (A.yb) A.yb[(size_t)v * A.ybs + c] = f2bf(val);
+            for (int n = 0; n < NT; ++n) {
+                const int col = co0 + 16 * n + r;
+                if (col < A.coutp) b[n] = load8(A.w + ((size_t)tap * A.coutp + col) * A.cinp + c0);
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], acc[n], 0, 0, 0);
+    }
+    // lane holds rows 4g..4g+3 of column r of each tile
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int c = co0 + 16 * n + r;
+        if (c >= A.cout_valid) continue;
+        const float bb = A.bias ? A.bias[c] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = v0 + 4 * g + i;
+            if (v >= V) continue;
+            float val = acc[n][i] + bb;
+            if (A.relu) val = fmaxf(val, 0.f);
+            if (A.yf) A.yf[(size_t)v * A.yfs + c] = val;
+            if (A.yb) A.yb[(size_t)v * A.ybs + c] = f2bf(val);
+        }
     }
 }
 
@@ -497,8 +534,15 @@ int conv(wsn_ctx* c, const Layer& l, const bf16* x, int xs, int D, int H, int W,
     a.relu = grad_form ? 0 : l.relu;
     a.cout_valid = cout_valid;
     const int V = D * H * W;
-    dim3 grid((V / 16 + 3) / 4 + 1, (coutp + 15) / 16);
-    conv_kernel<<<grid, 256, 0, c->st>>>(a);
+    const int tiles = (coutp + 15) / 16;
+    const int nt = tiles >= 4 ? 4 : tiles >= 2 ? 2 : 1;
+    dim3 grid((V / 16 + 3) / 4 + 1, (tiles + nt - 1) / nt);
+    if (nt == 4)
+        conv_kernel<4><<<grid, 256, 0, c->st>>>(a);
+    else if (nt == 2)
+        conv_kernel<2><<<grid, 256, 0, c->st>>>(a);
+    else
+        conv_kernel<1><<<grid, 256, 0, c->st>>>(a);
     WCHK(hipGetLastError());
     return 0;
 }
