@@ -121,6 +121,52 @@ class Solver:
         st = L.check(L.lib().dvm_iterate(self._h, n, tol, C.byref(it), C.byref(r)))
         return it.value, r.value, st == L.DVM_OK
 
+    def run(self, max_iters: int, tol: float = 0.0, log=None, diverge_window: int = 0):
+        """Iterate one step at a time up to max_iters (or residual <= tol),
+        writing one JSON line per iteration to the open file ``log`` if given
+        (iteration, residual per field, total mass, wall seconds, GPt/s), and
+        stopping with ``diverged`` set when the residual has grown for
+        ``diverge_window`` iterations in a row above its starting value.
+        Returns a dict: iterations, residual, converged, diverged, seconds."""
+        import json
+        import time
+        hist = []
+        diverged = converged = False
+        t_all = time.perf_counter()
+        it = 0
+        for it in range(1, max_iters + 1):
+            t0 = time.perf_counter()
+            _, r, ok = self.iterate(1, tol=tol)
+            dt = time.perf_counter() - t0
+            hist.append(r)
+            if log is not None:
+                W, _, _, M0 = self.state()
+                rec = {"it": it, "residual": r, "residual_fields": [float(x) for x in self.residual(True)],
+                       "mass_rel": float(self.total_mass(W) / M0) if M0 else None, "t_iter": dt,
+                       "gpt_per_s": self.case.points / dt / 1e9}
+                log.write(json.dumps(rec) + "\n")
+                log.flush()
+            if ok:
+                converged = True
+                break
+            if diverge_window and diverging(hist, diverge_window):
+                diverged = True
+                break
+        return {"iterations": it, "residual": hist[-1] if hist else float("nan"), "converged": converged,
+                "diverged": diverged, "seconds": time.perf_counter() - t_all}
+
+    def total_mass(self, W=None) -> float:
+        """Sum of rho times cell volume over the fluid cells."""
+        if W is None:
+            W = self.state()[0]
+        c = self.case
+        if c.spacing is not None:
+            hx, hy, hz = (np.full(n, L / n) if h is None else np.asarray(h) for n, L, h in zip(c.n, c.L, c.spacing))
+        else:
+            hx, hy, hz = (np.full(n, L / n) for n, L in zip(c.n, c.L))
+        vol = (hz[:, None, None] * hy[None, :, None] * hx[None, None, :]).ravel()
+        return float((W[0] * vol).sum())
+
     def residual(self, per_field: bool = False):
         r = np.zeros(5)
         L.check(L.lib().dvm_get_residuals(self._h, _ptr(r)))
@@ -171,6 +217,16 @@ class Solver:
         a = C.c_double(); b = C.c_double(); d = C.c_double(); n = C.c_int()
         L.check(L.lib().dvm_get_timings(self._h, C.byref(a), C.byref(b), C.byref(d), C.byref(n)))
         return {"params_ms": a.value, "sweep_ms": b.value, "finalize_ms": d.value, "iterations": n.value}
+
+
+def diverging(history, window: int) -> bool:
+    """True when the last ``window`` residuals each grew and the latest is
+    above the first of the run (a run that has started to blow up rather
+    than a transient bump on the way down)."""
+    if window <= 0 or len(history) < window + 1:
+        return False
+    tail = history[-(window + 1):]
+    return all(b > a for a, b in zip(tail, tail[1:])) and history[-1] > history[0]
 
 
 def selftest_wave_reduce(x: np.ndarray) -> np.ndarray:

@@ -85,3 +85,15 @@ def test_field_difference_norms():
     assert abs(d["rho"] - 0.1 / 1.2) < 1e-12 and d["T"] == 0.0
     dv = W.field_difference(a, b, "dev")
     assert abs(dv["rho"] - 0.1 / 0.2) < 1e-12
+
+
+def test_divergence_detector():
+    from paper_1810_00348_amd.solver import diverging
+    down = [1.0, 0.5, 0.3, 0.2, 0.25, 0.15, 0.1]
+    assert not any(diverging(down[:k], 3) for k in range(len(down) + 1))
+    up = [1.0, 0.5, 0.6, 0.9, 1.3, 2.0]
+    # three growths in a row and above the start from the fifth value on
+    assert [diverging(up[:k], 3) for k in range(len(up) + 1)] == [False] * 5 + [True, True]
+    assert not diverging(up, 0)
+    # growing, but still below the start: not yet
+    assert not diverging([1.0, 0.1, 0.2, 0.3, 0.4], 3)
