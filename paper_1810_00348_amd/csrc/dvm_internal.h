@@ -90,6 +90,7 @@ struct SweepArgs {
     S* zgface;
     S* specg;
     double* partial;      // [8*ntiles][N][PREC]
+    double rdx;           // 1 / h_x on a uniform mesh, 1 on a non-uniform one
     int nx, ny, nz, N, mx, my, MT, NV;
     int nbx, nby, nbz, bz;
     int ntiles, slots, lstride;

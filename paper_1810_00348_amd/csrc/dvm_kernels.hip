@@ -765,6 +765,12 @@ __device__ __forceinline__ void stb(T* base, unsigned off, T v)
 {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
+// an empty statement that reads x: x stays in its register up to here
+template <typename T>
+__device__ __forceinline__ void keep_alive(T x)
+{
+    asm volatile("" ::"v"(x));
+}
 // streaming store (non-temporal hint): the outflow faces and moment partials
 // are read back only by a later launch, so they should not displace the cell
 // tables and faces of the running launch from the caches
@@ -866,7 +872,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
     const S xiy = (S)xiy_d, xiz = (S)xiz_d;
     const S ay = (S)lt[2], az = (S)lt[3];
     const int vb = (int)lt[4], vc = (int)lt[5];
-    S xix[VL], ax[VL], asum[VL];
+    // |xi_x| / h_x is formed per cell from the node and a wave-uniform
+    // factor (the octant's sign over h_x, or the sign alone on a non-uniform
+    // mesh, whose cells bring their own inverse size): fewer live registers
+    S xix[VL];
     double wm0[VL], wm1[VL], wm2[VL], wm3[VL];
     unsigned oa[VL], oal[VL];
 #pragma unroll
@@ -875,8 +884,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
         const double w = lt[LT_SHARED + LT_PER_V * v + 2];
         const int a = (int)lt[LT_SHARED + LT_PER_V * v + 3];
         xix[v] = (S)x;
-        ax[v] = (S)lt[LT_SHARED + LT_PER_V * v + 1];
-        asum[v] = ax[v] + ay + az;
         oa[v] = (unsigned)a * SB;
         oal[v] = (unsigned)(a + A.mx * (vb + A.my * vc)) * SB;
         wm0[v] = w;
@@ -885,6 +892,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
         wm3[v] = w * x * x * x;
     }
     const unsigned ob = (unsigned)(A.mx + vb) * SB, oc = (unsigned)(A.mx + A.my + vc) * SB;
+    const S sgx = px ? (S)A.rdx : -(S)A.rdx;
     const double yz2 = xiy_d * xiy_d + xiz_d * xiz_d;
     const double xiyy = xiy_d * xiy_d, xizz = xiz_d * xiz_d, xiyz = xiy_d * xiz_d;
     const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
@@ -1066,13 +1074,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 const S Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
                 // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
                 // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
-                S ayc = ay, azc = az, idx = (S)1, aynu = (S)0;
+                S ayc = ay, azc = az, sx = sgx;
                 if constexpr (NU) {
-                    idx = P[P_IDX];
+                    sx = sgx * P[P_IDX];
                     ayc = ay * P[P_IDY];
                     azc = az * P[P_IDZ];
-                    aynu = ayc + azc + nu;
                 }
+                const S aynu = ayc + azc + nu;
                 double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
                 double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // second order: sum w (F_d - f)
                 S Fy[VL], Fz[VL];
@@ -1098,7 +1106,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                         const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
                         nfs = gyz * ldb(E, oa[v]) * poly;
                     }
-                    const S axv = NU ? ax[v] * idx : ax[v];
+                    const S axv = xix[v] * sx;
                     S f;
                     if constexpr (O2) {
                         const S axk = axv * kx;
@@ -1117,7 +1125,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                         e2 += wm0[v] * (double)dz;
                     } else {
                         const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
-                        f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
+                        f = num * fast_rcp(axv + aynu);
                     }
                     prev[v] = f;
                     lds(jj, ii, v) = f;
@@ -1288,7 +1296,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     const S xiy = (S)xiy_d, xiz = (S)xiz_d;
     const S ay = (S)lt[2], az = (S)lt[3];
     const int vb = (int)lt[4], vc = (int)lt[5];
-    S xix[VL], ax[VL], asum[VL];
+    // |xi_x| / h_x is formed per cell from the node and a wave-uniform
+    // factor (the octant's sign over h_x, or the sign alone on a non-uniform
+    // mesh, whose cells bring their own inverse size): fewer live registers
+    S xix[VL];
     double xd[VL], wd[VL];
     unsigned oa[VL], oal[VL];
 #pragma unroll
@@ -1297,12 +1308,11 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         wd[v] = lt[LT_SHARED + LT_PER_V * v + 2];
         const int a = (int)lt[LT_SHARED + LT_PER_V * v + 3];
         xix[v] = (S)xd[v];
-        ax[v] = (S)lt[LT_SHARED + LT_PER_V * v + 1];
-        asum[v] = ax[v] + ay + az;
         oa[v] = (unsigned)a * SB;
         oal[v] = (unsigned)(a + A.mx * (vb + A.my * vc)) * SB;
     }
     const unsigned ob = (unsigned)(A.mx + vb) * SB, oc = (unsigned)(A.mx + A.my + vc) * SB;
+    const S sgx = px ? (S)A.rdx : -(S)A.rdx;
     const double yz2 = xiy_d * xiy_d + xiz_d * xiz_d;
     const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
     const int shX = 4 * sideX, shY = 4 * sideY, shZ = 4 * sideZ;
@@ -1379,6 +1389,70 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 #pragma unroll
     for (int v = 0; v < VL; ++v) prev[v] = prevF[v] = (S)0;
     uint32_t ybnd = 0;  // second order: plane cells whose y upwind side is a boundary
+    // stores of the last fluid cell (pcell < 0: none pending)
+    int pcell = -1, pii = 0, pjj = 0, pkk = 0;
+    double ptot = 0.0;
+    S pFy[VL], pFz[VL];
+#pragma unroll
+    for (int v = 0; v < VL; ++v) pFy[v] = pFz[v] = (S)0;
+    // the values the last flush stored (first order: the second-order
+    // form stores at once, its registers being scarce)
+    S sd[VL];
+    double sdt = 0.0;
+#pragma unroll
+    for (int v = 0; v < VL; ++v) sd[v] = (S)0;
+    auto flush = [&]() {
+        if constexpr (!O2) {
+#pragma unroll
+            for (int v = 0; v < VL; ++v) sd[v] = prev[v];
+            sdt = ptot;
+        }
+        if (pcell < 0) return;
+        if (pii == BX - 1 && wx) {
+            S* dst = xout + ((size_t)pkk * ny + pjj) * fstride;
+#pragma unroll
+            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            if constexpr (O2) {
+                S* g = xgout + ((size_t)pkk * ny + pjj) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, prevF[v]);
+            }
+        }
+        if (pjj == BY - 1 && wy) {
+            S* dst = yout + ((size_t)pkk * nx + pii) * fstride;
+#pragma unroll
+            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            if constexpr (O2) {
+                S* g = ygout + ((size_t)pkk * nx + pii) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFy[v]);
+            }
+        }
+        if (pkk == A.bz - 1 && wz) {
+            S* dst = zout + ((size_t)pjj * nx + pii) * fstride;
+#pragma unroll
+            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            if constexpr (O2) {
+                S* g = zgout + ((size_t)pjj * nx + pii) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFz[v]);
+            }
+        }
+        if (sbuf != nullptr && !pz && kr0 + pkk == nz - 1) {
+            const int i = px ? ir0 + pii : nx - 1 - (ir0 + pii);
+            const int j = py ? jr0 + pjj : ny - 1 - (jr0 + pjj);
+            S* dst = sbuf + ((size_t)j * nx + i) * fstride;
+#pragma unroll
+            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            if constexpr (O2) {
+                S* g = sgbuf + ((size_t)j * nx + i) * fstride;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFz[v]);
+            }
+        }
+        if (writer) stb_nt(part + (size_t)pcell * PREC, oridx, ptot);
+        if constexpr (O2) pcell = -1;  // stored at once: nothing left for the next cell
+    };
     for (int n = 0; n < ncell; ++n) {
         const S eb = eb_n, ec = ec_n, nu = nu_n;
         const uint32_t info = info_n;
@@ -1400,7 +1474,19 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 ++nk;
             }
         }
-        if (n + 1 < ncell) prefetch(ni, nj, nk);
+        // the loads issued one cell ahead are in (vmcnt 0; the other
+        // counters left alone), so the stores below are never waited for
+        // along with them
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        // the data registers of the previous cell's stores stay allocated
+        // until here, where those stores are known to be done: reusing one
+        // earlier would wait for the stores and, the counter being in order,
+        // for the loads issued after them
+        if constexpr (!O2) {
+#pragma unroll
+            for (int v = 0; v < VL; ++v) keep_alive(sd[v]);
+            keep_alive(sdt);
+        }
 
         const int cell = cell0 + ii * si + jj * sj + kk * sk;
         const S* P = params + (size_t)cell * PSTRIDE;
@@ -1470,12 +1556,30 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             }
             {
                 const uint32_t code = (info >> shZ) & 15u;
+                // the interior inflow is read from LDS whatever the cell's
+                // side: a boundary alternative then loads after it, never
+                // before it on a path the compiler has to assume (a load
+                // ahead of the LDS read into the same registers makes it
+                // wait for every load in flight, those issued one cell
+                // ahead included)
+                S zl[VL], zg[VL];
+#pragma unroll
+                for (int v = 0; v < VL; ++v) {
+                    zl[v] = lds(jj, ii, v);
+                    zg[v] = O2 ? S(ldz(jj, ii, v)) : (S)0;
+                }
+                // pinned here: not moved below the loads of the branches
+#pragma unroll
+                for (int v = 0; v < VL; ++v) {
+                    keep_alive(zl[v]);
+                    if constexpr (O2) keep_alive(zg[v]);
+                }
                 if (O2 && code == 0) {
                     izf = true;
 #pragma unroll
                     for (int v = 0; v < VL; ++v) {
-                        uz[v] = lds(jj, ii, v);
-                        fz[v] = ldz(jj, ii, v) + (S)0.5 * uz[v];
+                        uz[v] = zl[v];
+                        fz[v] = zg[v] + (S)0.5 * uz[v];
                     }
                 } else if (O2 && code == CODE_SPECULAR) {
                     // the mirror image beyond the symmetry plane
@@ -1491,7 +1595,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                     }
                 } else if (code == 0) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fz[v] = lds(jj, ii, v);
+                    for (int v = 0; v < VL; ++v) fz[v] = zl[v];
                 } else if (code == CODE_SPECULAR) {
                     const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
                     const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
@@ -1506,6 +1610,13 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 }
             }
 
+            // the previous cell's stores and the next cell's loads go out
+            // once the inflow is resolved (its boundary loads waited for
+            // here): no wait below then covers them
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            flush();
+            if (n + 1 < ncell) prefetch(ni, nj, nk);
+
             const S Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
             const S L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
             const S qx = P[P_QX], qy = P[P_QY], qz = P[P_QZ], tT = P[P_TWO_T];
@@ -1518,13 +1629,13 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             const S Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
             // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
             // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
-            S ayc = ay, azc = az, idx = (S)1, aynu = (S)0;
+            S ayc = ay, azc = az, sx = sgx;
             if constexpr (NU) {
-                idx = P[P_IDX];
+                sx = sgx * P[P_IDX];
                 ayc = ay * P[P_IDY];
                 azc = az * P[P_IDZ];
-                aynu = ayc + azc + nu;
             }
+            const S aynu = ayc + azc + nu;
             double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
             double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // second order: sum w (F_d - f)
             S Fy[VL], Fz[VL];
@@ -1548,7 +1659,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                     const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
                     nfs = gyz * ex[v] * poly;
                 }
-                const S axv = NU ? ax[v] * idx : ax[v];
+                const S axv = xix[v] * sx;
                 const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
                 S f;
                 if constexpr (O2) {
@@ -1564,7 +1675,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                     e1 += wd[v] * (double)dy;
                     e2 += wd[v] * (double)dz;
                 } else {
-                    f = num * fast_rcp(NU ? axv + aynu : asum[v] + nu);
+                    f = num * fast_rcp(axv + aynu);
                 }
                 prev[v] = f;
                 lds(jj, ii, v) = f;
@@ -1575,49 +1686,6 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 u1 += t1;
                 u2 += t2;
                 u3 += t2 * xd[v];
-            }
-
-            if (ii == BX - 1 && wx) {
-                S* dst = xout + ((size_t)kk * ny + jj) * fstride;
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
-                if constexpr (O2) {
-                    S* g = xgout + ((size_t)kk * ny + jj) * fstride;
-#pragma unroll
-                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, prevF[v]);
-                }
-            }
-            if (jj == BY - 1 && wy) {
-                S* dst = yout + ((size_t)kk * nx + ii) * fstride;
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
-                if constexpr (O2) {
-                    S* g = ygout + ((size_t)kk * nx + ii) * fstride;
-#pragma unroll
-                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, Fy[v]);
-                }
-            }
-            if (kk == A.bz - 1 && wz) {
-                S* dst = zout + ((size_t)jj * nx + ii) * fstride;
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
-                if constexpr (O2) {
-                    S* g = zgout + ((size_t)jj * nx + ii) * fstride;
-#pragma unroll
-                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, Fz[v]);
-                }
-            }
-            if (sbuf != nullptr && !pz && kr0 + kk == nz - 1) {
-                const int i = px ? ir0 + ii : nx - 1 - (ir0 + ii);
-                const int j = py ? jr0 + jj : ny - 1 - (jr0 + jj);
-                S* dst = sbuf + ((size_t)j * nx + i) * fstride;
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
-                if constexpr (O2) {
-                    S* g = sgbuf + ((size_t)j * nx + i) * fstride;
-#pragma unroll
-                    for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, Fz[v]);
-                }
             }
 
             double m[O2 ? 16 : 13];
@@ -1644,17 +1712,39 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             } else {
                 tot = wave_reduce13(m);
             }
-            if (writer) stb_nt(part + (size_t)cell * PREC, oridx, tot);
+            // the cell's stores go out at the top of the next cell, after
+            // the wait for the loads issued one cell ahead and before the
+            // next ones: a store between a load and its wait would be waited
+            // for as well (one in-order counter covers loads and stores)
+            pcell = cell;
+            pii = ii;
+            pjj = jj;
+            pkk = kk;
+            ptot = tot;
+            if constexpr (O2) {
+#pragma unroll
+                for (int v = 0; v < VL; ++v) {
+                    pFy[v] = Fy[v];
+                    pFz[v] = Fz[v];
+                }
+                flush();
+            }
+        } else {
+            flush();
+            if (n + 1 < ncell) prefetch(ni, nj, nk);
+            pcell = -1;
         }
         ii = ni;
         jj = nj;
         kk = nk;
     }
+    flush();
 }
 
 // NU: non-uniform mesh (the upwind coefficients take the cell's own sizes)
 template <typename S, int VL, int BX, int BY, bool NU>
-__global__ __launch_bounds__(64) void sweep_kernel_pf(const SweepArgs<S> A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VL == 4 ? (sizeof(S) == 4 ? 4 : 3) : 1)))
+void sweep_kernel_pf(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
     sweep_body_pf<S, VL, BX, BY, NU>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,

@@ -481,6 +481,7 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.partial = c->P<double>(c->off.partial);
                 a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.N = c->N;
                 a.mx = c->vg.m[0]; a.my = c->vg.m[1]; a.MT = C.MT; a.NV = c->NV;
+                a.rdx = c->nonuniform ? 1.0 : 1.0 / c->dx[0];
                 a.nbx = c->nbx; a.nby = c->nby; a.nbz = c->nbz; a.bz = c->BZ;
                 a.ntiles = gnt; a.slots = gnt * 64; a.lstride = c->lstride;
                 a.brick_off = c->diag_off[T]; a.brick_cnt = cnt;
