@@ -1475,8 +1475,8 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             }
         }
         // the loads issued one cell ahead are in (vmcnt 0; the other
-        // counters left alone), so the stores below are never waited for
-        // along with them
+        // counters left alone): nothing issued before this point is waited
+        // for later in the cell
         __builtin_amdgcn_s_waitcnt(0x0F70);
         // the data registers of the previous cell's stores stay allocated
         // until here, where those stores are known to be done: reusing one
@@ -1569,10 +1569,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                     zg[v] = O2 ? S(ldz(jj, ii, v)) : (S)0;
                 }
                 // pinned here: not moved below the loads of the branches
+                // (first order; the second-order form has no registers to spare)
+                if constexpr (!O2) {
 #pragma unroll
-                for (int v = 0; v < VL; ++v) {
-                    keep_alive(zl[v]);
-                    if constexpr (O2) keep_alive(zg[v]);
+                    for (int v = 0; v < VL; ++v) keep_alive(zl[v]);
                 }
                 if (O2 && code == 0) {
                     izf = true;
@@ -1741,7 +1741,9 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     flush();
 }
 
-// NU: non-uniform mesh (the upwind coefficients take the cell's own sizes)
+// NU: non-uniform mesh (the upwind coefficients take the cell's own sizes).
+// Occupancy with 4 per lane: 4 waves per SIMD (128 registers) in FP32, 3
+// (168) in FP64, reached without spills inside the cell loop.
 template <typename S, int VL, int BX, int BY, bool NU>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VL == 4 ? (sizeof(S) == 4 ? 4 : 3) : 1)))
 void sweep_kernel_pf(const SweepArgs<S> A)
@@ -1760,8 +1762,11 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 }
 
 // second-order upwind and/or ES-BGK (uniform meshes), pipelined body
+// (occupancy: FP32 ES-BGK with 4 per lane fits 4 waves per SIMD without
+// spills in the loop; the FP64 and second-order forms would spill there)
 template <typename S, int VL, int BX, int BY, bool O2, bool ES>
-__global__ __launch_bounds__(64) void sweep_kernel_pfx(const SweepArgs<S> A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VL == 4 && !O2 && sizeof(S) == 4 ? 4 : 1)))
+void sweep_kernel_pfx(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
     sweep_body_pf<S, VL, BX, BY, false, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface,
@@ -1785,7 +1790,7 @@ __global__ __launch_bounds__(64) void sweep_kernel_x(const SweepArgs<S> A)
     X(float, 4, 2, 2) X(float, 8, 4, 2) X(float, 8, 2, 2)
 // the shapes the defaults choose, also built for non-uniform meshes
 #define DVM_SWEEP_VARIANTS_NU(X) \
-    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) \
+    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 // and for the second-order and ES-BGK sweeps
 #define DVM_SWEEP_VARIANTS_O2(X) \

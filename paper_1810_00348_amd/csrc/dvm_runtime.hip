@@ -140,9 +140,9 @@ void derive_schedule(dvm_ctx* c)
     // VL: 4 velocities per lane, halved while more than 1/8 of the lanes'
     // velocity slots of the larger x half would be empty.  Brick and body by
     // measurement (cavity 64^3 x 32^3 FP64, 96^3 x 28^3 and cube FP32):
-    // FP64 with 4 per lane: 2x2 bricks (the LDS plane of 4 FP64 values per
-    // lane and cell limits occupancy) and the software-pipelined body; FP64
-    // with 2: 4x2 bricks, plain body; FP32: 4x2 bricks, pipelined body.
+    // 4x2 bricks and the software-pipelined body, except FP64 with 2 per
+    // lane (plain body) and the second-order and ES-BGK FP64 forms with 4
+    // per lane (2x2 bricks: their registers and LDS planes allow no more).
     const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
     const bool f64 = c->prec == DVM_F64;
     int vl = 4;
@@ -151,24 +151,25 @@ void derive_schedule(dvm_ctx* c)
     if (f64 && nax % 4) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
     vl = env_int("DVM_VL", vl);
-    int bx = (f64 && vl == 4) ? 2 : 4;
+    const int o2 = c->order == 2, es = c->model == 1;
+    int bx = (f64 && vl == 4 && (o2 || es)) ? 2 : 4;
     int by = vl == 1 ? 4 : 2;
     int pf = (!f64 || vl == 4) ? 1 : 0;
     bx = env_int("DVM_BX", bx);
     by = env_int("DVM_BY", by);
-    const int o2 = c->order == 2, es = c->model == 1;
     if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) {
         // the shape is not built (for this mesh kind): the defaults' shape for VL
-        bx = (f64 && vl == 4) ? 2 : 4;
+        bx = (f64 && vl == 4 && (o2 || es)) ? 2 : 4;
         by = vl == 1 ? 4 : 2;
         if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) { vl = 1; bx = 4; by = 4; }
     }
     c->VL = vl;
     c->BX = bx;
     c->BY = by;
-    // cells per brick column: 12 for the 2x2 FP64 bricks (measured on the
-    // cavity 64^3 x 32^3: +2.8 % over 8, 16 is slower), 8 otherwise
-    c->BZ = env_int("DVM_BZ", (f64 && vl == 4 && bx == 2 && by == 2) ? 12 : 8);
+    // cells per brick column: 12 for FP64 with 4 per lane (cavity 64^3 x
+    // 32^3, 4x2 bricks: 265 GPt/s against 262 at 8 and 256 at 16), 8
+    // otherwise (FP32: 12 is 1-2 % slower on 96^3 x 28^3 and the cube)
+    c->BZ = env_int("DVM_BZ", (f64 && vl == 4) ? 12 : 8);
     c->PF = env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;

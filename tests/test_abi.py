@@ -125,8 +125,8 @@ def test_spacing_arguments(L):
     assert lib.dvm_set_spacing(h, good.ctypes.data_as(P), hy.ctypes.data_as(P), None) == 0
     inf = L.Info()
     assert lib.dvm_get_info(h, C.byref(inf)) == 0
-    # FP64 with 8 nodes per x half: 4 per lane, 2x2 bricks, pipelined body
-    assert (inf.vel_per_lane, inf.brick[0], inf.brick[1], inf.pipelined) == (4, 2, 2, 1)
+    # FP64 with 8 nodes per x half: 4 per lane, 4x2 bricks, pipelined body
+    assert (inf.vel_per_lane, inf.brick[0], inf.brick[1], inf.pipelined) == (4, 4, 2, 1)
     n = C.c_size_t()
     assert lib.dvm_required_workspace(h, C.byref(n)) == 0
     assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 16) == -3
@@ -180,6 +180,7 @@ def test_order_arguments(L):
     assert lib.dvm_set_order(h, 2) == 0
     info = L.Info()
     assert lib.dvm_get_info(h, C.byref(info)) == 0
+    # the second-order FP64 form with 4 per lane runs 2x2 bricks
     assert info.pipelined == 1 and (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 2, 2)
     n2 = C.c_size_t()
     assert lib.dvm_required_workspace(h, C.byref(n2)) == 0
