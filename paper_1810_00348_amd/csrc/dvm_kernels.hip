@@ -1794,7 +1794,7 @@ __global__ __launch_bounds__(64) void sweep_kernel_x(const SweepArgs<S> A)
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 // and for the second-order and ES-BGK sweeps
 #define DVM_SWEEP_VARIANTS_O2(X) \
-    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) \
+    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) X(double, 4, 4, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 
 bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2, int esbgk)

@@ -349,7 +349,7 @@ def test_second_order_matches_oracle(oracle_mod, name):
 
 
 @pytest.mark.parametrize("pf", [0, 1])
-@pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2)])
+@pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2), (4, 4, 2)])
 @pytest.mark.parametrize("name", ["ragged", "cube_half", "es_cube_half"])
 def test_second_order_sweep_variants(oracle_mod, monkeypatch, name, vl, bx, by, pf):
     """Plain and pipelined bodies of the second-order sweep (and of the
@@ -446,7 +446,7 @@ def _es_cases():
     a = cases.cavity((13, 10, 19), 8, kn=0.3, lid=0.4, vmax=4.5)      # ragged bricks
     b = cases.cavity((9, 11, 7), 9, kn=2.0, lid=0.2, vmax=5.0)         # odd M
     c = cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=10, vmax=7.0, mach=2.0, kn=0.5)  # mirror, body
-    e = cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2)                  # 4 per lane, 2x2 bricks (FP64)
+    e = cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2)                  # 4 per lane, 4x2 bricks (FP64)
     out = {k: dataclasses.replace(v, model="esbgk") for k, v in
            {"ragged": a, "oddM": b, "cube_half": c, "cavity_m16": e}.items()}
     out["order2"] = dataclasses.replace(out["ragged"], order=2)
@@ -575,7 +575,7 @@ def test_two_nodes_per_axis_with_correction_is_rejected(oracle_mod):
 
 
 @pytest.mark.parametrize("pf", [0, 1])
-@pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2)])
+@pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2), (4, 4, 2)])
 def test_esbgk_sweep_variants(oracle_mod, monkeypatch, vl, bx, by, pf):
     monkeypatch.setenv("DVM_VL", str(vl))
     monkeypatch.setenv("DVM_BX", str(bx))
