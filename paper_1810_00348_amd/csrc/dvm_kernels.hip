@@ -1785,12 +1785,12 @@ __global__ __launch_bounds__(64) void sweep_kernel_x(const SweepArgs<S> A)
 // instantiated variants: (precision, VL, BX, BY)
 #define DVM_SWEEP_VARIANTS(X) \
     X(double, 1, 4, 4) X(double, 2, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) X(double, 4, 4, 4) \
-    X(double, 2, 2, 2) X(double, 4, 2, 2) \
+    X(double, 2, 2, 2) X(double, 4, 2, 2) X(double, 4, 3, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2) X(float, 4, 4, 4) \
     X(float, 4, 2, 2) X(float, 8, 4, 2) X(float, 8, 2, 2)
 // the shapes the defaults choose, also built for non-uniform meshes
 #define DVM_SWEEP_VARIANTS_NU(X) \
-    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) \
+    X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) X(double, 4, 3, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 // and for the second-order and ES-BGK sweeps
 #define DVM_SWEEP_VARIANTS_O2(X) \

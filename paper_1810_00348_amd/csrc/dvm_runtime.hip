@@ -140,11 +140,13 @@ void derive_schedule(dvm_ctx* c)
     // VL: 4 velocities per lane, halved while more than 1/8 of the lanes'
     // velocity slots of the larger x half would be empty.  Brick and body by
     // measurement (cavity 64^3 x 32^3 FP64, 96^3 x 28^3 and cube FP32):
-    // 4x2 bricks and the software-pipelined body, except the second-order
-    // FP64 form with 4 per lane (2x2 bricks: its registers and two LDS planes
-    // allow no more; 132 GPt/s against 116 at 4x2 on 64^3 x 32^3) and 1 per
-    // lane (plain body, 4x4).  FP64 with 2 per lane (96^3 x 28^3): pipelined
-    // 234 GPt/s, plain 214; ES-BGK FP64, 64^3 x 32^3: 195 at 4x2, 187 at 2x2.
+    // 4x2 bricks and the software-pipelined body, except FP64 with 4 per
+    // lane: 3x2 bricks (64^3 x 32^3: 277 GPt/s against 267 at 4x2 -- the
+    // 12 KB LDS plane lets 3 waves per SIMD stay resident where 4x2's 16 KB
+    // allows 2.5), 4x2 for ES-BGK (its registers allow 2 waves anyway: 195
+    // against 187 at 2x2) and 2x2 for the second-order form (registers and
+    // two LDS planes: 132 against 116 at 4x2); 1 per lane: plain body, 4x4.
+    // FP64 with 2 per lane (96^3 x 28^3): pipelined 234 GPt/s, plain 214.
     const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
     const bool f64 = c->prec == DVM_F64;
     int vl = 4;
@@ -154,14 +156,15 @@ void derive_schedule(dvm_ctx* c)
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
     vl = env_int("DVM_VL", vl);
     const int o2 = c->order == 2, es = c->model == 1;
-    int bx = (f64 && vl == 4 && o2) ? 2 : 4;
+    auto default_bx = [&](int v) { return (f64 && v == 4) ? (o2 ? 2 : es ? 4 : 3) : 4; };
+    int bx = default_bx(vl);
     int by = vl == 1 ? 4 : 2;
     int pf = vl >= 2 ? 1 : 0;
     bx = env_int("DVM_BX", bx);
     by = env_int("DVM_BY", by);
     if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) {
         // the shape is not built (for this mesh kind): the defaults' shape for VL
-        bx = (f64 && vl == 4 && o2) ? 2 : 4;
+        bx = default_bx(vl);
         by = vl == 1 ? 4 : 2;
         if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) { vl = 1; bx = 4; by = 4; }
     }
