@@ -765,6 +765,14 @@ __device__ __forceinline__ void stb(T* base, unsigned off, T v)
 {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
+// wait until no vector-memory load or store of this wave is outstanding,
+// leaving the other counters alone: s_waitcnt with vmcnt 0 (bits 3:0 and
+// 15:14), expcnt 7 (bits 6:4) and lgkmcnt 15 (bits 11:8), i.e. no wait on
+// those two (gfx9 encoding)
+__device__ __forceinline__ void wait_vector_memory()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+}
 // an empty statement that reads x: x stays in its register up to here
 template <typename T>
 __device__ __forceinline__ void keep_alive(T x)
@@ -1401,12 +1409,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     double sdt = 0.0;
 #pragma unroll
     for (int v = 0; v < VL; ++v) sd[v] = (S)0;
-    auto flush = [&]() {
-        if constexpr (!O2) {
-#pragma unroll
-            for (int v = 0; v < VL; ++v) sd[v] = prev[v];
-            sdt = ptot;
-        }
+    auto flush_faces = [&]() {
         if (pcell < 0) return;
         if (pii == BX - 1 && wx) {
             S* dst = xout + ((size_t)pkk * ny + pjj) * fstride;
@@ -1450,8 +1453,18 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFz[v]);
             }
         }
-        if (writer) stb_nt(part + (size_t)pcell * PREC, oridx, ptot);
-        if constexpr (O2) pcell = -1;  // stored at once: nothing left for the next cell
+    };
+    auto flush_partial = [&]() {
+        if (pcell >= 0 && writer) stb_nt(part + (size_t)pcell * PREC, oridx, ptot);
+    };
+    auto flush = [&]() {
+        if constexpr (!O2) {
+#pragma unroll
+            for (int v = 0; v < VL; ++v) sd[v] = prev[v];
+            sdt = ptot;
+        }
+        flush_faces();
+        flush_partial();
     };
     for (int n = 0; n < ncell; ++n) {
         const S eb = eb_n, ec = ec_n, nu = nu_n;
@@ -1477,7 +1490,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         // the loads issued one cell ahead are in (vmcnt 0; the other
         // counters left alone): nothing issued before this point is waited
         // for later in the cell
-        __builtin_amdgcn_s_waitcnt(0x0F70);
+        wait_vector_memory();
         // the data registers of the previous cell's stores stay allocated
         // until here, where those stores are known to be done: reusing one
         // earlier would wait for the stores and, the counter being in order,
@@ -1610,12 +1623,14 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 }
             }
 
-            // the previous cell's stores and the next cell's loads go out
-            // once the inflow is resolved (its boundary loads waited for
-            // here): no wait below then covers them
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-            flush();
-            if (n + 1 < ncell) prefetch(ni, nj, nk);
+            // first order: the previous cell's stores and the next cell's
+            // loads go out once the inflow is resolved (its boundary loads
+            // waited for here): no wait below then covers them
+            if constexpr (!O2) {
+                wait_vector_memory();
+                flush();
+                if (n + 1 < ncell) prefetch(ni, nj, nk);
+            }
 
             const S Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
             const S L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
@@ -1687,6 +1702,24 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 u2 += t2;
                 u3 += t2 * xd[v];
             }
+            if constexpr (O2) {
+                // second order: the previous cell's moment record and this
+                // cell's faces go out now, the next cell's loads after them
+                // (the wait at the top of the next cell then finds all of
+                // them issued a reduction earlier)
+                flush_partial();
+                pcell = cell;
+                pii = ii;
+                pjj = jj;
+                pkk = kk;
+#pragma unroll
+                for (int v = 0; v < VL; ++v) {
+                    pFy[v] = Fy[v];
+                    pFz[v] = Fz[v];
+                }
+                flush_faces();
+                if (n + 1 < ncell) prefetch(ni, nj, nk);
+            }
 
             double m[O2 ? 16 : 13];
             m[0] = u0;
@@ -1712,7 +1745,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             } else {
                 tot = wave_reduce13(m);
             }
-            // the cell's stores go out at the top of the next cell, after
+            // first order: the cell's stores go out in the next cell, after
             // the wait for the loads issued one cell ahead and before the
             // next ones: a store between a load and its wait would be waited
             // for as well (one in-order counter covers loads and stores)
@@ -1721,16 +1754,11 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             pjj = jj;
             pkk = kk;
             ptot = tot;
-            if constexpr (O2) {
-#pragma unroll
-                for (int v = 0; v < VL; ++v) {
-                    pFy[v] = Fy[v];
-                    pFz[v] = Fz[v];
-                }
-                flush();
-            }
         } else {
-            flush();
+            if constexpr (O2)
+                flush_partial();  // its faces are out
+            else
+                flush();
             if (n + 1 < ncell) prefetch(ni, nj, nk);
             pcell = -1;
         }
@@ -1738,7 +1766,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         jj = nj;
         kk = nk;
     }
-    flush();
+    if constexpr (O2)
+        flush_partial();  // its faces are out
+    else
+        flush();
 }
 
 // NU: non-uniform mesh (the upwind coefficients take the cell's own sizes).
