@@ -243,3 +243,31 @@ def test_model_arguments(L):
     assert lib.dvm_create(C.byref(g), C.byref(vg), C.byref(gas), 0, None, C.byref(h)) == 0
     assert lib.dvm_set_model(h, 1) == -1 and b"Pr" in lib.dvm_last_error()
     lib.dvm_destroy(h)
+
+
+@pytest.mark.parametrize("name,prec,order,model,expect", [
+    # (VL, BX, BY, BZ, pipelined) chosen by the library for the benchmark workloads
+    ("c2", 0, 1, 0, (4, 3, 2, 12, 1)),    # FP64, 16 nodes per x half
+    ("c2", 0, 1, 1, (4, 4, 2, 12, 1)),    # ES-BGK FP64
+    ("c2", 0, 2, 0, (4, 2, 2, 12, 1)),    # second order FP64
+    ("c3", 1, 1, 0, (4, 4, 2, 8, 1)),     # FP32, 14 nodes per half (empty slots)
+    ("c3", 0, 1, 0, (2, 4, 2, 8, 1)),     # FP64, 14 nodes per half -> 2 per lane
+    ("c4", 1, 1, 0, (4, 4, 2, 8, 1)),     # FP32, 24 nodes per half
+    ("c1", 0, 1, 0, (2, 4, 2, 8, 1)),     # FP64, 6 nodes per half
+])
+def test_default_schedule_of_the_benchmark_workloads(L, name, prec, order, model, expect):
+    """The sweep shape the library picks for each workload (host-only: no
+    device work happens before a workspace is bound)."""
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    case = cases.config(name)
+    h = _ctx(L, case, prec)
+    if order == 2:
+        assert lib.dvm_set_order(h, 2) == 0
+    if model == 1:
+        assert lib.dvm_set_model(h, 1) == 0
+    info = L.Info()
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    got = (info.vel_per_lane, info.brick[0], info.brick[1], info.brick[2], info.pipelined)
+    assert got == expect, (name, prec, order, model, got)
+    lib.dvm_destroy(h)
