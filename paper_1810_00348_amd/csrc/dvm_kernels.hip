@@ -1264,6 +1264,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     constexpr unsigned SB = sizeof(S);
     const size_t fstride = (size_t)A.slots * VL;
     const unsigned lofs = (unsigned)slot * VL * SB;
+    // a face cell of this brick, as a 32-bit byte offset from the brick's face
+    // base (c < BZ * max(nx, ny) + BY: the host keeps c * rowb below 2^32)
+    const unsigned rowb = (unsigned)(fstride * SB);
+    auto fcell = [rowb](auto* base, int c) { return (decltype(base))((const char*)base + (unsigned)c * rowb); };
 
     const int iend = min(BX, nx - I * BX), jend = min(BY, ny - J * BY);
     const int kend = min(A.bz, nz - K * A.bz);
@@ -1367,23 +1371,23 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 #pragma unroll
         for (int v = 0; v < VL; ++v) ex_n[v] = ldb(E, oa[v]);
         if (ii == 0 && ir0 > 0) {
-            const S* src = xin + ((size_t)kk * ny + jj) * fstride;
+            const S* src = fcell(xin, kk * ny + jj);
 #pragma unroll
             for (int v = 0; v < VL; ++v) fx_n[v] = ldb(src, lofs + v * SB);
             if constexpr (O2) {
-                const S* gsrc = xgin + ((size_t)kk * ny + jj) * fstride;
+                const S* gsrc = fcell(xgin, kk * ny + jj);
 #pragma unroll
                 for (int v = 0; v < VL; ++v) gx_n[v] = ldb(gsrc, lofs + v * SB);
             }
         }
         if ((jj == 0 || (O2 && jj == 1)) && jr0 > 0) {
-            const S* src = yin + ((size_t)kk * nx + ii) * fstride;
+            const S* src = fcell(yin, kk * nx + ii);
 #pragma unroll
             for (int v = 0; v < VL; ++v) fy_n[v] = ldb(src, lofs + v * SB);
         }
         if constexpr (O2) {
             if (jj == 0 && jr0 > 0) {
-                const S* gsrc = ygin + ((size_t)kk * nx + ii) * fstride;
+                const S* gsrc = fcell(ygin, kk * nx + ii);
 #pragma unroll
                 for (int v = 0; v < VL; ++v) gy_n[v] = ldb(gsrc, lofs + v * SB);
             }
@@ -1397,14 +1401,15 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 #pragma unroll
     for (int v = 0; v < VL; ++v) prev[v] = prevF[v] = (S)0;
     uint32_t ybnd = 0;  // second order: plane cells whose y upwind side is a boundary
-    // stores of the last fluid cell (pcell < 0: none pending)
+    // the last fluid cell whose stores are pending (pcell < 0: none; in the
+    // second-order form only its moment record, its faces being out)
     int pcell = -1, pii = 0, pjj = 0, pkk = 0;
     double ptot = 0.0;
     S pFy[VL], pFz[VL];
 #pragma unroll
     for (int v = 0; v < VL; ++v) pFy[v] = pFz[v] = (S)0;
-    // the values the last flush stored (first order: the second-order
-    // form stores at once, its registers being scarce)
+    // first order: the values the last flush stored, kept allocated until
+    // the next cell's wait (the second-order form has no registers for it)
     S sd[VL];
     double sdt = 0.0;
 #pragma unroll
@@ -1412,31 +1417,31 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     auto flush_faces = [&]() {
         if (pcell < 0) return;
         if (pii == BX - 1 && wx) {
-            S* dst = xout + ((size_t)pkk * ny + pjj) * fstride;
+            S* dst = fcell(xout, pkk * ny + pjj);
 #pragma unroll
             for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
             if constexpr (O2) {
-                S* g = xgout + ((size_t)pkk * ny + pjj) * fstride;
+                S* g = fcell(xgout, pkk * ny + pjj);
 #pragma unroll
                 for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, prevF[v]);
             }
         }
         if (pjj == BY - 1 && wy) {
-            S* dst = yout + ((size_t)pkk * nx + pii) * fstride;
+            S* dst = fcell(yout, pkk * nx + pii);
 #pragma unroll
             for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
             if constexpr (O2) {
-                S* g = ygout + ((size_t)pkk * nx + pii) * fstride;
+                S* g = fcell(ygout, pkk * nx + pii);
 #pragma unroll
                 for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFy[v]);
             }
         }
         if (pkk == A.bz - 1 && wz) {
-            S* dst = zout + ((size_t)pjj * nx + pii) * fstride;
+            S* dst = fcell(zout, pjj * nx + pii);
 #pragma unroll
             for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
             if constexpr (O2) {
-                S* g = zgout + ((size_t)pjj * nx + pii) * fstride;
+                S* g = fcell(zgout, pjj * nx + pii);
 #pragma unroll
                 for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFz[v]);
             }

@@ -172,8 +172,9 @@ void derive_schedule(dvm_ctx* c)
     c->BX = bx;
     c->BY = by;
     // cells per brick column: 12 for FP64 with 4 per lane (cavity 64^3 x
-    // 32^3, 4x2 bricks: 265 GPt/s against 262 at 8 and 256 at 16), 8
-    // otherwise (FP32: 12 is 1-2 % slower on 96^3 x 28^3 and the cube)
+    // 32^3: 3x2 bricks 277 GPt/s against 268 at 8 and 270 at 16; 4x2 265
+    // against 262 at 8 and 256 at 16), 8 otherwise (FP32: 12 is 1-2 %
+    // slower on 96^3 x 28^3 and the cube)
     c->BZ = env_int("DVM_BZ", (f64 && vl == 4) ? 12 : 8);
     c->PF = env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
@@ -200,6 +201,20 @@ void derive_schedule(dvm_ctx* c)
     for (int g = 0; g < c->ngroups; ++g) c->gtiles = std::max(c->gtiles, c->gt0[g + 1] - c->gt0[g]);
     c->lstride = LT_SHARED + LT_PER_V * c->VL;
     if (c->lstride & 1) c->lstride++;
+    // the sweep addresses a face cell of its brick by a 32-bit byte offset
+    // from the brick's face base: keep (BZ - 1) * max(nx, ny) + max(BX, BY)
+    // face cells of one group's velocities below 2^32 bytes (shorter brick
+    // columns if needed; a grid that breaches this even with BZ = 1 has
+    // face buffers far beyond any device memory)
+    {
+        const size_t rowb = (size_t)c->gtiles * 64 * c->VL * (c->prec == DVM_F64 ? 8 : 4);
+        const size_t span = (size_t)std::max(c->g.nx, c->g.ny);
+        auto fits = [&](int bz) {
+            return ((size_t)(bz - 1) * span + (size_t)std::max(c->BX, c->BY)) * rowb < ((size_t)1 << 32);
+        };
+        while (c->BZ > 1 && !fits(c->BZ)) c->BZ = std::max(1, c->BZ / 2);
+        c->nbz = (c->g.nz + c->BZ - 1) / c->BZ;
+    }
 
     // bricks grouped by diagonal I + J + K
     c->ndiag = c->nbx + c->nby + c->nbz - 2;
