@@ -271,3 +271,27 @@ def test_default_schedule_of_the_benchmark_workloads(L, name, prec, order, model
     got = (info.vel_per_lane, info.brick[0], info.brick[1], info.brick[2], info.pipelined)
     assert got == expect, (name, prec, order, model, got)
     lib.dvm_destroy(h)
+
+
+def test_brick_columns_shortened_for_32bit_face_offsets(L):
+    """The sweep addresses a face cell of its brick by a 32-bit byte offset:
+    on a wide grid with many velocities the library shortens the brick
+    columns so that (BZ - 1) * max(nx, ny) + max(BX, BY) face cells stay
+    below 4 GiB (host-only: no device work)."""
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    # 2000 x 2000 x 2 cells, 64^3 velocities, FP64: an octant has 32^3
+    # velocities = 8192 lanes of 4 = 128 tiles, so one face cell holds
+    # 128 x 64 x 4 x 8 bytes = 256 KiB and 4 GiB holds 16384 of them:
+    # (BZ - 1) * 2000 + 3 < 16384 -> BZ <= 9; halving from 12 gives 6
+    case = cases.cavity((2000, 2000, 2), 64, kn=1.0)
+    h = _ctx(L, case, 0)
+    info = L.Info()
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 3, 2)
+    assert info.brick[2] == 6, tuple(info.brick)
+    lib.dvm_destroy(h)
+    # the benchmark grid keeps its 12-cell columns
+    h = _ctx(L, cases.config("c2"), 0)
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.brick[2] == 12
+    lib.dvm_destroy(h)
