@@ -144,18 +144,20 @@ void derive_schedule(dvm_ctx* c)
     // lane: 3x2 bricks (64^3 x 32^3: 277 GPt/s against 267 at 4x2 -- the
     // 12 KB LDS plane lets 3 waves per SIMD stay resident where 4x2's 16 KB
     // allows 2.5), 4x2 for ES-BGK (its registers allow 2 waves anyway: 195
-    // against 187 at 2x2) and 2x2 for the second-order form (registers and
-    // two LDS planes: 132 against 116 at 4x2); 1 per lane: plain body, 4x4.
+    // against 187 at 2x2); the second-order FP64 form takes 2 per lane and
+    // 4x2x12 bricks (141 GPt/s against 131 with 4 per lane at 2x2, the most
+    // its registers and two LDS planes allow); 1 per lane: plain body, 4x4.
     // FP64 with 2 per lane (96^3 x 28^3): pipelined 234 GPt/s, plain 214.
     const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
     const bool f64 = c->prec == DVM_F64;
+    const int o2 = c->order == 2, es = c->model == 1;
     int vl = 4;
     // FP64 takes 4 per lane only without empty slots (measured: 96^3 x 28^3,
-    // 14 nodes per half, is faster with 2 per lane and 4x2 bricks)
-    if (f64 && nax % 4) vl = 2;
+    // 14 nodes per half, is faster with 2 per lane and 4x2 bricks) and in
+    // the first-order forms
+    if (f64 && (nax % 4 || o2)) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
     vl = env_int("DVM_VL", vl);
-    const int o2 = c->order == 2, es = c->model == 1;
     auto default_bx = [&](int v) { return (f64 && v == 4) ? (o2 ? 2 : es ? 4 : 3) : 4; };
     int bx = default_bx(vl);
     int by = vl == 1 ? 4 : 2;
@@ -171,11 +173,12 @@ void derive_schedule(dvm_ctx* c)
     c->VL = vl;
     c->BX = bx;
     c->BY = by;
-    // cells per brick column: 12 for FP64 with 4 per lane (cavity 64^3 x
+    // cells per brick column: 12 for FP64 with 4 per lane and for the
+    // second-order FP64 form (141 GPt/s against 137 at 8), (cavity 64^3 x
     // 32^3: 3x2 bricks 277 GPt/s against 268 at 8 and 270 at 16; 4x2 265
     // against 262 at 8 and 256 at 16), 8 otherwise (FP32: 12 is 1-2 %
     // slower on 96^3 x 28^3 and the cube)
-    c->BZ = env_int("DVM_BZ", (f64 && vl == 4) ? 12 : 8);
+    c->BZ = env_int("DVM_BZ", (f64 && (vl == 4 || o2)) ? 12 : 8);
     c->PF = env_int("DVM_PF", pf) != 0;
     if (c->BZ < 1) c->BZ = 1;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;

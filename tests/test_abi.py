@@ -167,8 +167,8 @@ def test_velocity_groups_arguments_and_workspace(L):
 
 def test_order_arguments(L):
     """dvm_set_order: 1 or 2, uniform meshes only, before binding; the
-    second order keeps the schedule (pipelined body at 4 per lane) and
-    doubles the face buffers."""
+    second order re-derives the schedule (FP64: 2 per lane, pipelined body)
+    and doubles the face buffers."""
     import numpy as np
     from paper_1810_00348_amd import cases
     lib = L.lib()
@@ -180,8 +180,8 @@ def test_order_arguments(L):
     assert lib.dvm_set_order(h, 2) == 0
     info = L.Info()
     assert lib.dvm_get_info(h, C.byref(info)) == 0
-    # the second-order FP64 form with 4 per lane runs 2x2 bricks
-    assert info.pipelined == 1 and (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 2, 2)
+    # the second-order FP64 form runs 2 per lane on 4x2 bricks
+    assert info.pipelined == 1 and (info.vel_per_lane, info.brick[0], info.brick[1]) == (2, 4, 2)
     n2 = C.c_size_t()
     assert lib.dvm_required_workspace(h, C.byref(n2)) == 0
     assert n2.value > n1.value
@@ -249,7 +249,7 @@ def test_model_arguments(L):
     # (VL, BX, BY, BZ, pipelined) chosen by the library for the benchmark workloads
     ("c2", 0, 1, 0, (4, 3, 2, 12, 1)),    # FP64, 16 nodes per x half
     ("c2", 0, 1, 1, (4, 4, 2, 12, 1)),    # ES-BGK FP64
-    ("c2", 0, 2, 0, (4, 2, 2, 12, 1)),    # second order FP64
+    ("c2", 0, 2, 0, (2, 4, 2, 12, 1)),    # second order FP64: 2 per lane
     ("c3", 1, 1, 0, (4, 4, 2, 8, 1)),     # FP32, 14 nodes per half (empty slots)
     ("c3", 0, 1, 0, (2, 4, 2, 8, 1)),     # FP64, 14 nodes per half -> 2 per lane
     ("c4", 1, 1, 0, (4, 4, 2, 8, 1)),     # FP32, 24 nodes per half
