@@ -469,6 +469,14 @@ def main():
             "traffic_label": label,
         },
     }
+    # the measured HBM bytes per launch over the live launch time, against
+    # the same peak (the third figure of the roofline: what the memory
+    # system actually moved, beside the algorithmic rate above)
+    tr = line["roofline"]["traffic"]
+    if tr is not None and sweep_ms > 0:
+        gbs = tr * launches / (sweep_ms / 1e3) / 1e9
+        line["roofline"]["traffic_gbs"] = round(gbs, 1)
+        line["roofline"]["traffic_frac"] = round(gbs / PEAK_HBM_GBS, 4)
     if not args.no_cpu and args.workload != "c6":
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)
