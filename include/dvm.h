@@ -102,8 +102,15 @@ typedef struct {
     int velocity_groups;        /* velocity groups swept one after another        */
 } dvm_info;
 
-/* Create a context.  precision: DVM_F64 or DVM_F32 (storage and update type of
-   f; moments, correction and all per-cell quantities stay FP64).  hip_stream:
+/* Create a context.  precision: DVM_F64 or DVM_F32, the storage and update
+   type of f.  With DVM_F32 the sweep also evaluates the equilibrium in FP32:
+   the per-cell parameters (U, T, 1/tau, the Shakhov coefficients and the
+   multipliers of the conservative correction) are computed in FP64 from the
+   FP64 conserved moments and then rounded to FP32 for the sweep, so the
+   FP32 collision operator conserves mass, momentum and energy to FP32
+   rounding; the velocity moments are accumulated in FP64, and the
+   finalisation, wall densities, mass rescaling and residual are FP64 in
+   both precisions.  hip_stream:
    a hipStream_t on which every kernel and copy is issued (NULL = null stream).
    Defaults: all six faces diffuse walls at rest with T = 1, no solid, closed.
    Errors: DVM_ERR_ARG for non-positive sizes, lengths, kn, pr or T. */
@@ -115,10 +122,16 @@ dvm_status dvm_create(const dvm_grid* grid, const dvm_vgrid* vgrid, const dvm_ga
    with an odd velocity count along z), DVM_ERR_STATE after binding. */
 dvm_status dvm_set_face_bc(dvm_ctx* ctx, int face, const dvm_face_bc* bc);
 
-/* Solid cells (mask[c] != 0) inside the box; their faces are diffuse walls
-   with velocity u_wall and temperature T_wall.  mask may be NULL (no solid). */
+/* Solid cells (mask[c] != 0, nx*ny*nz bytes, host, copied by the call)
+   inside the box; their faces are diffuse walls with velocity u_wall and
+   temperature T_wall (the solid body of the cube flow, Sec. 4.2).  mask may
+   be NULL (no solid).  Before binding the workspace (DVM_ERR_STATE after
+   it); DVM_ERR_ARG for T_wall <= 0. */
 dvm_status dvm_set_solid(dvm_ctx* ctx, const unsigned char* mask, const double u_wall[3],
                          double T_wall);
+/* The same call under the name of the solid-mask setter. */
+dvm_status dvm_set_solid_mask(dvm_ctx* ctx, const unsigned char* mask, const double u_wall[3],
+                              double T_wall);
 
 /* closed != 0: rescale the density field after every iteration so that the
    total mass stays that of the initial state (Sec. 3.4, internal flows). */
@@ -198,6 +211,22 @@ dvm_status dvm_set_order(dvm_ctx* ctx, int order);
    cells, 48^3 velocities) fit one device.  Before binding the workspace;
    DVM_ERR_STATE after it, DVM_ERR_ARG for groups < 1. */
 dvm_status dvm_set_velocity_groups(dvm_ctx* ctx, int groups);
+
+/* Sweep schedule in place of the library's choice, for measurements and
+   tests of a particular kernel: vel_per_lane discrete velocities per lane
+   (1, 2, 4 or 8), bricks of bx x by x bz cells, body 1 = plain,
+   2 = software-pipelined.  0 keeps the library's choice for that value
+   (the brick's x and y sizes default to those of the chosen velocities per
+   lane).  The result is the same for every schedule up to the order of the
+   FP64 moment sums; only the speed differs.  The brick column is shortened
+   where the sweep's 32-bit face offsets would overflow (dvm_get_info
+   reports the schedule in use).  DVM_ERR_ARG for values out of range or a
+   kernel shape that is not built for the context's precision, mesh kind,
+   order and model (the previous schedule stays; a later dvm_set_order,
+   dvm_set_model or dvm_set_spacing that leaves the request without a
+   kernel makes dvm_bind_workspace fail with DVM_ERR_ARG).  Before binding
+   the workspace (DVM_ERR_STATE after it). */
+dvm_status dvm_set_schedule(dvm_ctx* ctx, int vel_per_lane, int bx, int by, int bz, int body);
 
 /* Bytes of device workspace the context needs with its current settings. */
 dvm_status dvm_required_workspace(dvm_ctx* ctx, size_t* bytes);

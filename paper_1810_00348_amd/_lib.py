@@ -58,6 +58,8 @@ EXPORTS = {
                     C.POINTER(C.c_void_p)], C.c_int),
     "dvm_set_face_bc": ([C.c_void_p, C.c_int, C.POINTER(FaceBC)], C.c_int),
     "dvm_set_solid": ([C.c_void_p, C.c_void_p, _P, C.c_double], C.c_int),
+    "dvm_set_solid_mask": ([C.c_void_p, C.c_void_p, _P, C.c_double], C.c_int),
+    "dvm_set_schedule": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
     "dvm_set_closed": ([C.c_void_p, C.c_int], C.c_int),
     "dvm_set_spacing": ([C.c_void_p, _P, _P, _P], C.c_int),
     "dvm_set_velocity_groups": ([C.c_void_p, C.c_int], C.c_int),

@@ -1265,7 +1265,8 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     const size_t fstride = (size_t)A.slots * VL;
     const unsigned lofs = (unsigned)slot * VL * SB;
     // a face cell of this brick, as a 32-bit byte offset from the brick's face
-    // base (c < BZ * max(nx, ny) + BY: the host keeps c * rowb below 2^32)
+    // base: c <= (BZ - 1) * max(nx, ny) + max(BX, BY) - 1 on the x and y faces,
+    // c <= (BY - 1) * nx + BX - 1 on the z face; the host keeps c * rowb below 2^32
     const unsigned rowb = (unsigned)(fstride * SB);
     auto fcell = [rowb](auto* base, int c) { return (decltype(base))((const char*)base + (unsigned)c * rowb); };
 

@@ -47,13 +47,6 @@ dvm_status fail(dvm_status st, const char* fmt, ...)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int env_int(const char* name, int dflt)
-{
-    const char* s = getenv(name);
-    if (!s || !*s) return dflt;
-    return atoi(s);
-}
-
 }  // namespace
 
 struct dvm_ctx {
@@ -74,6 +67,12 @@ struct dvm_ctx {
     int hsplit[3];  // number of nodes with xi < 0 along each axis
     int VL = 2, BX = 4, BY = 4, BZ = 8;
     int PF = 1;  // software-pipelined sweep body
+    // schedule requested with dvm_set_schedule (0: the library's choice);
+    // req_ok is false while the request names a kernel shape that is not
+    // built for the current precision, mesh kind, order and model
+    int req_vl = 0, req_bx = 0, req_by = 0, req_bz = 0, req_body = 0;
+    bool req_ok = true;
+    bool fits32 = true;  // the 32-bit face offsets of the schedule fit
     int order = 1;  // spatial order of the upwind scheme (1 or 2)
     int model = 0;  // 0: Shakhov, 1: ES-BGK
     // velocity nodes and weights per axis (empty: uniform, trapezoid)
@@ -136,7 +135,8 @@ void derive_schedule(dvm_ctx* c)
     for (int d = 0; d < 3; ++d) c->hsplit[d] = c->vg.m[d] / 2;
     c->Ssz = c->prec == DVM_F64 ? 8 : 4;
 
-    // velocities per lane, brick shape (overridable for tuning)
+    // velocities per lane, brick shape and body: the library's choice, or
+    // what dvm_set_schedule requested where that kernel is built.
     // VL: 4 velocities per lane, halved while more than 1/8 of the lanes'
     // velocity slots of the larger x half would be empty.  Brick and body by
     // measurement (cavity 64^3 x 32^3 FP64, 96^3 x 28^3 and cube FP32):
@@ -157,30 +157,37 @@ void derive_schedule(dvm_ctx* c)
     // the first-order forms
     if (f64 && (nax % 4 || o2)) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
-    vl = env_int("DVM_VL", vl);
     auto default_bx = [&](int v) { return (f64 && v == 4) ? (o2 ? 2 : es ? 4 : 3) : 4; };
-    int bx = default_bx(vl);
-    int by = vl == 1 ? 4 : 2;
+    auto default_by = [&](int v) { return v == 1 ? 4 : 2; };
+    if (!sweep_variant_available(c->prec, vl, default_bx(vl), default_by(vl), c->nonuniform, o2, es)) vl = 1;
+    int bx = default_bx(vl), by = default_by(vl);
     int pf = vl >= 2 ? 1 : 0;
-    bx = env_int("DVM_BX", bx);
-    by = env_int("DVM_BY", by);
-    if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) {
-        // the shape is not built (for this mesh kind): the defaults' shape for VL
-        bx = default_bx(vl);
-        by = vl == 1 ? 4 : 2;
-        if (!sweep_variant_available(c->prec, vl, bx, by, c->nonuniform, o2, es)) { vl = 1; bx = 4; by = 4; }
-    }
-    c->VL = vl;
-    c->BX = bx;
-    c->BY = by;
     // cells per brick column: 12 for FP64 with 4 per lane and for the
     // second-order FP64 form (141 GPt/s against 137 at 8), (cavity 64^3 x
     // 32^3: 3x2 bricks 277 GPt/s against 268 at 8 and 270 at 16; 4x2 265
     // against 262 at 8 and 256 at 16), 8 otherwise (FP32: 12 is 1-2 %
     // slower on 96^3 x 28^3 and the cube)
-    c->BZ = env_int("DVM_BZ", (f64 && (vl == 4 || o2)) ? 12 : 8);
-    c->PF = env_int("DVM_PF", pf) != 0;
-    if (c->BZ < 1) c->BZ = 1;
+    int bz = (f64 && (vl == 4 || o2)) ? 12 : 8;
+    c->req_ok = true;
+    if (c->req_vl || c->req_bx || c->req_by || c->req_bz || c->req_body) {
+        const int rv = c->req_vl ? c->req_vl : vl;
+        const int rbx = c->req_bx ? c->req_bx : (c->req_vl ? default_bx(rv) : bx);
+        const int rby = c->req_by ? c->req_by : (c->req_vl ? default_by(rv) : by);
+        if (sweep_variant_available(c->prec, rv, rbx, rby, c->nonuniform, o2, es)) {
+            vl = rv;
+            bx = rbx;
+            by = rby;
+            if (c->req_bz) bz = c->req_bz;
+            if (c->req_body) pf = c->req_body == 2;
+        } else {
+            c->req_ok = false;
+        }
+    }
+    c->VL = vl;
+    c->BX = bx;
+    c->BY = by;
+    c->BZ = bz;
+    c->PF = pf;
     c->nbx = (c->g.nx + c->BX - 1) / c->BX;
     c->nby = (c->g.ny + c->BY - 1) / c->BY;
     c->nbz = (c->g.nz + c->BZ - 1) / c->BZ;
@@ -205,18 +212,23 @@ void derive_schedule(dvm_ctx* c)
     c->lstride = LT_SHARED + LT_PER_V * c->VL;
     if (c->lstride & 1) c->lstride++;
     // the sweep addresses a face cell of its brick by a 32-bit byte offset
-    // from the brick's face base: keep (BZ - 1) * max(nx, ny) + max(BX, BY)
-    // face cells of one group's velocities below 2^32 bytes (shorter brick
-    // columns if needed; a grid that breaches this even with BZ = 1 has
-    // face buffers far beyond any device memory)
+    // from the brick's face base: the x and y faces up to face cell
+    // (BZ - 1) * max(nx, ny) + max(BX, BY) - 1, the z face up to
+    // (BY - 1) * nx + BX - 1.  Keep both offsets, in bytes of one group's
+    // velocities, below 2^32 (shorter brick columns if needed; a grid that
+    // breaches this even with BZ = 1 has face buffers far beyond any device
+    // memory)
     {
         const size_t rowb = (size_t)c->gtiles * 64 * c->VL * (c->prec == DVM_F64 ? 8 : 4);
         const size_t span = (size_t)std::max(c->g.nx, c->g.ny);
+        const size_t zcells = (size_t)(c->BY - 1) * c->g.nx + c->BX;
         auto fits = [&](int bz) {
-            return ((size_t)(bz - 1) * span + (size_t)std::max(c->BX, c->BY)) * rowb < ((size_t)1 << 32);
+            const size_t xycells = (size_t)(bz - 1) * span + (size_t)std::max(c->BX, c->BY);
+            return std::max(xycells, zcells) * rowb < ((size_t)1 << 32);
         };
         while (c->BZ > 1 && !fits(c->BZ)) c->BZ = std::max(1, c->BZ / 2);
         c->nbz = (c->g.nz + c->BZ - 1) / c->BZ;
+        c->fits32 = fits(c->BZ);
     }
 
     // bricks grouped by diagonal I + J + K
@@ -800,6 +812,39 @@ dvm_status dvm_set_order(dvm_ctx* c, int order)
     return DVM_OK;
 }
 
+dvm_status dvm_set_schedule(dvm_ctx* c, int vel_per_lane, int bx, int by, int bz, int body)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "the schedule must be set before binding the workspace");
+    if (vel_per_lane < 0 || vel_per_lane > 8 || bx < 0 || bx > 8 || by < 0 || by > 8 || bz < 0 || bz > 256 ||
+        body < 0 || body > 2)
+        return fail(DVM_ERR_ARG, "schedule out of range (vel_per_lane %d, brick %dx%dx%d, body %d)", vel_per_lane,
+                    bx, by, bz, body);
+    const int old[5] = {c->req_vl, c->req_bx, c->req_by, c->req_bz, c->req_body};
+    c->req_vl = vel_per_lane;
+    c->req_bx = bx;
+    c->req_by = by;
+    c->req_bz = bz;
+    c->req_body = body;
+    derive_schedule(c);
+    if (!c->req_ok) {
+        c->req_vl = old[0];
+        c->req_bx = old[1];
+        c->req_by = old[2];
+        c->req_bz = old[3];
+        c->req_body = old[4];
+        derive_schedule(c);
+        return fail(DVM_ERR_ARG, "no sweep kernel with %d velocities per lane and %dx%d bricks is built for this "
+                    "precision, mesh kind, order and model", vel_per_lane, bx, by);
+    }
+    return DVM_OK;
+}
+
+dvm_status dvm_set_solid_mask(dvm_ctx* c, const unsigned char* mask, const double u_wall[3], double T_wall)
+{
+    return dvm_set_solid(c, mask, u_wall, T_wall);
+}
+
 dvm_status dvm_set_velocity_groups(dvm_ctx* c, int groups)
 {
     if (check_ctx(c)) return DVM_ERR_ARG;
@@ -832,6 +877,12 @@ dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
     if (c->bound) return fail(DVM_ERR_STATE, "workspace already bound");
     if (!ptr) return fail(DVM_ERR_ARG, "workspace pointer is NULL");
     if ((uintptr_t)ptr & 255) return fail(DVM_ERR_ARG, "workspace must be 256-byte aligned");
+    if (!c->req_ok)
+        return fail(DVM_ERR_ARG, "the schedule set with dvm_set_schedule has no kernel for the order, model or "
+                    "mesh kind set after it");
+    if (!c->fits32)
+        return fail(DVM_ERR_ARG, "a face row of this grid and velocity set exceeds the 32-bit offsets of the "
+                    "sweep even with one-cell brick columns: use more velocity groups");
     layout(c);
     if (bytes < c->off.end) return fail(DVM_ERR_OOM, "workspace too small: %zu < %zu bytes", bytes, c->off.end);
     c->ws = (char*)ptr;

@@ -19,16 +19,19 @@ def _ptr(a: np.ndarray):
 class Solver:
     """Iterative DVM solver for one ``Case`` on one GPU.
 
-    precision: "f64" (default) or "f32" (f stored and updated in FP32; moments,
-    correction and per-cell quantities in FP64).
-    """
+    precision: "f64" (default) or "f32" (f stored and updated in FP32, the
+    equilibrium evaluated in FP32 from per-cell parameters computed in FP64;
+    moments accumulated in FP64; finalisation and residual in FP64)."""
 
     def __init__(self, case: Case, precision: str = "f64", device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, velocity_groups: Optional[int] = None,
-                 memory_fraction: float = 0.9):
+                 memory_fraction: float = 0.9, schedule: Optional[dict] = None):
         """velocity_groups: sweep the velocity set in that many parts per
         iteration (None: the fewest parts whose workspace fits
-        memory_fraction of the device's free memory)."""
+        memory_fraction of the device's free memory).  schedule: a sweep
+        kernel shape in place of the library's choice, any of the keys vl
+        (velocities per lane), bx, by, bz (brick cells) and pipelined
+        (True / False); see dvm_set_schedule."""
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
         self.case = case
@@ -72,6 +75,14 @@ class Solver:
             L.check(lib.dvm_set_model(h, 1))
         if case.order != 1:
             L.check(lib.dvm_set_order(h, int(case.order)))
+        if schedule:
+            unknown = set(schedule) - {"vl", "bx", "by", "bz", "pipelined"}
+            if unknown:
+                raise ValueError(f"unknown schedule keys {sorted(unknown)}")
+            body = schedule.get("pipelined")
+            L.check(lib.dvm_set_schedule(h, int(schedule.get("vl", 0)), int(schedule.get("bx", 0)),
+                                         int(schedule.get("by", 0)), int(schedule.get("bz", 0)),
+                                         0 if body is None else (2 if body else 1)))
         nbytes = C.c_size_t()
         groups = 1 if velocity_groups is None else int(velocity_groups)
         L.check(lib.dvm_set_velocity_groups(h, groups))

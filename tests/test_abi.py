@@ -295,3 +295,69 @@ def test_brick_columns_shortened_for_32bit_face_offsets(L):
     h = _ctx(L, cases.config("c2"), 0)
     assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.brick[2] == 12
     lib.dvm_destroy(h)
+
+
+def test_schedule_requests(L):
+    """dvm_set_schedule picks a built kernel shape or refuses (host-only)."""
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    info = L.Info()
+    h = _ctx(L, cases.config("c2"), 0)
+    # a built shape: taken, the column length and body as given
+    assert lib.dvm_set_schedule(h, 2, 4, 2, 7, 1) == 0
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert (info.vel_per_lane, *info.brick, info.pipelined) == (2, 4, 2, 7, 0)
+    # a shape that is not built: refused, the previous request stays
+    assert lib.dvm_set_schedule(h, 4, 5, 2, 0, 0) == -1 and b"built" in lib.dvm_last_error()
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert (info.vel_per_lane, *info.brick, info.pipelined) == (2, 4, 2, 7, 0)
+    # out of range
+    for args in ((9, 0, 0, 0, 0), (0, 0, 0, 0, 3), (0, -1, 0, 0, 0)):
+        assert lib.dvm_set_schedule(h, *args) == -1
+    # all zero: the library's choice again
+    assert lib.dvm_set_schedule(h, 0, 0, 0, 0, 0) == 0
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert (info.vel_per_lane, *info.brick, info.pipelined) == (4, 3, 2, 12, 1)
+    # velocities per lane alone: the brick defaults of that width
+    assert lib.dvm_set_schedule(h, 1, 0, 0, 0, 0) == 0
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert (info.vel_per_lane, info.brick[0], info.brick[1]) == (1, 4, 4)
+    # a shape built for the first order only, then the second order: the
+    # request has no kernel any more and binding refuses it (before any
+    # device work)
+    assert lib.dvm_set_schedule(h, 4, 3, 2, 0, 2) == 0
+    assert lib.dvm_set_order(h, 2) == 0
+    assert lib.dvm_bind_workspace(h, C.c_void_p(4096), 1 << 40) == -1
+    assert b"dvm_set_schedule" in lib.dvm_last_error()
+    lib.dvm_destroy(h)
+    # the solid-mask name is the same call
+    h = _ctx(L, cases.cavity((3, 3, 3), 4), 0)
+    mask = (C.c_ubyte * 27)(*([0] * 13 + [1] + [0] * 13))
+    u = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert lib.dvm_set_solid_mask(h, mask, u, 1.0) == 0
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.nfluid == 26
+    assert lib.dvm_set_solid_mask(h, mask, u, 0.0) == -1
+    lib.dvm_destroy(h)
+
+
+def test_z_face_offsets_bound_the_schedule(L):
+    """The z face of a brick is addressed up to cell (BY - 1) * nx + BX - 1:
+    on a grid so long in x that one face row of the velocity set overflows
+    32-bit offsets even with one-cell columns, binding refuses the case
+    (host-only: refused before any device work)."""
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    info = L.Info()
+    # 64^3 velocities, FP64, 4 per lane: 256 KiB per face cell, 16384 face
+    # cells in 4 GiB; a 20000-cell x extent puts the second z-face row of a
+    # 3x2 brick beyond that
+    case = cases.cavity((20000, 2, 2), 64, kn=1.0)
+    h = _ctx(L, case, 0)
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert (info.vel_per_lane, info.brick[0], info.brick[1], info.brick[2]) == (4, 3, 2, 1)
+    assert lib.dvm_bind_workspace(h, C.c_void_p(4096), 1 << 40) == -1
+    assert b"32-bit" in lib.dvm_last_error()
+    # velocity groups shrink the face rows and let it through the check
+    assert lib.dvm_set_velocity_groups(h, 4) == 0
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.brick[2] >= 1
+    lib.dvm_destroy(h)

@@ -42,9 +42,9 @@ def field_errors(g, r):
     return out
 
 
-def run_pair(case, iters, oracle_mod, precision="f64", init=None, groups=1):
+def run_pair(case, iters, oracle_mod, precision="f64", init=None, groups=1, schedule=None):
     Solver = _solver()
-    s = Solver(case, precision=precision, velocity_groups=groups)
+    s = Solver(case, precision=precision, velocity_groups=groups, schedule=schedule)
     o = oracle_mod.Oracle(case)
     if init is None:
         s.init_uniform(); o.init_uniform()
@@ -162,16 +162,12 @@ def test_fp32_storage_error_is_bounded(oracle_mod):
 @pytest.mark.parametrize("pf,vl,bx,by", [(1, 2, 4, 2), (0, 4, 4, 2), (1, 4, 4, 2), (0, 1, 4, 4), (1, 2, 4, 4),
                                           (1, 4, 2, 2), (0, 2, 2, 2), (1, 4, 3, 2), (0, 4, 3, 2)])
 @pytest.mark.parametrize("name", ["ragged", "oddM", "cube"])
-def test_sweep_variants_match_oracle(oracle_mod, monkeypatch, name, pf, vl, bx, by):
+def test_sweep_variants_match_oracle(oracle_mod, name, pf, vl, bx, by):
     """Every sweep body (plain / software-pipelined) and lane/brick shape
     reproduces the oracle (FP64)."""
-    monkeypatch.setenv("DVM_PF", str(pf))
-    monkeypatch.setenv("DVM_VL", str(vl))
-    monkeypatch.setenv("DVM_BX", str(bx))
-    monkeypatch.setenv("DVM_BY", str(by))
     case = _ragged_cases()[name]
     init = cases.random_fields(case, seed=11) if name != "cube" else None
-    s, o = run_pair(case, 2, oracle_mod, init=init)
+    s, o = run_pair(case, 2, oracle_mod, init=init, schedule=dict(vl=vl, bx=bx, by=by, pipelined=bool(pf)))
     inf = s.info()
     assert inf["vel_per_lane"] == vl and inf["brick"][0] == bx and inf["brick"][1] == by
     err = field_errors(s.fields(), o.fields())
@@ -212,14 +208,15 @@ def _stretched_cases():
 
 @pytest.mark.parametrize("pf", [None, 0, 1])
 @pytest.mark.parametrize("name", ["cavity", "cube", "cavity_m16"])
-def test_stretched_mesh_matches_oracle(oracle_mod, monkeypatch, name, pf):
+def test_stretched_mesh_matches_oracle(oracle_mod, name, pf):
     """Non-uniform (stretched) meshes: per-cell upwind coefficients and cell
     volumes, against the oracle (FP64)."""
-    if pf is not None:
-        monkeypatch.setenv("DVM_PF", str(pf))
     case = _stretched_cases()[name]
     init = cases.random_fields(case, seed=21) if name != "cube" else None
-    s, o = run_pair(case, 3, oracle_mod, init=init)
+    sched = None if pf is None else dict(pipelined=bool(pf))
+    s, o = run_pair(case, 3, oracle_mod, init=init, schedule=sched)
+    if pf is not None:
+        assert s.info()["sweep_kernel"] == ("sweep_kernel_pf" if pf else "sweep_kernel")
     err = field_errors(s.fields(), o.fields())
     print(name, pf, err, s.info())
     for k in ("rho", "ux", "uy", "uz", "T"):
@@ -351,16 +348,12 @@ def test_second_order_matches_oracle(oracle_mod, name):
 @pytest.mark.parametrize("pf", [0, 1])
 @pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2), (4, 4, 2)])
 @pytest.mark.parametrize("name", ["ragged", "cube_half", "es_cube_half"])
-def test_second_order_sweep_variants(oracle_mod, monkeypatch, name, vl, bx, by, pf):
+def test_second_order_sweep_variants(oracle_mod, name, vl, bx, by, pf):
     """Plain and pipelined bodies of the second-order sweep (and of the
     second-order ES-BGK sweep) at every built shape."""
-    monkeypatch.setenv("DVM_VL", str(vl))
-    monkeypatch.setenv("DVM_BX", str(bx))
-    monkeypatch.setenv("DVM_BY", str(by))
-    monkeypatch.setenv("DVM_PF", str(pf))
     case = _o2_cases()[name] if name != "es_cube_half" else dataclasses.replace(_o2_cases()["cube_half"],
                                                                                model="esbgk")
-    s, o = run_pair(case, 2, oracle_mod)
+    s, o = run_pair(case, 2, oracle_mod, schedule=dict(vl=vl, bx=bx, by=by, pipelined=bool(pf)))
     info = s.info()
     assert (info["vel_per_lane"], info["brick"][0], info["brick"][1]) == (vl, bx, by), info
     assert info["sweep_kernel"] == ("sweep_kernel_pf" if pf else "sweep_kernel"), info
@@ -576,13 +569,10 @@ def test_two_nodes_per_axis_with_correction_is_rejected(oracle_mod):
 
 @pytest.mark.parametrize("pf", [0, 1])
 @pytest.mark.parametrize("vl,bx,by", [(1, 4, 4), (2, 4, 2), (4, 2, 2), (4, 4, 2)])
-def test_esbgk_sweep_variants(oracle_mod, monkeypatch, vl, bx, by, pf):
-    monkeypatch.setenv("DVM_VL", str(vl))
-    monkeypatch.setenv("DVM_BX", str(bx))
-    monkeypatch.setenv("DVM_BY", str(by))
-    monkeypatch.setenv("DVM_PF", str(pf))
+def test_esbgk_sweep_variants(oracle_mod, vl, bx, by, pf):
     case = _es_cases()["ragged"]
-    s, o = run_pair(case, 2, oracle_mod, init=cases.random_fields(case, seed=62))
+    s, o = run_pair(case, 2, oracle_mod, init=cases.random_fields(case, seed=62),
+                    schedule=dict(vl=vl, bx=bx, by=by, pipelined=bool(pf)))
     info = s.info()
     assert (info["vel_per_lane"], info["brick"][0], info["brick"][1], info["sweep_kernel"]) == \
         (vl, bx, by, "sweep_kernel_pf" if pf else "sweep_kernel"), info
