@@ -6,13 +6,20 @@ moment reduction, finalisation, mass rescaling and the residual read-back) on
 the 3D lid-driven cavity with 64^3 cells and 32^3 discrete velocities on
 [-5,5]^3, Kn = 1, lid speed 0.16, FP64 -- synthetic input, resident in HBM.
 
-Prints ONE JSON line (rank 0).  Options:
+Prints ONE JSON line (rank 0).  Besides the throughput it carries, for the
+default workload, the metric's second half: iterations and wall time to
+residual 1e-6 from the uniform start in FP64, in FP32 storage followed by
+FP64, and both from the learned warm start (``time_to_residual``); the
+roofline object adds the whole-iteration fraction and a plain device copy's
+bandwidth as the practical ceiling; ``cpu_baseline`` names the host CPU and
+the per-core rate.  Options:
   --gpus N      only N = 1 is supported (this build targets one GPU)
   --steps K     timed iterations (default 10)
   --warmup W    untimed iterations first (default 2)
   --workload    c2 (default), c3 (FP32 storage form) or c4 (cube, FP32)
   --precision   override f64/f32
   --no-cpu      skip the CPU oracle baseline
+  --no-ttr      skip the time-to-residual runs
   --traffic F   JSON file with measured HBM bytes per sweep launch (from
                 rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, calibrated)
   --time-to-residual
@@ -159,11 +166,16 @@ def cpu_baseline(case, budget_s: float = 25.0):
     o.iterate(1)
     dt = time.perf_counter() - t0
     pts = sample.points
+    model, nproc, avail = host_cpu()
     return {
         "value": pts / dt / 1e9,
         "unit": "GPt/s",
         "cores": o.threads,
         "kind": "oracle",
+        "per_core_value": pts / dt / 1e9 / max(1, o.threads),
+        "cpu_model": model,
+        "nproc": nproc,
+        "cpus_available": avail,
         "sample": f"one FP64 oracle iteration on {sample.n[0]}x{sample.n[1]}x{sample.n[2]} cells x "
                   f"{m}^3 velocities ({pts:.3g} points, {dt:.1f} s)",
     }
@@ -251,7 +263,7 @@ def warmstart_kernels(n, steps, warmup):
     print(json.dumps(out), flush=True)
 
 
-def time_to_residual(workloads, tol=1e-6, max_iters=3000):
+def time_to_residual_row(name, case, net, chan_std, tol=1e-6, max_iters=3000):
     """Wall time to the residual tolerance from the uniform start (the full
     dvm_iterate loop including its per-iteration residual read-back): FP64
     storage, and FP32 storage until its noise floor followed by FP64 from the
@@ -262,56 +274,104 @@ def time_to_residual(workloads, tol=1e-6, max_iters=3000):
     import torch
     from paper_1810_00348_amd import warmstart as W
     from paper_1810_00348_amd.solver import Solver, solve_fp32_then_fp64
+
+    def field_diff(a, b):
+        return {key: float(f"{np.abs(x - y).max() / max(np.abs(y).max(), 1e-300):.3e}")
+                for key, x, y in (("rho", a["rho"], b["rho"]), ("ux", a["u"][0], b["u"][0]),
+                                  ("uy", a["u"][1], b["u"][1]), ("uz", a["u"][2], b["u"][2]),
+                                  ("T", a["T"], b["T"]))}
+
+    row = {"workload": name, "case": case.name, "points_per_iteration": case.points, "tol": tol}
+    s = Solver(case, precision="f64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.init_uniform()
+    it, r, ok = s.iterate(max_iters, tol=tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    f64 = s.fields()
+    row["f64"] = {"iters": it, "seconds": round(dt, 3), "converged": ok, "residual": r,
+                  "ms_per_iter": round(dt * 1e3 / max(it, 1), 3)}
+    del s
+    torch.cuda.empty_cache()
+    m = solve_fp32_then_fp64(case, tol, max_iters)
+    row["f32_then_f64"] = {k: (round(v, 3) if isinstance(v, float) and k.endswith("seconds") else v)
+                           for k, v in m.items() if k != "fields"}
+    row["mixed_vs_f64_converged"] = field_diff(m["fields"], f64)
+    row["speedup_time_to_residual"] = round(row["f64"]["seconds"] / m["seconds"], 3)
+    torch.cuda.empty_cache()
+    # learned warm start: FP64, and FP32 then FP64
+    w = W.warm_started_solve(net, case, chan_std, tol=tol, max_iters=max_iters)
+    row["warm_f64"] = {"iters": w["iters"], "seconds": round(w["seconds"], 3), "converged": w["converged"],
+                       "fallback": w["fallback"]}
+    row["warm_f64_vs_f64_converged"] = field_diff(w["fields"], f64)
+    row["speedup_warm_f64"] = round(row["f64"]["seconds"] / w["seconds"], 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = W.predict(net, case, chan_std)
+    t_pred = time.perf_counter() - t0
+    mw = solve_fp32_then_fp64(case, tol, max_iters, init=pred, target_mass=1.0)
+    row["warm_f32_then_f64"] = {"iters": mw["iters"], "f32_iters": mw["f32_iters"], "f64_iters": mw["f64_iters"],
+                                "seconds": round(mw["seconds"] + t_pred, 3), "converged": mw["converged"]}
+    row["warm_mixed_vs_f64_converged"] = field_diff(mw["fields"], f64)
+    row["speedup_warm_mixed"] = round(row["f64"]["seconds"] / row["warm_f32_then_f64"]["seconds"], 3)
+    torch.cuda.empty_cache()
+    return row
+
+
+def load_warmstart_net(big):
+    from paper_1810_00348_amd import warmstart as W
     theta, chan_std, _ = W.load_weights(os.path.join(os.path.dirname(W.__file__), "data", "warmstart_unet.npz"))
-    big = max(max(case.n) for _, case in workloads)
     net = W.WarmStartNet(max_grid=(big, big, big))
     net.set_params(theta)
+    return net, chan_std
+
+
+def time_to_residual(workloads, tol=1e-6, max_iters=3000):
+    """One JSON line per workload (see time_to_residual_row)."""
+    big = max(max(case.n) for _, case in workloads)
+    net, chan_std = load_warmstart_net(big)
     for name, case in workloads:
-        row = {"workload": name, "case": case.name, "points_per_iteration": case.points, "tol": tol}
-        s = Solver(case, precision="f64")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.init_uniform()
-        it, r, ok = s.iterate(max_iters, tol=tol)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        f64 = s.fields()
-        row["f64"] = {"iters": it, "seconds": round(dt, 3), "converged": ok, "residual": r,
-                      "ms_per_iter": round(dt * 1e3 / max(it, 1), 3)}
-        del s
-        torch.cuda.empty_cache()
-        m = solve_fp32_then_fp64(case, tol, max_iters)
-        row["f32_then_f64"] = {k: (round(v, 3) if isinstance(v, float) and k.endswith("seconds") else v)
-                               for k, v in m.items() if k != "fields"}
-        a = m["fields"]
-        err = {}
-        for key, x, y in (("rho", a["rho"], f64["rho"]), ("ux", a["u"][0], f64["u"][0]),
-                          ("uy", a["u"][1], f64["u"][1]), ("uz", a["u"][2], f64["u"][2]),
-                          ("T", a["T"], f64["T"])):
-            err[key] = float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
-        row["mixed_vs_f64_converged"] = err
-        row["speedup_time_to_residual"] = round(row["f64"]["seconds"] / m["seconds"], 3)
-        torch.cuda.empty_cache()
-        # learned warm start: FP64, and FP32 then FP64
-        w = W.warm_started_solve(net, case, chan_std, tol=tol, max_iters=max_iters)
-        row["warm_f64"] = {"iters": w["iters"], "seconds": round(w["seconds"], 3), "converged": w["converged"],
-                           "fallback": w["fallback"]}
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pred = W.predict(net, case, chan_std)
-        t_pred = time.perf_counter() - t0
-        mw = solve_fp32_then_fp64(case, tol, max_iters, init=pred, target_mass=1.0)
-        row["warm_f32_then_f64"] = {"iters": mw["iters"], "f32_iters": mw["f32_iters"], "f64_iters": mw["f64_iters"],
-                                    "seconds": round(mw["seconds"] + t_pred, 3), "converged": mw["converged"]}
-        a = mw["fields"]
-        row["warm_mixed_vs_f64_converged"] = {
-            key: float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
-            for key, x, y in (("rho", a["rho"], f64["rho"]), ("ux", a["u"][0], f64["u"][0]),
-                              ("uy", a["u"][1], f64["u"][1]), ("uz", a["u"][2], f64["u"][2]),
-                              ("T", a["T"], f64["T"]))}
-        row["speedup_warm_mixed"] = round(row["f64"]["seconds"] / row["warm_f32_then_f64"]["seconds"], 3)
-        torch.cuda.empty_cache()
-        print(json.dumps(row), flush=True)
+        print(json.dumps(time_to_residual_row(name, case, net, chan_std, tol, max_iters)), flush=True)
+
+
+def copy_bandwidth(gib: float = 4.0, reps: int = 5):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy
+    of gib GiB (read + write counted), best of reps, timed with HIP events."""
+    import torch
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (best / 1e3) / 1e9
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
 
 
 def main():
@@ -323,6 +383,8 @@ def main():
     ap.add_argument("--kn", type=float, default=1.0)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ttr", action="store_true",
+                    help="skip the time-to-residual runs of the default line (64^3 x 32^3 cavity, Kn 1)")
     ap.add_argument("--traffic", default=None)
     ap.add_argument("--time-to-residual", action="store_true")
     ap.add_argument("--solve", type=int, default=0, metavar="ITERS",
@@ -469,6 +531,17 @@ def main():
             "traffic_label": label,
         },
     }
+    # the whole iteration (parameters, sweep, finalisation, residual
+    # read-back) at the same algorithmic bytes, and a plain copy's rate on
+    # this device as the practical ceiling beside the vendor peak
+    step_gbs = pts * 2 * sbytes / (ms / 1e3) / 1e9
+    line["roofline"]["achieved_step"] = round(step_gbs, 1)
+    line["roofline"]["frac_step"] = round(step_gbs / PEAK_HBM_GBS, 4)
+    del s
+    torch.cuda.empty_cache()
+    cgbs = copy_bandwidth()
+    line["roofline"]["copy_gbs"] = round(cgbs, 1)
+    line["roofline"]["frac_of_copy"] = round(achieved_gbs / cgbs, 4)
     # the measured HBM bytes per launch over the live launch time, against
     # the same peak (the third figure of the roofline: what the memory
     # system actually moved, beside the algorithmic rate above)
@@ -477,6 +550,14 @@ def main():
         gbs = tr * launches / (sweep_ms / 1e3) / 1e9
         line["roofline"]["traffic_gbs"] = round(gbs, 1)
         line["roofline"]["traffic_frac"] = round(gbs / PEAK_HBM_GBS, 4)
+    plain = args.stretch == 0 and args.order == 1 and args.model == "shakhov" and args.precision is None
+    if args.workload == "c2" and args.kn == 1.0 and plain and not args.no_ttr:
+        # the metric's second half: time to residual 1e-6 from the uniform
+        # start, FP64 against FP32-then-FP64 and the learned warm start
+        net, chan_std = load_warmstart_net(max(case.n))
+        line["time_to_residual"] = time_to_residual_row("c2_kn1", case, net, chan_std)
+        del net
+        torch.cuda.empty_cache()
     if not args.no_cpu and args.workload != "c6":
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)

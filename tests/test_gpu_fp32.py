@@ -1,0 +1,96 @@
+"""FP32 storage form against the FP64 oracle, at the sweep kernel the FP32
+workloads run: 4 discrete velocities per lane, 4 x 2 bricks, the
+software-pipelined body, a uniform mesh -- the library's own choice, which
+each test asserts before it compares.
+
+The FP64 oracle runs the same iterations from the same start; the error
+measure is that of the FP64 parity tests (per field, normwise).  Bars: the
+FP32 rounding of f (2^-24 relative) and of the per-cell parameters enters
+every update; the update is a convex combination of upwind values and the
+equilibrium, so it does not grow along the sweep, but the moment sums over
+all velocities cancel in U and q: after 5 iterations rho, T <= 1e-5 and
+the velocity components <= 1e-4 of their scale.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1810_00348_amd import cases
+
+from test_gpu_parity import _solver, field_errors, run_pair
+
+pytestmark = pytest.mark.gpu
+
+BAR_RHO_T = 1e-5
+BAR_U = 1e-4
+
+
+def _assert_default_fp32_kernel(info):
+    assert info["precision"] == 1, info
+    assert info["vel_per_lane"] == 4, info
+    assert info["brick"][:2] == [4, 2], info
+    assert info["sweep_kernel"] == "sweep_kernel_pf", info
+
+
+def _fp32_cases():
+    # cavity with 16^3 velocities: 8 nodes per half axis, two lanes per row
+    a = cases.cavity((12, 12, 12), 16, kn=0.5, lid=0.3)
+    # 28 nodes per axis (the 96^3 cavity's velocity grid): 14 per half, so
+    # every fourth lane of a row carries two empty velocity slots
+    b = cases.cavity((10, 9, 11), 28, kn=0.5, lid=0.3)
+    # cube half-domain at Mach 5, Kn 0.1, velocities on [-12, 12]^3:
+    # specular plane, solid body, free stream on five faces
+    c = cases.cube_half(nx=16, ny=12, nz=8, edge=4, x0=4, m=16, vmax=12.0, mach=5.0, kn=0.1)
+    d = cases.cube_half(nx=16, ny=12, nz=8, edge=4, x0=4, m=24, vmax=12.0, mach=5.0, kn=0.1)
+    return {"cavity_m16": a, "cavity_m28": b, "cube_m16": c, "cube_m24": d}
+
+
+@pytest.mark.parametrize("name", ["cavity_m16", "cavity_m28", "cube_m16", "cube_m24"])
+def test_fp32_default_kernel_matches_fp64_oracle(oracle_mod, name):
+    case = _fp32_cases()[name]
+    s, o = run_pair(case, 5, oracle_mod, precision="f32")
+    info = s.info()
+    _assert_default_fp32_kernel(info)
+    err = field_errors(s.fields(), o.fields())
+    print(name, info, {k: f"{v:.2e}" for k, v in err.items()})
+    for k in ("rho", "T"):
+        assert err[k] <= BAR_RHO_T, (k, err)
+    for k in ("ux", "uy", "uz"):
+        assert err[k] <= BAR_U, (k, err)
+    # the wall / free-stream inflow densities of the boundary faces
+    rwg, rwo = s.state()[2], o.state()[2]
+    assert np.abs(rwg - rwo).max() <= BAR_RHO_T * np.abs(rwo).max()
+
+
+def test_fp32_default_kernel_random_start(oracle_mod):
+    """A random (rho, U, T) start puts a heat flux and a drifting, heated
+    equilibrium with a non-trivial correction in every cell from the second
+    iteration on."""
+    case = _fp32_cases()["cavity_m16"]
+    init = cases.random_fields(case, seed=5)
+    s, o = run_pair(case, 3, oracle_mod, precision="f32", init=init)
+    _assert_default_fp32_kernel(s.info())
+    err = field_errors(s.fields(), o.fields())
+    print({k: f"{v:.2e}" for k, v in err.items()})
+    for k in ("rho", "T"):
+        assert err[k] <= BAR_RHO_T, (k, err)
+    for k in ("ux", "uy", "uz"):
+        assert err[k] <= BAR_U, (k, err)
+
+
+def test_fp32_collision_conserves_mass_in_closed_cavity():
+    """Closed cavity in FP32 storage: the mass rescaling (FP64) holds the
+    total mass at M0 to FP64 rounding every iteration."""
+    Solver = _solver()
+    case = _fp32_cases()["cavity_m28"]
+    s = Solver(case, precision="f32")
+    _assert_default_fp32_kernel(s.info())
+    rho, u, T = cases.random_fields(case, seed=9)
+    s.init_fields(rho, u, T)
+    M0 = s.state()[3]
+    dv = 1.0 / case.ncells
+    for _ in range(3):
+        s.iterate(1)
+        W = s.state()[0]
+        assert abs(W[0].sum() * dv - M0) <= 1e-13 * M0

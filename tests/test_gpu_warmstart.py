@@ -184,6 +184,43 @@ def test_training_reduces_the_loss():
     assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
 
 
+def test_adam_kernel_matches_reference():
+    """Two Adam steps of the HIP kernel (FP32, bias-corrected) against the
+    FP64 reference update, fed the gradients the network computed; the
+    reference carries its own moment estimates from the same gradients."""
+    ws = _ws()
+    import torch
+    specs = U.layer_specs(3, 5, 8)
+    theta = U.init_params(specs, seed=21).astype(np.float32)
+    net = ws.WarmStartNet(max_grid=(8, 8, 8), base=8, cin=3)
+    net.set_params(theta)
+    rng = np.random.default_rng(22)
+    dev = net.device
+    x = torch.from_numpy(rng.standard_normal((8, 8, 8, 3)).astype(np.float32)).to(dev)
+    t = torch.from_numpy(rng.standard_normal((8, 8, 8, 5)).astype(np.float32)).to(dev)
+    mask = torch.ones((8, 8, 8), dtype=torch.float32, device=dev)
+    lr = 2e-3
+    th_ref = theta.astype(np.float64)
+    m = np.zeros_like(th_ref)
+    v = np.zeros_like(th_ref)
+    for step in (1, 2):
+        net.zero_grad()
+        net.forward(x)
+        net.backward_mse(t, mask)
+        g = net.grads().astype(np.float64)
+        assert np.abs(g).max() > 0
+        net.adam_step(lr)
+        th_ref, m, v = U.adam(th_ref, m, v, g, step, lr)
+        got = net.params().astype(np.float64)
+        # FP32 update of an FP32 parameter: a few units of its last place,
+        # plus the FP32 rounding of the step itself (|step| <= ~lr)
+        err = np.abs(got - th_ref)
+        bound = 1e-4 * lr + 4e-7 * np.abs(th_ref)
+        assert (err <= bound).all(), (step, float((err / bound).max()))
+        # the parameters did move by about lr
+        assert np.abs(got - theta).max() > 0.5 * lr
+
+
 WEIGHTS = os.path.join(ROOT, "paper_1810_00348_amd", "data", "warmstart_unet.npz")
 
 
