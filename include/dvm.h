@@ -29,10 +29,13 @@
  *     FP64 (a 3-vector field u is u[d*N + c]).
  *   - Host arrays are owned by the caller; every call that reads or writes
  *     them copies synchronously on the context's stream.
- *   - Device memory: the library allocates none.  The caller (the Python
+ *   - Device memory: a context allocates none.  The caller (the Python
  *     binding uses torch) allocates a workspace of dvm_required_workspace()
  *     bytes and lends it with dvm_bind_workspace(); the library never frees
  *     it.  The workspace must stay alive and untouched until dvm_destroy().
+ *     Small contexts may instead take the library's static workspace
+ *     (dvm_bind_static_workspace).  Only the self-test
+ *     dvm_selftest_wave_reduce allocates (and frees) device memory.
  *   - Every call returns a dvm_status; on an error the context keeps the
  *     last good iterate and dvm_last_error() describes the failure.
  *   - A context is not thread-safe; distinct contexts are independent.
@@ -235,6 +238,25 @@ dvm_status dvm_required_workspace(dvm_ctx* ctx, size_t* bytes);
    Uploads the velocity set and boundary tables and computes the wall
    emission shapes on the device. */
 dvm_status dvm_bind_workspace(dvm_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* For callers that cannot allocate device memory (code that runs under HIP
+   graph capture, tight serving loops, hosts that forbid hipMalloc): bind the
+   library's own static workspace of the current device instead of a lent
+   one.  That workspace is a file-scope device array of 64 MiB per device
+   (DVM_STATIC_WORKSPACE_BYTES), held by each device the library runs on
+   until the process ends; this call allocates nothing.  It holds contexts
+   whose dvm_required_workspace() is at most that size (e.g. 16^3 cells x
+   12^3 velocities FP64 needs 35 MiB); larger ones get DVM_ERR_OOM, nothing
+   changed.  One device array serves one context at a time: binding it to a
+   new context takes it from the previous one, whose later calls that touch
+   the workspace (init, iterate, get/set state, fields, stress) return
+   DVM_ERR_STATE; calls of two contexts on one device that overlap in time
+   race on the array.  Everything a kernel reads before writing is written
+   by this call or the initial state, so the previous contents do not
+   matter.  The current device must be the stream's device (DVM_ERR_ARG
+   otherwise).  Other errors as dvm_bind_workspace. */
+#define DVM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+dvm_status dvm_bind_static_workspace(dvm_ctx* ctx);
 
 /* Uniform initial state (rho, u, T); q = 0; wall densities from the
    non-penetration flux of the initial equilibrium (Sec. 2.2, initial

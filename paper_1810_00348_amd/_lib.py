@@ -70,6 +70,7 @@ EXPORTS = {
     "dvm_set_velocity_axes": ([C.c_void_p, _P, _P, _P, _P, _P, _P], C.c_int),
     "dvm_required_workspace": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "dvm_bind_workspace": ([C.c_void_p, C.c_void_p, C.c_size_t], C.c_int),
+    "dvm_bind_static_workspace": ([C.c_void_p], C.c_int),
     "dvm_init_uniform": ([C.c_void_p, C.c_double, _P, C.c_double], C.c_int),
     "dvm_init_fields": ([C.c_void_p, _P, _P, _P, C.c_double], C.c_int),
     "dvm_iterate": ([C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_int), _P], C.c_int),

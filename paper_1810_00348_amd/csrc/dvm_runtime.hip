@@ -14,6 +14,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -96,6 +97,7 @@ struct dvm_ctx {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     bool bound = false;
+    int static_dev = -1;  // device whose static workspace is bound (-1: a lent one)
     struct {
         size_t axes, spacing, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
             partial, acc, xface, yface, zface, spec, xg, yg, zg, specg, stress, blockmass, respart, out, flag,
@@ -123,7 +125,31 @@ struct dvm_ctx {
     T* P(size_t o) const { return reinterpret_cast<T*>(ws + o); }
 };
 
+// The allocation-free workspace: one array per device, lent to at most one
+// context at a time by dvm_bind_static_workspace.  In host code `scratch` is
+// only a handle for the runtime's symbol lookup; its device address on each
+// device comes from hipGetSymbolAddress with that device current.
+constexpr size_t kStaticWorkspaceBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+const dvm_ctx* g_static_owner[kMaxDevices] = {};
+
+// a context bound to a device's static workspace may touch it only while it
+// is that workspace's latest owner
+dvm_status check_workspace_owner(const dvm_ctx* c)
+{
+    if (c->static_dev < 0) return DVM_OK;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_owner[c->static_dev] != c)
+        return fail(DVM_ERR_STATE, "the static workspace of device %d was bound to another context since",
+                    c->static_dev);
+    return DVM_OK;
+}
 
 void derive_schedule(dvm_ctx* c)
 {
@@ -779,6 +805,7 @@ dvm_status dvm_get_stress(dvm_ctx* c, double* P)
     if (c->model != 1) return fail(DVM_ERR_STATE, "the stress is kept for the ES-BGK model only");
     if (!c->initialized) return fail(DVM_ERR_STATE, "no state yet");
     if (!P) return fail(DVM_ERR_ARG, "NULL");
+    if (dvm_status e = check_workspace_owner(c)) return e;
     const size_t N = c->N;
     HIPCHK(hipMemcpyAsync(P, c->P<double>(c->off.stress) + (size_t)c->cur * 6 * N, sizeof(double) * 6 * N,
                           hipMemcpyDeviceToHost, c->stream));
@@ -792,6 +819,7 @@ dvm_status dvm_set_stress(dvm_ctx* c, const double* P)
     if (c->model != 1) return fail(DVM_ERR_STATE, "the stress is kept for the ES-BGK model only");
     if (!c->initialized) return fail(DVM_ERR_STATE, "set a state first");
     if (!P) return fail(DVM_ERR_ARG, "NULL");
+    if (dvm_status e = check_workspace_owner(c)) return e;
     const size_t N = c->N;
     for (size_t i = 0; i < 6 * N; ++i)
         if (!isfinite(P[i])) return fail(DVM_ERR_ARG, "stress value %zu is not finite", i);
@@ -871,12 +899,12 @@ dvm_status dvm_required_workspace(dvm_ctx* c, size_t* bytes)
     return DVM_OK;
 }
 
-dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
+namespace {
+
+// checks that need no workspace: the schedule has a kernel and fits
+dvm_status check_bindable(dvm_ctx* c)
 {
-    if (check_ctx(c)) return DVM_ERR_ARG;
     if (c->bound) return fail(DVM_ERR_STATE, "workspace already bound");
-    if (!ptr) return fail(DVM_ERR_ARG, "workspace pointer is NULL");
-    if ((uintptr_t)ptr & 255) return fail(DVM_ERR_ARG, "workspace must be 256-byte aligned");
     if (!c->req_ok)
         return fail(DVM_ERR_ARG, "the schedule set with dvm_set_schedule has no kernel for the order, model or "
                     "mesh kind set after it");
@@ -884,7 +912,14 @@ dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
         return fail(DVM_ERR_ARG, "a face row of this grid and velocity set exceeds the 32-bit offsets of the "
                     "sweep even with one-cell brick columns: use more velocity groups");
     layout(c);
-    if (bytes < c->off.end) return fail(DVM_ERR_OOM, "workspace too small: %zu < %zu bytes", bytes, c->off.end);
+    return DVM_OK;
+}
+
+// carve the workspace, upload the tables, compute the emission shapes; every
+// buffer a kernel reads before writing it is written here or by the initial
+// state, so the workspace's previous contents do not matter
+dvm_status bind_impl(dvm_ctx* c, void* ptr, size_t bytes)
+{
     c->ws = (char*)ptr;
     c->ws_bytes = bytes;
     hipStream_t st = c->stream;
@@ -943,11 +978,67 @@ dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
     return DVM_OK;
 }
 
+}  // namespace
+
+dvm_status dvm_bind_workspace(dvm_ctx* c, void* ptr, size_t bytes)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (!ptr) return fail(DVM_ERR_ARG, "workspace pointer is NULL");
+    if ((uintptr_t)ptr & 255) return fail(DVM_ERR_ARG, "workspace must be 256-byte aligned");
+    if (dvm_status e = check_bindable(c)) return e;
+    if (bytes < c->off.end) return fail(DVM_ERR_OOM, "workspace too small: %zu < %zu bytes", bytes, c->off.end);
+    return bind_impl(c, ptr, bytes);
+}
+
+dvm_status dvm_bind_static_workspace(dvm_ctx* c)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (dvm_status e = check_bindable(c)) return e;
+    if (c->off.end > kStaticWorkspaceBytes)
+        return fail(DVM_ERR_OOM, "the context needs %zu bytes of workspace, more than the %zu bytes of the static "
+                    "workspace: lend one with dvm_bind_workspace", c->off.end, kStaticWorkspaceBytes);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DVM_ERR_DEVICE, "device %d out of range", dev);
+    if (c->stream) {
+        hipDevice_t sdev = -1;
+        HIPCHK(hipStreamGetDevice(c->stream, &sdev));
+        if (sdev != dev)
+            return fail(DVM_ERR_ARG, "the context's stream is on device %d, the current device is %d", (int)sdev,
+                        dev);
+    }
+    void* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (!g_static_ptr[dev]) {
+            void* a = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !a)
+                return fail(DVM_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                            hipGetErrorString(e));
+            g_static_ptr[dev] = a;
+        }
+        p = g_static_ptr[dev];
+        // the previous owner loses the workspace before it is overwritten
+        g_static_owner[dev] = c;
+    }
+    c->static_dev = dev;
+    const dvm_status st = bind_impl(c, p, kStaticWorkspaceBytes);
+    if (st != DVM_OK) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[dev] == c) g_static_owner[dev] = nullptr;
+        c->static_dev = -1;
+        c->ws = nullptr;
+    }
+    return st;
+}
+
 dvm_status dvm_init_fields(dvm_ctx* c, const double* rho, const double* u, const double* T, double target_mass)
 {
     if (check_ctx(c)) return DVM_ERR_ARG;
     if (!c->bound) return fail(DVM_ERR_STATE, "bind a workspace first");
     if (!rho || !u || !T) return fail(DVM_ERR_ARG, "NULL field");
+    if (dvm_status e = check_workspace_owner(c)) return e;
     const size_t N = c->N;
     double mass = 0;
     for (size_t i = 0; i < N; ++i) {
@@ -992,6 +1083,7 @@ dvm_status dvm_iterate(dvm_ctx* c, int max_iters, double tol, int* iters_done, d
     if (check_ctx(c)) return DVM_ERR_ARG;
     if (!c->initialized) return fail(DVM_ERR_STATE, "initialise the state first");
     if (max_iters < 0) return fail(DVM_ERR_ARG, "max_iters must be >= 0");
+    if (dvm_status e = check_workspace_owner(c)) return e;
     if (iters_done) *iters_done = 0;
     double hout[8];
     double r = INFINITY;
@@ -1032,6 +1124,7 @@ dvm_status dvm_get_state(dvm_ctx* c, double* W, double* q, double* rho_w, double
 {
     if (check_ctx(c)) return DVM_ERR_ARG;
     if (!c->initialized) return fail(DVM_ERR_STATE, "no state yet");
+    if (dvm_status e = check_workspace_owner(c)) return e;
     const size_t N = c->N;
     hipStream_t st = c->stream;
     if (W) HIPCHK(hipMemcpyAsync(W, c->P<double>(c->off.W) + c->cur * 5 * N, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, st));
@@ -1047,6 +1140,7 @@ dvm_status dvm_set_state(dvm_ctx* c, const double* W, const double* q, const dou
     if (check_ctx(c)) return DVM_ERR_ARG;
     if (!c->bound) return fail(DVM_ERR_STATE, "bind a workspace first");
     if (!W || !q || !rho_w) return fail(DVM_ERR_ARG, "NULL");
+    if (dvm_status e = check_workspace_owner(c)) return e;
     const size_t N = c->N;
     for (size_t i = 0; i < N; ++i) {
         if (c->cellinfo[i] & SOLID_BIT) continue;
@@ -1164,6 +1258,10 @@ dvm_status dvm_selftest_wave_reduce(const double* in, double* out)
 void dvm_destroy(dvm_ctx* c)
 {
     if (!c) return;
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+    }
     for (int k = 0; k < 4; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;

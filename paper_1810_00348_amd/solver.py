@@ -25,13 +25,17 @@ class Solver:
 
     def __init__(self, case: Case, precision: str = "f64", device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, velocity_groups: Optional[int] = None,
-                 memory_fraction: float = 0.9, schedule: Optional[dict] = None):
+                 memory_fraction: float = 0.9, schedule: Optional[dict] = None,
+                 static_workspace: bool = False):
         """velocity_groups: sweep the velocity set in that many parts per
         iteration (None: the fewest parts whose workspace fits
         memory_fraction of the device's free memory).  schedule: a sweep
         kernel shape in place of the library's choice, any of the keys vl
         (velocities per lane), bx, by, bz (brick cells) and pipelined
-        (True / False); see dvm_set_schedule."""
+        (True / False); see dvm_set_schedule.  static_workspace: bind the
+        library's static device workspace (no allocation; small contexts
+        only, one context per device at a time; see
+        dvm_bind_static_workspace) instead of a torch buffer."""
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
         self.case = case
@@ -97,9 +101,14 @@ class Solver:
                 groups += 1
                 L.check(lib.dvm_set_velocity_groups(h, groups))
                 L.check(lib.dvm_required_workspace(h, C.byref(nbytes)))
-        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
-        with torch.cuda.device(self.device):
-            L.check(lib.dvm_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value))
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                L.check(lib.dvm_bind_static_workspace(h))
+        else:
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            with torch.cuda.device(self.device):
+                L.check(lib.dvm_bind_workspace(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value))
         self.N = case.ncells
 
     def __del__(self):

@@ -361,3 +361,19 @@ def test_z_face_offsets_bound_the_schedule(L):
     assert lib.dvm_set_velocity_groups(h, 4) == 0
     assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.brick[2] >= 1
     lib.dvm_destroy(h)
+
+
+def test_static_workspace_size_limit(L):
+    """dvm_bind_static_workspace refuses a context larger than the static
+    array before it touches a device, and leaves the context unbound."""
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    h = _ctx(L, cases.config("c2"))
+    n = C.c_size_t()
+    assert lib.dvm_required_workspace(h, C.byref(n)) == 0
+    assert n.value > 64 << 20
+    assert lib.dvm_bind_static_workspace(h) == -3
+    msg = lib.dvm_last_error()
+    assert b"static workspace" in msg and str(64 << 20).encode() in msg
+    assert lib.dvm_init_uniform(h, 1.0, (C.c_double * 3)(0, 0, 0), 1.0) == -2  # still unbound
+    lib.dvm_destroy(h)
