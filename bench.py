@@ -335,6 +335,53 @@ def time_to_residual(workloads, tol=1e-6, max_iters=3000):
         print(json.dumps(time_to_residual_row(name, case, net, chan_std, tol, max_iters)), flush=True)
 
 
+def precision_error(name, case, checkpoints=(1, 5, 20), floor_iters=60, tol=1e-6, parameter_bits=0):
+    """The FP32 storage form against the FP64 path on the same inputs: both
+    from the uniform start, per-field max |x32 - x64| / max |x64| (rho, U_x,
+    U_y, U_z, T, q_x, q_y, q_z) after each checkpoint iteration count; then
+    FP64 to the tolerance and FP32 for floor_iters iterations (its residual
+    stalls at its floor), and the same errors between those two states."""
+    import numpy as np
+    import torch
+    from paper_1810_00348_amd.solver import Solver
+
+    def errors(a, b):
+        out = {}
+        for key in ("rho", "T"):
+            out[key] = float(f"{np.abs(a[key] - b[key]).max() / np.abs(b[key]).max():.3e}")
+        for vec, names in (("u", ("ux", "uy", "uz")), ("q", ("qx", "qy", "qz"))):
+            big = np.abs(b[vec]).max()
+            for d, k in enumerate(names):
+                den = max(np.abs(b[vec][d]).max(), 1e-3 * big, 1e-300)
+                out[k] = float(f"{np.abs(a[vec][d] - b[vec][d]).max() / den:.3e}")
+        return out
+
+    row = {"workload": name, "case": case.name, "checkpoints": {}, "parameter_bits": parameter_bits or 32}
+    s64 = Solver(case, precision="f64")
+    s32 = Solver(case, precision="f32", parameter_bits=parameter_bits)
+    s64.init_uniform()
+    s32.init_uniform()
+    done = 0
+    for k in checkpoints:
+        s64.iterate(k - done)
+        s32.iterate(k - done)
+        done = k
+        row["checkpoints"][str(k)] = errors(s32.fields(), s64.fields())
+    it64, r64, ok64 = s64.iterate(3000, tol=tol)
+    hist = []
+    for _ in range(max(0, floor_iters - done)):
+        _, r, _ = s32.iterate(1)
+        hist.append(r)
+    row["f64_converged"] = {"iters": done + it64, "residual": r64, "converged": ok64}
+    row["f32_floor"] = {"iters": floor_iters, "residual_last": hist[-1] if hist else None,
+                        "residual_min": min(hist) if hist else None,
+                        "residual_last10_max": max(hist[-10:]) if hist else None}
+    row["f32_floor_vs_f64_converged"] = errors(s32.fields(), s64.fields())
+    del s64, s32
+    torch.cuda.empty_cache()
+    return row
+
+
 def copy_bandwidth(gib: float = 4.0, reps: int = 5):
     """Achievable HBM bandwidth on this device: a plain device-to-device copy
     of gib GiB (read + write counted), best of reps, timed with HIP events."""
@@ -383,6 +430,14 @@ def main():
     ap.add_argument("--kn", type=float, default=1.0)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--body", default=None, choices=("plain", "pf", "dyn"),
+                    help="sweep body in place of the library's choice: plain, software-pipelined (pf) "
+                         "or pipelined in one dependency-driven launch (dyn)")
+    ap.add_argument("--param-bits", type=int, default=0, choices=(0, 32, 64),
+                    help="FP32 storage: per-cell parameters and equilibrium evaluation in FP64 (64)")
+    ap.add_argument("--precision-error", action="store_true",
+                    help="instead of the throughput line: per-field error of the FP32 storage form against "
+                         "FP64 on the same inputs (after 1, 5, 20 iterations and at the FP32 floor)")
     ap.add_argument("--no-ttr", action="store_true",
                     help="skip the time-to-residual runs of the default line (64^3 x 32^3 cavity, Kn 1)")
     ap.add_argument("--traffic", default=None)
@@ -429,6 +484,11 @@ def main():
         warmstart_kernels(args.warmstart, args.steps, args.warmup)
         return
 
+    if args.precision_error:
+        case, _ = workload(args.workload, args.kn)
+        print(json.dumps(precision_error(args.workload, case, parameter_bits=args.param_bits)), flush=True)
+        return
+
     if args.time_to_residual:
         from paper_1810_00348_amd import cases
         wl = [(f"c2_kn{kn:g}", cases.config("c2", kn=kn)) for kn in (10.0, 1.0, 0.1)]
@@ -453,7 +513,8 @@ def main():
     if args.solve > 0:
         solve(case, prec, args.solve, args.tol, describe(args.workload, case))
         return
-    s = Solver(case, precision=prec)
+    sched = None if args.body is None else {"pipelined": {"plain": False, "pf": True, "dyn": "dyn"}[args.body]}
+    s = Solver(case, precision=prec, schedule=sched, parameter_bits=args.param_bits)
     s.init_uniform()
     info = s.info()
     if args.warmup:
@@ -485,6 +546,10 @@ def main():
         label += f"_order{args.order}"
     if args.model != "shakhov":
         label += f"_{args.model}"
+    if info["sweep_kernel"] == "sweep_kernel_dyn":
+        label += "_dyn"
+    if prec == "f32" and info["parameter_bits"] == 64:
+        label += "_p64"
     line = {
         "metric": "phase-space GPoint-updates/s per iteration",
         "value": round(value, 3),
@@ -506,6 +571,8 @@ def main():
             "points_per_iteration": pts,
             "brick": info["brick"],
             "vel_per_lane": info["vel_per_lane"],
+            "sweep_kernel": info["sweep_kernel"],
+            "parameter_bits": info["parameter_bits"],
             "sweep_launches_per_iteration": launches,
             "phase_ms": {"params": round(tm["params_ms"] / iters, 4),
                          "sweep": round(sweep_ms, 4),

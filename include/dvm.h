@@ -101,8 +101,11 @@ typedef struct {
     int tiles_per_octant;       /* 64-lane velocity tiles per octant              */
     int sweep_launches;         /* sweep kernel launches per iteration            */
     size_t workspace_bytes;
-    int pipelined;              /* 1: software-pipelined sweep body, 0: plain     */
+    int pipelined;              /* sweep body: 0 plain, 1 software-pipelined, 2
+                                   pipelined in one dependency-driven launch       */
     int velocity_groups;        /* velocity groups swept one after another        */
+    int parameter_bits;         /* 64: per-cell parameters, Gaussian tables and
+                                   equilibrium evaluation in FP64; 32: in FP32    */
 } dvm_info;
 
 /* Create a context.  precision: DVM_F64 or DVM_F32, the storage and update
@@ -218,7 +221,13 @@ dvm_status dvm_set_velocity_groups(dvm_ctx* ctx, int groups);
 /* Sweep schedule in place of the library's choice, for measurements and
    tests of a particular kernel: vel_per_lane discrete velocities per lane
    (1, 2, 4 or 8), bricks of bx x by x bz cells, body 1 = plain,
-   2 = software-pipelined.  0 keeps the library's choice for that value
+   2 = software-pipelined, 3 = software-pipelined in one dependency-driven
+   launch per velocity group and specular phase (first-order Shakhov sweep
+   only): the waves take bricks from a device-wide counter in diagonal order
+   and start each one as soon as its three upwind bricks have published,
+   instead of one launch per brick diagonal; a wait that does not end
+   within half a second fails the iteration with DVM_ERR_DEVICE (the
+   iterate is not updated).  0 keeps the library's choice for that value
    (the brick's x and y sizes default to those of the chosen velocities per
    lane).  The result is the same for every schedule up to the order of the
    FP64 moment sums; only the speed differs.  The brick column is shortened
@@ -230,6 +239,17 @@ dvm_status dvm_set_velocity_groups(dvm_ctx* ctx, int groups);
    kernel makes dvm_bind_workspace fail with DVM_ERR_ARG).  Before binding
    the workspace (DVM_ERR_STATE after it). */
 dvm_status dvm_set_schedule(dvm_ctx* ctx, int vel_per_lane, int bx, int by, int bz, int body);
+
+/* FP32 contexts: bits = 64 keeps the per-cell parameters (U, 1/tau, the
+   Shakhov coefficients, the conservative-correction multipliers), the
+   Gaussian factor tables and the evaluation of the equilibrium in FP64; f
+   is still stored and updated in FP32 and takes the equilibrium rounded
+   once.  bits = 32 (default): all of them in FP32 (see dvm_create).  Built
+   for the first-order Shakhov sweep on a uniform mesh with 4 velocities per
+   lane, 4x2 bricks and a pipelined body; otherwise dvm_bind_workspace fails
+   with DVM_ERR_ARG.  FP64 contexts accept 64 only.  Before binding the
+   workspace (DVM_ERR_STATE after it). */
+dvm_status dvm_set_parameter_precision(dvm_ctx* ctx, int bits);
 
 /* Bytes of device workspace the context needs with its current settings. */
 dvm_status dvm_required_workspace(dvm_ctx* ctx, size_t* bytes);

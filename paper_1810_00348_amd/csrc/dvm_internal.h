@@ -99,6 +99,18 @@ struct SweepArgs {
     int spec_on;
     int has_solid;
     int nblocks;
+    // dependency-driven launches (sweep_kernel_dyn): ready flags
+    // [8][ntiles][nbz][nby][nbx] holding the epoch of the launch that last
+    // swept each brick, the work-unit counter and its value before this
+    // launch, the number of work units, the failure flag word, and where the
+    // launcher reports the number of waves it started (host memory)
+    unsigned* ready;
+    unsigned long long* head;
+    unsigned long long qbase;
+    unsigned epoch;
+    int nitems;
+    int* errflag;
+    int* launched;
 };
 
 // kernel launchers (dvm_kernels.hip)
@@ -114,8 +126,11 @@ hipError_t launch_emission(const Consts& C, const DevPtrs& D, const double* kind
 hipError_t launch_wall_init(const Consts& C, const DevPtrs& D, const void* params, const void* etab,
                             const double* ghat64, const double* gout, double* rho_w, int prec,
                             hipStream_t st);
+// wide_params: FP32 storage of f with the parameter record, Gaussian tables
+// and equilibrium evaluation in FP64 (args' params and etab point to doubles)
 hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, int order2,
-                        int esbgk, const void* args, hipStream_t st);
+                        int esbgk, int wide_params, const void* args, hipStream_t st);
+bool sweep_wide_params_available(int prec, int vl, int bx, int by, int nonuniform, int order2, int esbgk);
 hipError_t launch_finalize(const Consts& C, const DevPtrs& D, const double* partial, int ntiles,
                            const double* gout, double* Wn, double* qn, double* rwn, double* stress_n,
                            double* blockmass, int nblocks, int* flag, hipStream_t st);

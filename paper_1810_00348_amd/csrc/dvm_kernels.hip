@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "dvm_internal.h"
 
 namespace dvm {
@@ -788,6 +790,91 @@ __device__ __forceinline__ void stb_nt(T* base, unsigned off, T v)
     __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off));
 }
 
+// The VL values of a lane in a face row: row at byte offset cofs (uniform)
+// from the face base, the lane's values at lofs within it.  COH: loads and
+// stores coherent at device scope -- buffer instructions with the sc1 bit
+// (the lane offset in a VGPR, the row offset in an SGPR), which bypass the
+// per-CU caches and the per-XCD L2 whose copies of a face row are not kept
+// coherent while one kernel runs -- for faces that a later brick of the
+// same launch reads.  Otherwise plain loads and streaming stores (the
+// reader is a later launch).
+constexpr int BUF_SC1 = 16;                       // cache-policy bit: device scope
+constexpr int BUF_WORD3 = 0x00020000;             // gfx9 raw buffer: 32-bit data format
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t face_rsrc(const S* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base), (short)0, -1, BUF_WORD3);
+}
+template <bool COH, typename S, int VL>
+__device__ __forceinline__ void load_face(const S* base, unsigned cofs, unsigned lofs, S (&out)[VL])
+{
+    if constexpr (!COH) {
+        const S* src = reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + cofs);
+#pragma unroll
+        for (int v = 0; v < VL; ++v) out[v] = ldb(src, lofs + v * (unsigned)sizeof(S));
+    } else {
+        constexpr int NB = VL * (int)sizeof(S);
+        static_assert(NB % 4 == 0, "face values are whole dwords");
+        const __amdgpu_buffer_rsrc_t r = face_rsrc(base);
+        unsigned w[NB / 4];
+        int at = 0;
+#pragma unroll
+        for (; at + 16 <= NB; at += 16) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, lofs + at, cofs, BUF_SC1);
+            w[at / 4] = x[0]; w[at / 4 + 1] = x[1]; w[at / 4 + 2] = x[2]; w[at / 4 + 3] = x[3];
+        }
+        if constexpr (NB % 16 >= 8) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, lofs + (NB / 16) * 16, cofs, BUF_SC1);
+            w[(NB / 16) * 4] = x[0]; w[(NB / 16) * 4 + 1] = x[1];
+        }
+        if constexpr (NB % 8 == 4)
+            w[NB / 4 - 1] = __builtin_amdgcn_raw_buffer_load_b32(r, lofs + NB - 4, cofs, BUF_SC1);
+#pragma unroll
+        for (int v = 0; v < VL; ++v) {
+            if constexpr (sizeof(S) == 8)
+                out[v] = __builtin_bit_cast(S, (unsigned long long)w[2 * v] | ((unsigned long long)w[2 * v + 1] << 32));
+            else
+                out[v] = __builtin_bit_cast(S, w[v]);
+        }
+    }
+}
+template <bool COH, typename S, int VL>
+__device__ __forceinline__ void store_face(S* base, unsigned cofs, unsigned lofs, const S (&val)[VL])
+{
+    if constexpr (!COH) {
+        S* dst = reinterpret_cast<S*>(reinterpret_cast<char*>(base) + cofs);
+#pragma unroll
+        for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * (unsigned)sizeof(S), val[v]);
+    } else {
+        constexpr int NB = VL * (int)sizeof(S);
+        const __amdgpu_buffer_rsrc_t r = face_rsrc(base);
+        unsigned w[NB / 4];
+#pragma unroll
+        for (int v = 0; v < VL; ++v) {
+            if constexpr (sizeof(S) == 8) {
+                const unsigned long long u = __builtin_bit_cast(unsigned long long, val[v]);
+                w[2 * v] = (unsigned)u;
+                w[2 * v + 1] = (unsigned)(u >> 32);
+            } else {
+                w[v] = __builtin_bit_cast(unsigned, val[v]);
+            }
+        }
+        using u4 = __attribute__((ext_vector_type(4))) unsigned;
+        using u2 = __attribute__((ext_vector_type(2))) unsigned;
+        int at = 0;
+#pragma unroll
+        for (; at + 16 <= NB; at += 16) {
+            const u4 x = {w[at / 4], w[at / 4 + 1], w[at / 4 + 2], w[at / 4 + 3]};
+            __builtin_amdgcn_raw_buffer_store_b128(x, r, lofs + at, cofs, BUF_SC1);
+        }
+        if constexpr (NB % 16 >= 8) {
+            const u2 x = {w[(NB / 16) * 4], w[(NB / 16) * 4 + 1]};
+            __builtin_amdgcn_raw_buffer_store_b64(x, r, lofs + (NB / 16) * 16, cofs, BUF_SC1);
+        }
+        if constexpr (NB % 8 == 4) __builtin_amdgcn_raw_buffer_store_b32(w[NB / 4 - 1], r, lofs + NB - 4, cofs, BUF_SC1);
+    }
+}
+
 // O2: second-order upwind.  Each face carries the upwind cell's value
 // extrapolated linearly from that cell and its own upwind neighbour,
 // F = f + (f - f_up)/2 (F = f when that cell's upwind side is a boundary);
@@ -1234,15 +1321,14 @@ extern __shared__ __align__(16) unsigned char dvm_sweep_lds[];
 // first plane's F along z is staged into the second LDS plane with its f,
 // and the row-behind-the-face f that rebuilds F along y is prefetched for
 // the second row.
-template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false>
-__device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __restrict__ params,
-                                              const S* __restrict__ etab, const S* __restrict__ ghat,
-                                              const double* __restrict__ lanetab, const int* __restrict__ bricks,
-                                              S* __restrict__ xface, S* __restrict__ yface, S* __restrict__ zface,
-                                              S* __restrict__ spec, double* __restrict__ partial,
-                                              S* __restrict__ plane)
+// The work unit of a block of a per-diagonal launch: block ids are
+// regrouped so that each XCD gets a contiguous range of (brick, tile) units.
+struct WorkUnit {
+    int o, tile, I, J, K;
+};
+template <typename S>
+__device__ __forceinline__ WorkUnit diagonal_unit(const SweepArgs<S>& A, const int* __restrict__ bricks)
 {
-    const int lane = threadIdx.x;
     int bid = blockIdx.x;
     {
         const int nb = A.nblocks;
@@ -1251,17 +1337,36 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         const int start = xcd * per + (xcd < rem ? xcd : rem);
         bid = start + k;
     }
-    const int tile = bid % A.ntiles;
+    WorkUnit u;
+    u.tile = bid % A.ntiles;
     bid /= A.ntiles;
     const int bi = bid % A.brick_cnt;
-    const int o = A.oct_base + bid / A.brick_cnt;
-    const int I = bricks[4 * (A.brick_off + bi) + 0];
-    const int J = bricks[4 * (A.brick_off + bi) + 1];
-    const int K = bricks[4 * (A.brick_off + bi) + 2];
+    u.o = A.oct_base + bid / A.brick_cnt;
+    u.I = bricks[4 * (A.brick_off + bi) + 0];
+    u.J = bricks[4 * (A.brick_off + bi) + 1];
+    u.K = bricks[4 * (A.brick_off + bi) + 2];
+    return u;
+}
+
+// PT: type of the per-cell parameter record, the Gaussian factor tables and
+// the equilibrium evaluation (S, or double beside FP32 storage of f: the
+// equilibrium then enters the FP32 update rounded once).
+template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false, bool COH = false,
+          typename PT = S>
+__device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* __restrict__ params,
+                                              const PT* __restrict__ etab, const S* __restrict__ ghat,
+                                              const double* __restrict__ lanetab,
+                                              S* __restrict__ xface, S* __restrict__ yface, S* __restrict__ zface,
+                                              S* __restrict__ spec, double* __restrict__ partial,
+                                              S* __restrict__ plane, const WorkUnit u)
+{
+    const int lane = threadIdx.x;
+    const int o = u.o, tile = u.tile, I = u.I, J = u.J, K = u.K;
     const bool px = (o & 1) != 0, py = (o & 2) != 0, pz = (o & 4) != 0;
     const int slot = tile * 64 + lane;
     const int nx = A.nx, ny = A.ny, nz = A.nz, MT = A.MT;
-    constexpr unsigned SB = sizeof(S);
+    constexpr unsigned SB = sizeof(S), PB = sizeof(PT);
+    constexpr bool PD = sizeof(PT) > sizeof(S);  // parameters wider than f
     const size_t fstride = (size_t)A.slots * VL;
     const unsigned lofs = (unsigned)slot * VL * SB;
     // a face cell of this brick, as a 32-bit byte offset from the brick's face
@@ -1321,10 +1426,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         wd[v] = lt[LT_SHARED + LT_PER_V * v + 2];
         const int a = (int)lt[LT_SHARED + LT_PER_V * v + 3];
         xix[v] = (S)xd[v];
-        oa[v] = (unsigned)a * SB;
+        oa[v] = (unsigned)a * PB;
         oal[v] = (unsigned)(a + A.mx * (vb + A.my * vc)) * SB;
     }
-    const unsigned ob = (unsigned)(A.mx + vb) * SB, oc = (unsigned)(A.mx + A.my + vc) * SB;
+    const unsigned ob = (unsigned)(A.mx + vb) * PB, oc = (unsigned)(A.mx + A.my + vc) * PB;
     const S sgx = px ? (S)A.rdx : -(S)A.rdx;
     const double yz2 = xiy_d * xiy_d + xiz_d * xiz_d;
     const int sideX = px ? 0 : 1, sideY = py ? 2 : 3, sideZ = pz ? 4 : 5;
@@ -1338,59 +1443,54 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     if (kr0 > 0) {
         for (int jj = 0; jj < jend; ++jj)
             for (int ii = 0; ii < iend; ++ii) {
-                const S* src = zin + ((size_t)jj * nx + ii) * fstride;
+                S t[VL];
+                load_face<COH>(zin, (unsigned)(jj * nx + ii) * rowb, lofs, t);
 #pragma unroll
-                for (int v = 0; v < VL; ++v) lds(jj, ii, v) = ldb(src, lofs + v * SB);
+                for (int v = 0; v < VL; ++v) lds(jj, ii, v) = t[v];
                 if constexpr (O2) {
-                    const S* gsrc = zgin + ((size_t)jj * nx + ii) * fstride;
+                    load_face<COH>(zgin, (unsigned)(jj * nx + ii) * rowb, lofs, t);
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) ldz(jj, ii, v) = ldb(gsrc, lofs + v * SB);
+                    for (int v = 0; v < VL; ++v) ldz(jj, ii, v) = t[v];
                 }
             }
     }
 
     // ---- loads of the next cell, issued one cell ahead
-    S eb_n = (S)0, ec_n = (S)0, ex_n[VL], fx_n[VL], fy_n[VL];
+    PT eb_n = (PT)0, ec_n = (PT)0, ex_n[VL];
+    S fx_n[VL], fy_n[VL];
     // second order: F of the x / y faces; for the second row fy_n holds the
     // f of the row behind the y face (the same face value the first row took)
     S gx_n[VL], gy_n[VL];
 #pragma unroll
-    for (int v = 0; v < VL; ++v) ex_n[v] = fx_n[v] = fy_n[v] = gx_n[v] = gy_n[v] = (S)0;
+    for (int v = 0; v < VL; ++v) {
+        ex_n[v] = (PT)0;
+        fx_n[v] = fy_n[v] = gx_n[v] = gy_n[v] = (S)0;
+    }
     // the next cell's record is read one cell ahead as well: its info word
     // and 1/tau (which also bring the record's first cache lines into the
     // scalar cache for the rest of its loads)
-    S nu_n = (S)1;
+    PT nu_n = (PT)1;
     uint32_t info_n = 0;
     auto prefetch = [&](int ii, int jj, int kk) {
         const int cn = cell0 + ii * si + jj * sj + kk * sk;
-        const S* Pn = params + (size_t)cn * PSTRIDE;
+        const PT* Pn = params + (size_t)cn * PSTRIDE;
         nu_n = Pn[P_NU];
         info_n = reinterpret_cast<const uint32_t*>(Pn + P_INFO)[0];
-        const S* E = etab + (size_t)cn * MT;
+        const PT* E = etab + (size_t)cn * MT;
         eb_n = ldb(E, ob);
         ec_n = ldb(E, oc);
 #pragma unroll
         for (int v = 0; v < VL; ++v) ex_n[v] = ldb(E, oa[v]);
         if (ii == 0 && ir0 > 0) {
-            const S* src = fcell(xin, kk * ny + jj);
-#pragma unroll
-            for (int v = 0; v < VL; ++v) fx_n[v] = ldb(src, lofs + v * SB);
-            if constexpr (O2) {
-                const S* gsrc = fcell(xgin, kk * ny + jj);
-#pragma unroll
-                for (int v = 0; v < VL; ++v) gx_n[v] = ldb(gsrc, lofs + v * SB);
-            }
+            load_face<COH>(xin, (unsigned)(kk * ny + jj) * rowb, lofs, fx_n);
+            if constexpr (O2) load_face<COH>(xgin, (unsigned)(kk * ny + jj) * rowb, lofs, gx_n);
         }
         if ((jj == 0 || (O2 && jj == 1)) && jr0 > 0) {
-            const S* src = fcell(yin, kk * nx + ii);
-#pragma unroll
-            for (int v = 0; v < VL; ++v) fy_n[v] = ldb(src, lofs + v * SB);
+            load_face<COH>(yin, (unsigned)(kk * nx + ii) * rowb, lofs, fy_n);
         }
         if constexpr (O2) {
             if (jj == 0 && jr0 > 0) {
-                const S* gsrc = fcell(ygin, kk * nx + ii);
-#pragma unroll
-                for (int v = 0; v < VL; ++v) gy_n[v] = ldb(gsrc, lofs + v * SB);
+                load_face<COH>(ygin, (unsigned)(kk * nx + ii) * rowb, lofs, gy_n);
             }
         }
     };
@@ -1418,45 +1518,29 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
     auto flush_faces = [&]() {
         if (pcell < 0) return;
         if (pii == BX - 1 && wx) {
-            S* dst = fcell(xout, pkk * ny + pjj);
-#pragma unroll
-            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            store_face<COH>(xout, (unsigned)(pkk * ny + pjj) * rowb, lofs, prev);
             if constexpr (O2) {
-                S* g = fcell(xgout, pkk * ny + pjj);
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, prevF[v]);
+                store_face<COH>(xgout, (unsigned)(pkk * ny + pjj) * rowb, lofs, prevF);
             }
         }
         if (pjj == BY - 1 && wy) {
-            S* dst = fcell(yout, pkk * nx + pii);
-#pragma unroll
-            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            store_face<COH>(yout, (unsigned)(pkk * nx + pii) * rowb, lofs, prev);
             if constexpr (O2) {
-                S* g = fcell(ygout, pkk * nx + pii);
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFy[v]);
+                store_face<COH>(ygout, (unsigned)(pkk * nx + pii) * rowb, lofs, pFy);
             }
         }
         if (pkk == A.bz - 1 && wz) {
-            S* dst = fcell(zout, pjj * nx + pii);
-#pragma unroll
-            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            store_face<COH>(zout, (unsigned)(pjj * nx + pii) * rowb, lofs, prev);
             if constexpr (O2) {
-                S* g = fcell(zgout, pjj * nx + pii);
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFz[v]);
+                store_face<COH>(zgout, (unsigned)(pjj * nx + pii) * rowb, lofs, pFz);
             }
         }
         if (sbuf != nullptr && !pz && kr0 + pkk == nz - 1) {
             const int i = px ? ir0 + pii : nx - 1 - (ir0 + pii);
             const int j = py ? jr0 + pjj : ny - 1 - (jr0 + pjj);
-            S* dst = sbuf + ((size_t)j * nx + i) * fstride;
-#pragma unroll
-            for (int v = 0; v < VL; ++v) stb_nt(dst, lofs + v * SB, prev[v]);
+            store_face<false>(sbuf + ((size_t)j * nx + i) * fstride, 0u, lofs, prev);
             if constexpr (O2) {
-                S* g = sgbuf + ((size_t)j * nx + i) * fstride;
-#pragma unroll
-                for (int v = 0; v < VL; ++v) stb_nt(g, lofs + v * SB, pFz[v]);
+                store_face<false>(sgbuf + ((size_t)j * nx + i) * fstride, 0u, lofs, pFz);
             }
         }
     };
@@ -1473,9 +1557,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         flush_partial();
     };
     for (int n = 0; n < ncell; ++n) {
-        const S eb = eb_n, ec = ec_n, nu = nu_n;
+        const PT eb = eb_n, ec = ec_n, nu = nu_n;
         const uint32_t info = info_n;
-        S ex[VL], fxp[VL], fyp[VL], gxp[VL], gyp[VL];
+        PT ex[VL];
+        S fxp[VL], fyp[VL], gxp[VL], gyp[VL];
 #pragma unroll
         for (int v = 0; v < VL; ++v) {
             ex[v] = ex_n[v];
@@ -1508,7 +1593,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
         }
 
         const int cell = cell0 + ii * si + jj * sj + kk * sk;
-        const S* P = params + (size_t)cell * PSTRIDE;
+        const PT* P = params + (size_t)cell * PSTRIDE;
         if (!(info & SOLID_BIT)) {
             S fx[VL], fy[VL], fz[VL];
             S ux[VL], uy[VL], uz[VL];
@@ -1528,7 +1613,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                         for (int v = 0; v < VL; ++v) fx[v] = ii > 0 ? prev[v] : fxp[v];
                     }
                 } else {
-                    const S rf = P[P_RHO_SIDE + sideX];
+                    const S rf = (S)P[P_RHO_SIDE + sideX];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
                     for (int v = 0; v < VL; ++v) fx[v] = rf * ldb(g, oal[v]);
@@ -1567,7 +1652,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                         for (int v = 0; v < VL; ++v) fy[v] = fyp[v];
                     }
                 } else {
-                    const S rf = P[P_RHO_SIDE + sideY];
+                    const S rf = (S)P[P_RHO_SIDE + sideY];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
                     for (int v = 0; v < VL; ++v) fy[v] = rf * ldb(g, oal[v]);
@@ -1622,7 +1707,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 #pragma unroll
                     for (int v = 0; v < VL; ++v) fz[v] = ldb(src, lofs + v * SB);
                 } else {
-                    const S rf = P[P_RHO_SIDE + sideZ];
+                    const S rf = (S)P[P_RHO_SIDE + sideZ];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
                     for (int v = 0; v < VL; ++v) fz[v] = rf * ldb(g, oal[v]);
@@ -1638,25 +1723,25 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
                 if (n + 1 < ncell) prefetch(ni, nj, nk);
             }
 
-            const S Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
-            const S L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
-            const S qx = P[P_QX], qy = P[P_QY], qz = P[P_QZ], tT = P[P_TWO_T];
-            const S gyz = eb * ec;
-            const S cy = xiy - Uy, cz = xiz - Uz;
-            const S cyz2 = cy * cy + cz * cz;
-            const S Lyz = L0 + L2 * cy + L3 * cz;
-            const S Qyz = qy * cy + qz * cz;
+            const PT Ux = P[P_UX], Uy = P[P_UY], Uz = P[P_UZ];
+            const PT L0 = P[P_L0], L1 = P[P_L1], L2 = P[P_L2], L3 = P[P_L3], L4 = P[P_L4];
+            const PT qx = P[P_QX], qy = P[P_QY], qz = P[P_QZ], tT = P[P_TWO_T];
+            const PT gyz = eb * ec;
+            const PT cy = (PD ? (PT)xiy_d : (PT)xiy) - Uy, cz = (PD ? (PT)xiz_d : (PT)xiz) - Uz;
+            const PT cyz2 = cy * cy + cz * cz;
+            const PT Lyz = L0 + L2 * cy + L3 * cz;
+            const PT Qyz = qy * cy + qz * cz;
             // ES-BGK: qx, qy, qz hold A_xy, A_xz, A_yz
-            const S Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
+            const PT Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
             // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
             // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
             S ayc = ay, azc = az, sx = sgx;
             if constexpr (NU) {
-                sx = sgx * P[P_IDX];
-                ayc = ay * P[P_IDY];
-                azc = az * P[P_IDZ];
+                sx = sgx * (S)P[P_IDX];
+                ayc = ay * (S)P[P_IDY];
+                azc = az * (S)P[P_IDZ];
             }
-            const S aynu = ayc + azc + nu;
+            const S aynu = ayc + azc + (S)nu;
             double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
             double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // second order: sum w (F_d - f)
             S Fy[VL], Fz[VL];
@@ -1665,26 +1750,26 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
             const S ayk = ayc * ky, azk = azc * kz;
 #pragma unroll
             for (int v = 0; v < VL; ++v) {
-                const S cx = xix[v] - Ux;
-                const S c2 = cx * cx + cyz2;
-                S nfs;
+                const PT cx = (PD ? (PT)xd[v] : (PT)xix[v]) - Ux;
+                const PT c2 = cx * cx + cyz2;
+                PT nfs;
                 if constexpr (ES) {
-                    const S arg = -(cx * Bes + Ces);
-                    S cross;
-                    if constexpr (sizeof(S) == 8)
+                    const PT arg = -(cx * Bes + Ces);
+                    PT cross;
+                    if constexpr (sizeof(PT) == 8)
                         cross = exp(arg);
                     else
                         cross = __expf(arg);
                     nfs = gyz * ex[v] * (Lyz + L1 * cx + L4 * c2) * cross;
                 } else {
-                    const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
+                    const PT poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (PT)5);
                     nfs = gyz * ex[v] * poly;
                 }
                 const S axv = xix[v] * sx;
-                const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + nfs;
+                const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + (S)nfs;
                 S f;
                 if constexpr (O2) {
-                    f = num * fast_rcp(axv * kx + ayk + azk + nu);
+                    f = num * fast_rcp(axv * kx + ayk + azk + (S)nu);
                     const S dx = ixf ? (S)0.5 * (f - ux[v]) : (S)0;
                     const S dy = iyf ? (S)0.5 * (f - uy[v]) : (S)0;
                     const S dz = izf ? (S)0.5 * (f - uz[v]) : (S)0;
@@ -1781,13 +1866,98 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const S* __
 // NU: non-uniform mesh (the upwind coefficients take the cell's own sizes).
 // Occupancy with 4 per lane: 4 waves per SIMD (128 registers) in FP32, 3
 // (168) in FP64, reached without spills inside the cell loop.
-template <typename S, int VL, int BX, int BY, bool NU>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VL == 4 ? (sizeof(S) == 4 ? 4 : 3) : 1)))
+// PT: see sweep_body_pf (the parameter record and tables are of type PT).
+template <typename S, int VL, int BX, int BY, bool NU, typename PT = S>
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(VL == 4 ? (sizeof(S) == 4 && sizeof(PT) == 4 ? 4 : 3) : 1)))
 void sweep_kernel_pf(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
-    sweep_body_pf<S, VL, BX, BY, NU>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface, A.yface, A.zface,
-                                 A.spec, A.partial, plane);
+    sweep_body_pf<S, VL, BX, BY, NU, false, false, false, PT>(
+        A, reinterpret_cast<const PT*>(A.params), reinterpret_cast<const PT*>(A.etab), A.ghat, A.lanetab, A.xface,
+        A.yface, A.zface, A.spec, A.partial, plane, diagonal_unit(A, A.bricks));
+}
+
+// Spin until the three upwind bricks of a work unit (those that exist) have
+// published this launch's epoch.  The wait is bounded: it gives up after
+// DYN_WAIT_TICKS of the 100 MHz real-time counter (half a second), or at
+// once when another wave has already given up (the launch is then reported
+// as failed and its iterate discarded, so no wave needs to wait any more).
+constexpr unsigned long long DYN_WAIT_TICKS = 50000000ull;
+__device__ __forceinline__ bool wait_upwind(const unsigned* fx, const unsigned* fy, const unsigned* fz,
+                                            unsigned epoch, const int* errflag)
+{
+    unsigned long long t0 = 0;
+    for (unsigned n = 0;; ++n) {
+        const unsigned a = fx ? __hip_atomic_load(fx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : epoch;
+        const unsigned b = fy ? __hip_atomic_load(fy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : epoch;
+        const unsigned c = fz ? __hip_atomic_load(fz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : epoch;
+        if (a == epoch && b == epoch && c == epoch) return true;
+        const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+        if (n == 0) t0 = now;
+        if (now - t0 > DYN_WAIT_TICKS) return false;
+        if (__hip_atomic_load(errflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Dependency-driven form of the same sweep: one launch covers every brick
+// diagonal of the octants in A (all of one velocity group, or one specular
+// phase).  Each wave takes work units from a device-wide counter in the
+// order (diagonal, brick, octant, tile) -- every unit's upwind bricks come
+// earlier in that order and were taken by waves that are already running,
+// so every wait ends -- waits until its three upwind bricks of the same
+// octant and tile have published this launch's epoch, sweeps the brick,
+// waits for its own stores and publishes.  Faces move through
+// device-coherent loads and stores (load_vl / store_vl with COH), the ready
+// flags through relaxed device-scope atomics; the counter is never reset:
+// the host passes the value it held before the launch (every wave ends with
+// one failed take, so a launch of G waves advances it by units + G).
+template <typename S, int VL, int BX, int BY, bool NU, typename PT = S>
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(VL == 4 ? (sizeof(S) == 4 && sizeof(PT) == 4 ? 4 : 3) : 1)))
+void sweep_kernel_dyn(const SweepArgs<S> Aarg)
+{
+    S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
+    for (;;) {
+        // the arguments are read afresh from the kernel-argument segment in
+        // every work unit (through an opaque copy of its address): hoisted
+        // out of the loop they would stay live in registers across the whole
+        // brick and spill
+        using KArgs = const __attribute__((address_space(4))) SweepArgs<S>;
+        KArgs* Ap = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(Ap));
+        const SweepArgs<S>& A = *(const SweepArgs<S>*)Ap;
+        const int per_brick = A.noct * A.ntiles;
+        const int nbx = A.nbx, nby = A.nby, nbz = A.nbz;
+        const size_t chain = (size_t)nbx * nby * nbz;  // flags of one (octant, tile)
+        unsigned long long t = 0;
+        if (threadIdx.x == 0) t = __hip_atomic_fetch_add(A.head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)t);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(t >> 32));
+        const long long item = (long long)((((unsigned long long)hi << 32) | lo) - A.qbase);
+        if (item >= (long long)A.nitems) break;
+        const int b = (int)(item / per_brick), r = (int)(item % per_brick);
+        WorkUnit u;
+        u.o = A.oct_base + r / A.ntiles;
+        u.tile = r % A.ntiles;
+        u.I = A.bricks[4 * b + 0];
+        u.J = A.bricks[4 * b + 1];
+        u.K = A.bricks[4 * b + 2];
+        unsigned* f = A.ready + ((size_t)u.o * A.ntiles + u.tile) * chain;
+        const size_t self = ((size_t)u.K * nby + u.J) * nbx + u.I;
+        if (!wait_upwind(u.I > 0 ? f + self - 1 : nullptr, u.J > 0 ? f + self - nbx : nullptr,
+                         u.K > 0 ? f + self - (size_t)nbx * nby : nullptr, A.epoch, A.errflag)) {
+            if (threadIdx.x == 0) atomicOr(A.errflag, 8);
+        }
+        asm volatile("" ::: "memory");
+        sweep_body_pf<S, VL, BX, BY, NU, false, false, true, PT>(
+            A, reinterpret_cast<const PT*>(A.params), reinterpret_cast<const PT*>(A.etab), A.ghat, A.lanetab, A.xface,
+            A.yface, A.zface, A.spec, A.partial, plane, u);
+        // the brick's face stores are complete before its flag says so
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __hip_atomic_store(f + self, A.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <typename S, int VL, int BX, int BY, bool NU>
@@ -1806,8 +1976,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VL == 4 && !
 void sweep_kernel_pfx(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
-    sweep_body_pf<S, VL, BX, BY, false, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.bricks, A.xface,
-                                                A.yface, A.zface, A.spec, A.partial, plane);
+    sweep_body_pf<S, VL, BX, BY, false, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.xface, A.yface, A.zface,
+                                                A.spec, A.partial, plane, diagonal_unit(A, A.bricks));
 }
 
 // second-order upwind and/or ES-BGK (uniform meshes, plain body)
@@ -1850,15 +2020,39 @@ bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, i
     return false;
 }
 
-template <typename T, int V, int BXX, int BYY, bool NU>
+template <typename T, int V, int BXX, int BYY, bool NU, typename PT = T>
 hipError_t launch_sweep_t(int pipelined, const void* args, hipStream_t st)
 {
     const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
     const size_t lds = (size_t)BYY * BXX * V * 64 * sizeof(T);
+    if (pipelined == 2) {
+        // as many waves as stay resident (more would only wait for a CU)
+        static thread_local int resident = 0, cached_dev = -1;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (resident == 0 || cached_dev != dev) {
+            int per_cu = 0, cus = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_kernel_dyn<T, V, BXX, BYY, NU, PT>, 64,
+                                                             lds);
+            if (e != hipSuccess) return e;
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return e;
+            resident = std::max(1, per_cu) * std::max(1, cus);
+            cached_dev = dev;
+        }
+        const int grid = std::min(resident, a.nitems);
+        sweep_kernel_dyn<T, V, BXX, BYY, NU, PT><<<grid, 64, lds, st>>>(a);
+        e = hipGetLastError();
+        if (e == hipSuccess) *a.launched = grid;
+        return e;
+    }
     if (pipelined)
-        sweep_kernel_pf<T, V, BXX, BYY, NU><<<a.nblocks, 64, lds, st>>>(a);
-    else
+        sweep_kernel_pf<T, V, BXX, BYY, NU, PT><<<a.nblocks, 64, lds, st>>>(a);
+    else if constexpr (sizeof(PT) == sizeof(T))
         sweep_kernel<T, V, BXX, BYY, NU><<<a.nblocks, 64, lds, st>>>(a);
+    else
+        return hipErrorInvalidValue;  // the plain body has no wider parameters
     return hipGetLastError();
 }
 
@@ -1886,9 +2080,19 @@ hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, const void* args
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, int order2,
-                        int esbgk, const void* args, hipStream_t st)
+bool sweep_wide_params_available(int prec, int vl, int bx, int by, int nonuniform, int order2, int esbgk)
 {
+    return prec == 1 && vl == 4 && bx == 4 && by == 2 && !nonuniform && !order2 && !esbgk;
+}
+
+hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int nonuniform, int order2,
+                        int esbgk, int wide_params, const void* args, hipStream_t st)
+{
+    if (wide_params) {
+        if (!sweep_wide_params_available(prec, vl, bx, by, nonuniform, order2, esbgk) || pipelined == 0)
+            return hipErrorInvalidValue;
+        return launch_sweep_t<float, 4, 4, 2, false, double>(pipelined, args, st);
+    }
     if (order2 || esbgk) {
         if (nonuniform) return hipErrorInvalidValue;
 #define X(T, V, BXX, BYY)                                                     \

@@ -67,7 +67,7 @@ struct dvm_ctx {
     double dx[3];
     int hsplit[3];  // number of nodes with xi < 0 along each axis
     int VL = 2, BX = 4, BY = 4, BZ = 8;
-    int PF = 1;  // software-pipelined sweep body
+    int PF = 1;  // sweep body: 0 plain, 1 software-pipelined, 2 pipelined and dependency-driven
     // schedule requested with dvm_set_schedule (0: the library's choice);
     // req_ok is false while the request names a kernel shape that is not
     // built for the current precision, mesh kind, order and model
@@ -75,6 +75,10 @@ struct dvm_ctx {
     bool req_ok = true;
     bool fits32 = true;  // the 32-bit face offsets of the schedule fit
     int order = 1;  // spatial order of the upwind scheme (1 or 2)
+    // FP32 storage with the parameter record, Gaussian tables and the
+    // equilibrium evaluation in FP64 (dvm_set_parameter_precision(ctx, 64))
+    bool wide = false;
+    int pprec() const { return wide ? DVM_F64 : prec; }  // type of params and tables
     int model = 0;  // 0: Shakhov, 1: ES-BGK
     // velocity nodes and weights per axis (empty: uniform, trapezoid)
     std::vector<double> vnode[3], vweight[3];
@@ -101,10 +105,15 @@ struct dvm_ctx {
     struct {
         size_t axes, spacing, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
             partial, acc, xface, yface, zface, spec, xg, yg, zg, specg, stress, blockmass, respart, out, flag,
-            end;
+            ready, head, end;
     } off;
     size_t Ssz = 8;
     int nbF = 0;  // blocks of the per-cell kernels (256 threads)
+
+    // dependency-driven sweep: epoch of the last launch (ready flags hold
+    // it) and the work-unit counter's value before the next launch
+    unsigned epoch = 0;
+    unsigned long long qbase = 0;
 
     // state
     int cur = 0;
@@ -199,12 +208,14 @@ void derive_schedule(dvm_ctx* c)
         const int rv = c->req_vl ? c->req_vl : vl;
         const int rbx = c->req_bx ? c->req_bx : (c->req_vl ? default_bx(rv) : bx);
         const int rby = c->req_by ? c->req_by : (c->req_vl ? default_by(rv) : by);
-        if (sweep_variant_available(c->prec, rv, rbx, rby, c->nonuniform, o2, es)) {
+        // the dependency-driven launch exists for the first-order Shakhov sweep
+        const bool body_ok = c->req_body != 3 || (!o2 && !es);
+        if (body_ok && sweep_variant_available(c->prec, rv, rbx, rby, c->nonuniform, o2, es)) {
             vl = rv;
             bx = rbx;
             by = rby;
             if (c->req_bz) bz = c->req_bz;
-            if (c->req_body) pf = c->req_body == 2;
+            if (c->req_body) pf = c->req_body - 1;
         } else {
             c->req_ok = false;
         }
@@ -311,8 +322,9 @@ void layout(dvm_ctx* c)
     c->off.W = take(sizeof(double) * 2 * 5 * N);
     c->off.q = take(sizeof(double) * 2 * 3 * N);
     c->off.rw = take(sizeof(double) * 2 * 6 * N);
-    c->off.params = take(S * PSTRIDE * N);
-    c->off.etab = take(S * (size_t)(c->vg.m[0] + c->vg.m[1] + c->vg.m[2]) * N);
+    const size_t SP = c->wide ? sizeof(double) : S;  // parameter record and tables
+    c->off.params = take(SP * PSTRIDE * N);
+    c->off.etab = take(SP * (size_t)(c->vg.m[0] + c->vg.m[1] + c->vg.m[2]) * N);
     c->off.partial = take(sizeof(double) * PREC * 8 * (size_t)c->gtiles * N);
     c->off.acc = take(c->ngroups > 1 ? sizeof(double) * PREC * 8 * N : 0);
     c->off.xface = take(S * 8 * 2 * (size_t)c->g.nz * c->g.ny * fst);
@@ -331,6 +343,8 @@ void layout(dvm_ctx* c)
     c->off.respart = take(sizeof(double) * 10 * c->nbF);
     c->off.out = take(sizeof(double) * 8);
     c->off.flag = take(sizeof(int) * 4);
+    c->off.ready = take(c->PF == 2 ? sizeof(unsigned) * 8 * (size_t)c->gtiles * c->nbx * c->nby * c->nbz : 0);
+    c->off.head = take(c->PF == 2 ? sizeof(unsigned long long) : 0);
     c->off.end = o;
 }
 
@@ -508,7 +522,7 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                                 c->ws + c->off.params, c->ws + c->off.etab, c->prec, flag, st));
     else
         HIPCHK(launch_params(C, D, W + cur * 5 * N, q + cur * 3 * N, rw + cur * 6 * N, c->ws + c->off.params,
-                             c->ws + c->off.etab, c->prec, flag, st));
+                             c->ws + c->off.etab, c->pprec(), flag, st));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[1], st));
 
     // sweep: one launch per brick diagonal; with a specular plane the
@@ -517,12 +531,17 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
     // group's moments folded into the accumulator before the next reuses the
     // faces and partials.
     const int phases = c->spec_on ? 2 : 1;
+    const bool dyn = c->PF == 2;
+    const int nbricks = (int)(c->bricks.size() / 4);
     for (int grp = 0; grp < c->ngroups; ++grp) {
     const int t0 = c->gt0[grp], gnt = c->gt0[grp + 1] - t0;
     for (int ph = 0; ph < phases; ++ph) {
-        for (int T = 0; T < c->ndiag; ++T) {
-            const int cnt = c->diag_cnt[T];
+        // per-diagonal launches, or one dependency-driven launch over all
+        // bricks (diagonal 0 standing for all of them)
+        for (int T = 0; T < (dyn ? 1 : c->ndiag); ++T) {
+            const int cnt = dyn ? nbricks : c->diag_cnt[T];
             if (cnt == 0) continue;
+            int launched = 0;
             auto fill = [&](auto& a) {
                 using S = typename std::remove_pointer<decltype(a.xface)>::type;
                 a.params = c->P<S>(c->off.params);
@@ -546,24 +565,38 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.rdx = c->nonuniform ? 1.0 : 1.0 / c->dx[0];
                 a.nbx = c->nbx; a.nby = c->nby; a.nbz = c->nbz; a.bz = c->BZ;
                 a.ntiles = gnt; a.slots = gnt * 64; a.lstride = c->lstride;
-                a.brick_off = c->diag_off[T]; a.brick_cnt = cnt;
+                a.brick_off = dyn ? 0 : c->diag_off[T]; a.brick_cnt = cnt;
                 a.oct_base = c->spec_on ? 4 * ph : 0;
                 a.noct = c->spec_on ? 4 : 8;
                 a.spec_on = c->spec_on ? 1 : 0;
                 a.has_solid = c->nfluid < c->N ? 1 : 0;
                 a.nblocks = a.noct * cnt * gnt;
+                a.ready = dyn ? c->P<unsigned>(c->off.ready) : nullptr;
+                a.head = dyn ? c->P<unsigned long long>(c->off.head) : nullptr;
+                a.qbase = c->qbase;
+                a.epoch = dyn ? c->epoch + 1 : 0;
+                a.nitems = a.nblocks;
+                a.errflag = flag;
+                a.launched = &launched;
             };
             hipError_t e;
             if (c->prec == DVM_F64) {
                 SweepArgs<double> a;
                 fill(a);
-                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, &a, st);
+                e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, 0, &a,
+                                 st);
             } else {
                 SweepArgs<float> a;
                 fill(a);
-                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, &a, st);
+                e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, c->wide,
+                                 &a, st);
             }
             if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+            if (dyn) {
+                // every started wave ends with one failed take of the counter
+                c->epoch += 1;
+                c->qbase += (unsigned long long)cnt * (c->spec_on ? 4 : 8) * gnt + (unsigned long long)launched;
+            }
         }
     }
     if (c->ngroups > 1)
@@ -633,9 +666,9 @@ dvm_status upload_initial(dvm_ctx* c, const std::vector<double>& Wh)
     const Consts C = make_consts(c);
     const DevPtrs D = make_ptrs(c);
     HIPCHK(hipMemsetAsync(rw, 0, sizeof(double) * 6 * N, st));
-    HIPCHK(launch_params(C, D, W, q, rw, c->ws + c->off.params, c->ws + c->off.etab, c->prec, flag, st));
+    HIPCHK(launch_params(C, D, W, q, rw, c->ws + c->off.params, c->ws + c->off.etab, c->pprec(), flag, st));
     HIPCHK(launch_wall_init(C, D, c->ws + c->off.params, c->ws + c->off.etab, c->P<double>(c->off.ghat64),
-                            c->P<double>(c->off.gout), rw, c->prec, st));
+                            c->P<double>(c->off.gout), rw, c->pprec(), st));
     int hflag = 0;
     HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -840,12 +873,25 @@ dvm_status dvm_set_order(dvm_ctx* c, int order)
     return DVM_OK;
 }
 
+dvm_status dvm_set_parameter_precision(dvm_ctx* c, int bits)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (c->bound) return fail(DVM_ERR_STATE, "the parameter precision must be set before binding the workspace");
+    if (bits != 32 && bits != 64) return fail(DVM_ERR_ARG, "bits must be 32 or 64 (got %d)", bits);
+    if (c->prec == DVM_F64) {
+        if (bits == 32) return fail(DVM_ERR_ARG, "an FP64 context keeps its parameters in FP64");
+        return DVM_OK;
+    }
+    c->wide = bits == 64;
+    return DVM_OK;
+}
+
 dvm_status dvm_set_schedule(dvm_ctx* c, int vel_per_lane, int bx, int by, int bz, int body)
 {
     if (check_ctx(c)) return DVM_ERR_ARG;
     if (c->bound) return fail(DVM_ERR_STATE, "the schedule must be set before binding the workspace");
     if (vel_per_lane < 0 || vel_per_lane > 8 || bx < 0 || bx > 8 || by < 0 || by > 8 || bz < 0 || bz > 256 ||
-        body < 0 || body > 2)
+        body < 0 || body > 3)
         return fail(DVM_ERR_ARG, "schedule out of range (vel_per_lane %d, brick %dx%dx%d, body %d)", vel_per_lane,
                     bx, by, bz, body);
     const int old[5] = {c->req_vl, c->req_bx, c->req_by, c->req_bz, c->req_body};
@@ -862,8 +908,8 @@ dvm_status dvm_set_schedule(dvm_ctx* c, int vel_per_lane, int bx, int by, int bz
         c->req_bz = old[3];
         c->req_body = old[4];
         derive_schedule(c);
-        return fail(DVM_ERR_ARG, "no sweep kernel with %d velocities per lane and %dx%d bricks is built for this "
-                    "precision, mesh kind, order and model", vel_per_lane, bx, by);
+        return fail(DVM_ERR_ARG, "no sweep kernel with %d velocities per lane, %dx%d bricks and body %d is built for "
+                    "this precision, mesh kind, order and model", vel_per_lane, bx, by, body);
     }
     return DVM_OK;
 }
@@ -911,6 +957,10 @@ dvm_status check_bindable(dvm_ctx* c)
     if (!c->fits32)
         return fail(DVM_ERR_ARG, "a face row of this grid and velocity set exceeds the 32-bit offsets of the "
                     "sweep even with one-cell brick columns: use more velocity groups");
+    if (c->wide && (c->PF == 0 || !sweep_wide_params_available(c->prec, c->VL, c->BX, c->BY, c->nonuniform,
+                                                                c->order == 2, c->model == 1)))
+        return fail(DVM_ERR_ARG, "FP64 parameters beside FP32 storage are built for the first-order Shakhov sweep "
+                    "on a uniform mesh with 4 velocities per lane, 4x2 bricks and a pipelined body only");
     layout(c);
     return DVM_OK;
 }
@@ -968,6 +1018,10 @@ dvm_status bind_impl(dvm_ctx* c, void* ptr, size_t bytes)
     HIPCHK(hipMemcpyAsync(c->ws + c->off.kstate, ks.data(), sizeof(double) * ks.size(), hipMemcpyHostToDevice, st));
     // partial slots of tiles that an octant does not have stay zero
     HIPCHK(hipMemsetAsync(c->ws + c->off.partial, 0, c->off.xface - c->off.partial, st));
+    // dependency-driven sweep: no brick ready, counter at zero
+    if (c->PF == 2) HIPCHK(hipMemsetAsync(c->ws + c->off.ready, 0, c->off.end - c->off.ready, st));
+    c->epoch = 0;
+    c->qbase = 0;
     const Consts C = make_consts(c);
     const DevPtrs D = make_ptrs(c);
     HIPCHK(launch_emission(C, D, c->P<double>(c->off.kstate), NKIND, c->ws + c->off.ghat,
@@ -1091,6 +1145,9 @@ dvm_status dvm_iterate(dvm_ctx* c, int max_iters, double tol, int* iters_done, d
         const dvm_status st = run_iteration(c, hout);
         if (st != DVM_OK) return st;
         const int flag = (int)hout[6];
+        if (flag & 8)
+            return fail(DVM_ERR_DEVICE, "iteration %d: a sweep work unit waited too long for its upwind bricks; "
+                        "the iterate is not updated", it + 1);
         bool finite = true;
         for (int v = 0; v < 5; ++v) finite = finite && isfinite(hout[v]);
         if (flag || !finite) {
@@ -1209,10 +1266,11 @@ dvm_status dvm_get_info(dvm_ctx* c, dvm_info* info)
     info->tiles_per_octant = c->ntiles;
     int launches = 0;
     for (int T = 0; T < c->ndiag; ++T) launches += c->diag_cnt[T] > 0;
-    info->sweep_launches = launches * (c->spec_on ? 2 : 1) * c->ngroups;
+    info->sweep_launches = (c->PF == 2 ? 1 : launches) * (c->spec_on ? 2 : 1) * c->ngroups;
     info->workspace_bytes = c->off.end;
     info->pipelined = c->PF;
     info->velocity_groups = c->ngroups;
+    info->parameter_bits = c->pprec() == DVM_F64 ? 64 : 32;
     return DVM_OK;
 }
 

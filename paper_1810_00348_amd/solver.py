@@ -26,16 +26,20 @@ class Solver:
     def __init__(self, case: Case, precision: str = "f64", device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, velocity_groups: Optional[int] = None,
                  memory_fraction: float = 0.9, schedule: Optional[dict] = None,
-                 static_workspace: bool = False):
+                 static_workspace: bool = False, parameter_bits: int = 0):
         """velocity_groups: sweep the velocity set in that many parts per
         iteration (None: the fewest parts whose workspace fits
         memory_fraction of the device's free memory).  schedule: a sweep
         kernel shape in place of the library's choice, any of the keys vl
         (velocities per lane), bx, by, bz (brick cells) and pipelined
-        (True / False); see dvm_set_schedule.  static_workspace: bind the
+        (True / False, or "dyn": the pipelined body in one dependency-driven
+        launch); see dvm_set_schedule.  static_workspace: bind the
         library's static device workspace (no allocation; small contexts
         only, one context per device at a time; see
-        dvm_bind_static_workspace) instead of a torch buffer."""
+        dvm_bind_static_workspace) instead of a torch buffer.
+        parameter_bits: 64 with precision "f32" keeps the per-cell
+        parameters, Gaussian tables and the equilibrium evaluation in FP64
+        (see dvm_set_parameter_precision); 0 keeps the default."""
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
         self.case = case
@@ -79,14 +83,16 @@ class Solver:
             L.check(lib.dvm_set_model(h, 1))
         if case.order != 1:
             L.check(lib.dvm_set_order(h, int(case.order)))
+        if parameter_bits:
+            L.check(lib.dvm_set_parameter_precision(h, int(parameter_bits)))
         if schedule:
             unknown = set(schedule) - {"vl", "bx", "by", "bz", "pipelined"}
             if unknown:
                 raise ValueError(f"unknown schedule keys {sorted(unknown)}")
             body = schedule.get("pipelined")
+            code = 0 if body is None else (3 if body == "dyn" else 2 if body else 1)
             L.check(lib.dvm_set_schedule(h, int(schedule.get("vl", 0)), int(schedule.get("bx", 0)),
-                                         int(schedule.get("by", 0)), int(schedule.get("bz", 0)),
-                                         0 if body is None else (2 if body else 1)))
+                                         int(schedule.get("by", 0)), int(schedule.get("bz", 0)), code))
         nbytes = C.c_size_t()
         groups = 1 if velocity_groups is None else int(velocity_groups)
         L.check(lib.dvm_set_velocity_groups(h, groups))
@@ -227,8 +233,8 @@ class Solver:
                 "nvel": inf.nvel, "precision": inf.precision, "brick": list(inf.brick),
                 "vel_per_lane": inf.vel_per_lane, "tiles_per_octant": inf.tiles_per_octant,
                 "sweep_launches": inf.sweep_launches, "workspace_bytes": inf.workspace_bytes,
-                "sweep_kernel": "sweep_kernel_pf" if inf.pipelined else "sweep_kernel",
-                "velocity_groups": inf.velocity_groups}
+                "sweep_kernel": ("sweep_kernel", "sweep_kernel_pf", "sweep_kernel_dyn")[inf.pipelined],
+                "velocity_groups": inf.velocity_groups, "parameter_bits": inf.parameter_bits}
 
     def set_timing(self, enable: bool = True):
         L.check(L.lib().dvm_set_timing(self._h, int(enable)))

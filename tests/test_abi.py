@@ -312,7 +312,7 @@ def test_schedule_requests(L):
     assert lib.dvm_get_info(h, C.byref(info)) == 0
     assert (info.vel_per_lane, *info.brick, info.pipelined) == (2, 4, 2, 7, 0)
     # out of range
-    for args in ((9, 0, 0, 0, 0), (0, 0, 0, 0, 3), (0, -1, 0, 0, 0)):
+    for args in ((9, 0, 0, 0, 0), (0, 0, 0, 0, 4), (0, -1, 0, 0, 0)):
         assert lib.dvm_set_schedule(h, *args) == -1
     # all zero: the library's choice again
     assert lib.dvm_set_schedule(h, 0, 0, 0, 0, 0) == 0
@@ -376,4 +376,39 @@ def test_static_workspace_size_limit(L):
     msg = lib.dvm_last_error()
     assert b"static workspace" in msg and str(64 << 20).encode() in msg
     assert lib.dvm_init_uniform(h, 1.0, (C.c_double * 3)(0, 0, 0), 1.0) == -2  # still unbound
+    lib.dvm_destroy(h)
+
+
+def test_dependency_driven_schedule_and_parameter_precision(L):
+    """Body 3 (one dependency-driven launch) exists for the first-order
+    Shakhov sweep only; FP64 parameters beside FP32 storage for the 4-per-lane
+    4x2 pipelined shape only (host-only checks)."""
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    info = L.Info()
+    h = _ctx(L, cases.config("c2"), 0)
+    assert lib.dvm_set_schedule(h, 0, 0, 0, 0, 3) == 0
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert info.pipelined == 2 and info.sweep_launches == 1 and info.parameter_bits == 64
+    assert lib.dvm_set_order(h, 2) == 0
+    # the request has no second-order kernel: binding refuses
+    assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 1 << 40) == -1
+    assert lib.dvm_set_parameter_precision(h, 32) == -1          # FP64 context
+    assert lib.dvm_set_parameter_precision(h, 64) == 0
+    lib.dvm_destroy(h)
+    h = _ctx(L, cases.config("c3"), 1)
+    assert lib.dvm_set_parameter_precision(h, 48) == -1
+    assert lib.dvm_set_parameter_precision(h, 64) == 0
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    assert info.parameter_bits == 64 and info.vel_per_lane == 4 and tuple(info.brick[:2]) == (4, 2)
+    n = C.c_size_t()
+    assert lib.dvm_required_workspace(h, C.byref(n)) == 0
+    assert lib.dvm_set_parameter_precision(h, 32) == 0
+    m = C.c_size_t()
+    assert lib.dvm_required_workspace(h, C.byref(m)) == 0
+    assert n.value > m.value                                    # FP64 record and tables
+    assert lib.dvm_set_parameter_precision(h, 64) == 0
+    assert lib.dvm_set_schedule(h, 2, 4, 2, 0, 0) == 0
+    assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 1 << 40) == -1
+    assert b"FP64 parameters" in lib.dvm_last_error()
     lib.dvm_destroy(h)
