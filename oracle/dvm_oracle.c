@@ -23,7 +23,8 @@
  *     optionally (orc_set_order) the second-order upwind sweep that the
  *     paper's closing section proposes (three consecutive cells per axis:
  *     each face carries the upwind cell's value extrapolated linearly from
- *     that cell and its own upwind neighbour), uniform meshes only;
+ *     that cell and its own upwind neighbour, with the cells' sizes on a
+ *     stretched mesh);
  *   - optionally (orc_set_model) the ES-BGK model in place of Shakhov's:
  *     an anisotropic Gaussian built from the stress of the iterate,
  *     relaxing with frequency Pr p / mu, corrected the same way;
@@ -328,16 +329,10 @@ int orc_set_spacing(orc_state *s, const double *hx, const double *hy, const doub
 
 /* Spatial order of the upwind scheme (1 or 2).  The second order is the one
    the paper's closing section proposes, built from three consecutive cells
-   along each axis; it is defined here for uniform meshes only.             */
+   along each axis (see sweep_velocity); on uniform and stretched meshes.   */
 int orc_set_order(orc_state *s, int order)
 {
     if (order != 1 && order != 2) return ORC_ERR;
-    if (order == 2) {
-        const int n3[3] = {s->c.nx, s->c.ny, s->c.nz};
-        for (int d = 0; d < 3; ++d)
-            for (int i = 0; i < n3[d]; ++i)
-                if (fabs(s->h[d][i] - s->dx[d]) > 1e-12 * s->dx[d]) return ORC_ERR;
-    }
     s->order = order;
     return ORC_OK;
 }
@@ -513,12 +508,16 @@ typedef struct {
  *
  * fo[d] (3 x N): the value this velocity carries through each cell's
  * downstream face along axis d.  First order: the cell value.  Second
- * order: the linear extrapolation from the cell and its upwind neighbour
- * along d, f + (f - f_up)/2, or the cell value when the upwind side is a
- * boundary.  The cell balance is then, per axis with a = |xi_d| / h,
+ * order: the linear profile through the centres of the cell and of its
+ * upwind neighbour along d, evaluated at the cell's downstream face:
+ * f + theta (f - f_up) with theta = h / (h + h_up), h and h_up the two cells'
+ * sizes along d (1/2 on a uniform mesh; the mirror image beyond a symmetry
+ * plane has the cell's own size), or the cell value when the upwind side is
+ * a boundary.  The cell balance is then, per axis with a = |xi_d| / h,
  * a (fo_d(cell) - fo_d(upwind)) (the boundary's inflow value in place of
  * fo_d(upwind) at a boundary), so that the unknown f enters with
- * coefficient 3a/2 behind an interior face and a behind a boundary.        */
+ * coefficient (1 + theta) a behind an interior face and a behind a
+ * boundary.                                                                 */
 static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                            const double *feq, const double *nu,
                            const double *spec_mirror, double *f, double *fo)
@@ -544,6 +543,7 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                 double num = nu[id] * feq[id];
                 double den = nu[id];
                 double up[3] = {0, 0, 0};  /* f of the interior upwind cell */
+                double th[3] = {0, 0, 0};  /* second order: extrapolation weight */
                 int interior[3] = {0, 0, 0};
                 /* |xi_d| / (cell size along d): the flux through the cell's
                    upwind face per unit volume                               */
@@ -561,10 +561,14 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                         const int nxy = c->nx * c->ny, ij = i + c->nx * j;
                         const double fup = t < 0 ? f[nb] : spec_mirror[ij];
                         const double fin = t < 0 ? fo[(size_t)d * N + nb] : spec_mirror[nxy + ij];
+                        const int pos[3] = {i, j, k};
+                        const double hc = s->h[d][pos[d]];
+                        const double hu = t < 0 ? s->h[d][pos[d] - sg[d]] : hc;
+                        th[d] = hc / (hc + hu);
                         interior[d] = 1;
                         up[d] = fup;
-                        num += ad[d] * (fin + 0.5 * fup);
-                        den += 1.5 * ad[d];
+                        num += ad[d] * (fin + th[d] * fup);
+                        den += (1.0 + th[d]) * ad[d];
                         continue;
                     }
                     if (t < 0) fu = f[nb];
@@ -576,7 +580,7 @@ static void sweep_velocity(const orc_state *s, int a3, int b3, int c3,
                 }
                 f[id] = num / den;
                 for (int d = 0; d < 3; ++d)
-                    fo[(size_t)d * N + id] = interior[d] ? f[id] + 0.5 * (f[id] - up[d]) : f[id];
+                    fo[(size_t)d * N + id] = interior[d] ? f[id] + th[d] * (f[id] - up[d]) : f[id];
             }
         }
     }

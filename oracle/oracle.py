@@ -191,7 +191,7 @@ class Oracle:
                 raise ValueError(f"unknown model {model}")
         order = getattr(case, "order", 1)
         if order != 1 and lib().orc_set_order(self._h, order) != 0:
-            raise ValueError("second order needs a uniform mesh (order 1 or 2)")
+            raise ValueError("the upwind order must be 1 or 2")
 
     def __del__(self):
         h = getattr(self, "_h", None)

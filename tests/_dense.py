@@ -13,12 +13,15 @@ with LU (numpy), i.e. without any notion of sweep order, so it checks the
 oracle's sweep (traversal order, upwind selection, boundary bookkeeping).
 
 order=2: the flux through each face is the upwind cell's value extrapolated
-linearly from that cell and its own upwind neighbour, f_u + (f_u - f_uu)/2
-(just f_u when the upwind cell's upwind side is a boundary), and a
-boundary's inflow value where the face is a boundary; the cell's balance
-per axis is a_d (F_out(c) - F_in(c)).  A symmetry plane is an interior face
-whose far side is the mirror image: spec_mirror then holds two planes (the
-mirror's f and its extrapolated face value).
+linearly from that cell and its own upwind neighbour, i.e. the straight
+line through the two cell centres evaluated at the face,
+f_u + theta_u (f_u - f_uu) with theta_u = h_u / (h_u + h_uu) along d (1/2 on
+a uniform mesh; just f_u when the upwind cell's upwind side is a boundary),
+and a boundary's inflow value where the face is a boundary; the cell's
+balance per axis is a_d (F_out(c) - F_in(c)).  A symmetry plane is an
+interior face whose far side is the mirror image (of the same size):
+spec_mirror then holds two planes (the mirror's f and its extrapolated face
+value).
 """
 from __future__ import annotations
 
@@ -98,21 +101,29 @@ def dense_velocity_solve(case, alpha, feq, nu, rho_w, ghat_of_kind, spec_mirror=
                         A[c, c] += ad
                         b[c] += ad * up[1]
                         continue
-                    # interior face: a (1.5 f_c - 0.5 f_u - F_out(u))
-                    A[c, c] += 1.5 * ad
+                    # interior face: a ((1 + t_c) f_c - t_c f_u - F_out(u)),
+                    # t = own size / (own size + upwind neighbour's size)
+                    hc = h[d][pos[d]]
                     if up[0] == "spec":
+                        tc = hc / (hc + hc)
+                        A[c, c] += (1.0 + tc) * ad
                         nxy = nx * ny
-                        b[c] += ad * (0.5 * spec_mirror[up[1]] + spec_mirror[nxy + up[1]])
+                        b[c] += ad * (tc * spec_mirror[up[1]] + spec_mirror[nxy + up[1]])
                         continue
                     u = up[1]
-                    A[c, u] -= 0.5 * ad
+                    hu = h[d][up[2][d]]
+                    tc = hc / (hc + hu)
+                    A[c, c] += (1.0 + tc) * ad
+                    A[c, u] -= tc * ad
                     uu = upwind(up[2], d, u)
                     if uu[0] == "bnd":            # F_out(u) = f_u
                         A[c, u] -= ad
-                    elif uu[0] == "cell":         # F_out(u) = 1.5 f_u - 0.5 f_uu
-                        A[c, u] -= 1.5 * ad
-                        A[c, uu[1]] += 0.5 * ad
-                    else:                         # beyond u: the mirror image
-                        A[c, u] -= 1.5 * ad
-                        b[c] -= 0.5 * ad * spec_mirror[uu[1]]
+                    elif uu[0] == "cell":         # F_out(u) = (1 + t_u) f_u - t_u f_uu
+                        tu = hu / (hu + h[d][uu[2][d]])
+                        A[c, u] -= (1.0 + tu) * ad
+                        A[c, uu[1]] += tu * ad
+                    else:                         # beyond u: the mirror image, t_u = 1/2
+                        tu = hu / (hu + hu)
+                        A[c, u] -= (1.0 + tu) * ad
+                        b[c] -= tu * ad * spec_mirror[uu[1]]
     return np.linalg.solve(A, b)
