@@ -113,6 +113,56 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_byt
     print(json.dumps(rec))
 
 
+def summarize_trace(db_path: str, out_md: str, title: str, command: str, bench_json: str = ""):
+    """Kernel-trace summary (markdown) from a rocprofv3 --kernel-trace
+    database: per kernel the calls, total, average, min and max duration,
+    and for the sweep kernels the wall time their launches cover (the union
+    of the launch intervals: launches on several streams overlap, so the
+    sum of their durations exceeds the sweep phase's wall time)."""
+    import sqlite3
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, start, end from kernels").fetchall()
+    con.close()
+    by = {}
+    for name, t0, t1 in rows:
+        by.setdefault(name, []).append((t0, t1))
+    total = sum(t1 - t0 for v in by.values() for t0, t1 in v)
+    lines = [f"# Kernel stats: {title}", "", "Command (run from the repository root on one MI355X; output directory "
+             "under gpurun_out/):", "", "```", command, "```", "",
+             "| kernel | calls | total ms | avg us | % | min us | max us |", "|---|---|---|---|---|---|---|"]
+    for name, v in sorted(by.items(), key=lambda kv: -sum(t1 - t0 for t0, t1 in kv[1])):
+        d = [(t1 - t0) / 1e3 for t0, t1 in v]
+        short = name if len(name) <= 80 else name[:77] + "..."
+        lines.append(f"| `{short}` | {len(d)} | {sum(d) / 1e3:.3f} | {sum(d) / len(d):.1f} | "
+                     f"{100.0 * sum(d) * 1e3 / total:.2f} | {min(d):.1f} | {max(d):.1f} |")
+    sw = sorted(iv for name, v in by.items() if "sweep_kernel" in name for iv in v)
+    if sw:
+        busy, cur0, cur1 = 0, None, None
+        for t0, t1 in sw:
+            if cur1 is None or t0 > cur1:
+                if cur1 is not None:
+                    busy += cur1 - cur0
+                cur0, cur1 = t0, t1
+            else:
+                cur1 = max(cur1, t1)
+        busy += cur1 - cur0
+        summed = sum(t1 - t0 for t0, t1 in sw)
+        lines += ["", f"Sweep launches: {len(sw)}; summed duration {summed / 1e6:.3f} ms; wall time covered by "
+                  f"them (union of the launch intervals) {busy / 1e6:.3f} ms; launches in flight on average "
+                  f"{summed / busy:.2f}."]
+    if bench_json:
+        with open(bench_json) as f:
+            d = json.loads(f.read().strip().splitlines()[-1])
+        iters = d["steps"]
+        lines += ["", f"The bench line printed by the same profiled command: {d['value']} GPt/s, "
+                  f"{d['ms_per_step']} ms per iteration, sweep phase {d['config']['phase_ms']['sweep']} ms per "
+                  f"iteration by HIP events over the {iters} timed iterations (the trace above also holds the "
+                  f"{d['warmup']} warm-up iterations)."]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def measured_traffic(label: str):
     """Bytes per sweep launch from the committed counter summary, if it was
     taken on the current kernel source and the same workload/schedule."""
@@ -433,6 +483,11 @@ def main():
     ap.add_argument("--body", default=None, choices=("plain", "pf", "dyn"),
                     help="sweep body in place of the library's choice: plain, software-pipelined (pf) "
                          "or pipelined in one dependency-driven launch (dyn)")
+    ap.add_argument("--brick", default=None, metavar="VL,BX,BY,BZ",
+                    help="sweep schedule in place of the library's choice: velocities per lane and brick cells "
+                         "(0 keeps that value)")
+    ap.add_argument("--streams", type=int, default=0, choices=(0, 1, 2, 4, 8),
+                    help="streams for the per-diagonal sweep launches (0: the library's default)")
     ap.add_argument("--param-bits", type=int, default=0, choices=(0, 32, 64),
                     help="FP32 storage: per-cell parameters and equilibrium evaluation in FP64 (64)")
     ap.add_argument("--precision-error", action="store_true",
@@ -456,10 +511,18 @@ def main():
                     help="run the workload on a mesh stretched geometrically by this ratio per cell")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=4, default=None, metavar=("DB", "NAME", "TITLE", "BENCH_JSON"),
+                    help="write profiles/NAME.md from a rocprofv3 --kernel-trace database")
     ap.add_argument("--summarize-pmc", nargs=6, default=None,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "COPY_BYTES", "LABEL"),
                     help="write profiles/sweep_traffic_LABEL.json from rocprofv3 --pmc CSVs")
     args = ap.parse_args()
+    if args.summarize_trace:
+        db, name, title, bj = args.summarize_trace
+        cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof/W -o W "
+               "-- python3 $REPO/bench.py --workload W --steps 10 --warmup 2 --no-cpu --no-ttr")
+        summarize_trace(db, os.path.join(TRAFFIC_DIR, name + ".md"), title, cmd, bj)
+        return
     if args.summarize_pmc:
         a = args.summarize_pmc
         summarize_pmc(a[0], a[1], a[2], a[3], float(a[4]),
@@ -514,7 +577,10 @@ def main():
         solve(case, prec, args.solve, args.tol, describe(args.workload, case))
         return
     sched = None if args.body is None else {"pipelined": {"plain": False, "pf": True, "dyn": "dyn"}[args.body]}
-    s = Solver(case, precision=prec, schedule=sched, parameter_bits=args.param_bits)
+    if args.brick:
+        vl, bx, by, bz = (int(x) for x in args.brick.split(","))
+        sched = dict(sched or {}, vl=vl, bx=bx, by=by, bz=bz)
+    s = Solver(case, precision=prec, schedule=sched, parameter_bits=args.param_bits, sweep_streams=args.streams)
     s.init_uniform()
     info = s.info()
     if args.warmup:
@@ -526,7 +592,15 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tm = s.timings()
-    s.set_timing(False)
+    # per-launch durations, in a pass of their own after the timed steps
+    # (an event pair around every sweep launch on its stream): the launches
+    # of the sweep's streams overlap, so their average duration is longer
+    # than the sweep phase's wall time divided by the launches
+    s.set_timing(2)
+    s.iterate(3)
+    lt = s.launch_timings()
+    lt_phase = s.timings()
+    s.set_timing(0)
 
     ms = dt * 1e3 / args.steps
     pts = case.points
@@ -548,6 +622,8 @@ def main():
         label += f"_{args.model}"
     if info["sweep_kernel"] == "sweep_kernel_dyn":
         label += "_dyn"
+    elif info["sweep_streams"] != 1:
+        label += f"_s{info['sweep_streams']}"
     if prec == "f32" and info["parameter_bits"] == 64:
         label += "_p64"
     line = {
@@ -572,6 +648,7 @@ def main():
             "brick": info["brick"],
             "vel_per_lane": info["vel_per_lane"],
             "sweep_kernel": info["sweep_kernel"],
+            "sweep_streams": info["sweep_streams"],
             "parameter_bits": info["parameter_bits"],
             "sweep_launches_per_iteration": launches,
             "phase_ms": {"params": round(tm["params_ms"] / iters, 4),
@@ -591,7 +668,13 @@ def main():
             "kernel": info["sweep_kernel"],
             "bytes_per_point": 2 * sbytes,
             "launches_per_step": launches,
-            "avg_launch_ms": round(sweep_ms / max(1, launches), 5),
+            # HIP events around every launch (agrees with the kernel
+            # trace's average), the algorithmic rate of one launch over
+            # its own duration, and how many launches run at once
+            "avg_launch_ms": round(lt["launch_ms_total"] / max(1, lt["launches"]), 5),
+            "achieved_per_launch": round(pts * 2 * sbytes / launches
+                                         / (lt["launch_ms_total"] / max(1, lt["launches"]) / 1e3) / 1e9, 1),
+            "launches_in_flight": round(lt["launch_ms_total"] / max(1e-9, lt_phase["sweep_ms"]), 3),
             "alu_view": {"flops_per_point": FLOPS_PER_POINT,
                          "achieved_tflops": round(pts * FLOPS_PER_POINT / (sweep_ms / 1e3) / 1e12, 3),
                          "peak_tflops_fp64": PEAK_FP64_TFLOPS},

@@ -106,6 +106,7 @@ typedef struct {
     int velocity_groups;        /* velocity groups swept one after another        */
     int parameter_bits;         /* 64: per-cell parameters, Gaussian tables and
                                    equilibrium evaluation in FP64; 32: in FP32    */
+    int sweep_streams;          /* streams the per-diagonal sweep launches use    */
 } dvm_info;
 
 /* Create a context.  precision: DVM_F64 or DVM_F32, the storage and update
@@ -251,6 +252,18 @@ dvm_status dvm_set_schedule(dvm_ctx* ctx, int vel_per_lane, int bx, int by, int 
    workspace (DVM_ERR_STATE after it). */
 dvm_status dvm_set_parameter_precision(dvm_ctx* ctx, int bits);
 
+/* Streams for the per-diagonal sweep launches (1, 2, 4 or 8; default 2).
+   The octants of a phase (all eight, or the four of one side of a
+   specular plane) are split into that many sets, each set's launches go to
+   a stream of its own, forked from the context's stream after the
+   parameters and joined back before the moments are finalised: the octants
+   do not depend on each other within an iteration, so a set's next
+   diagonal fills the device while another set's launch drains.  The result
+   is the same for every count.  The streams (default priority) and their
+   events are created at the first iteration that needs them; a count above
+   the one created then is refused with DVM_ERR_STATE. */
+dvm_status dvm_set_sweep_streams(dvm_ctx* ctx, int streams);
+
 /* Bytes of device workspace the context needs with its current settings. */
 dvm_status dvm_required_workspace(dvm_ctx* ctx, size_t* bytes);
 
@@ -316,13 +329,18 @@ dvm_status dvm_set_state(dvm_ctx* ctx, const double* W, const double* q, const d
 /* Sizes and schedule of the context. */
 dvm_status dvm_get_info(dvm_ctx* ctx, dvm_info* info);
 
-/* Per-phase device timing.  enable != 0 records HIP events around the
+/* Per-phase device timing.  enable = 1 records HIP events around the
    parameter, sweep and finalisation phases of every following iteration
-   (on the context's stream).  dvm_get_timings returns the accumulated
-   milliseconds and the number of timed iterations, then resets them. */
+   (on the context's stream; the sweep phase from the fork of its streams to
+   their join).  enable = 2 also records events around every sweep launch on
+   the stream it is issued to.  dvm_get_timings returns the accumulated
+   milliseconds and the number of timed iterations, dvm_get_launch_timings
+   the summed duration of the timed sweep launches and their number; each
+   resets what it returns.  DVM_ERR_ARG for another level. */
 dvm_status dvm_set_timing(dvm_ctx* ctx, int enable);
 dvm_status dvm_get_timings(dvm_ctx* ctx, double* ms_params, double* ms_sweep,
                            double* ms_finalize, int* iterations);
+dvm_status dvm_get_launch_timings(dvm_ctx* ctx, double* ms_total, long long* launches);
 
 /* Check of the wave-level 13-moment reduction used by the sweep kernel:
    in[64*13] (lane-major: in[lane*13 + k]) -> out[13] = sum over lanes. */

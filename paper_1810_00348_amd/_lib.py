@@ -49,7 +49,7 @@ class Info(C.Structure):
                 ("nfluid", C.c_int), ("m", C.c_int * 3), ("nvel", C.c_int), ("precision", C.c_int),
                 ("brick", C.c_int * 3), ("vel_per_lane", C.c_int), ("tiles_per_octant", C.c_int),
                 ("sweep_launches", C.c_int), ("workspace_bytes", C.c_size_t), ("pipelined", C.c_int),
-                ("velocity_groups", C.c_int), ("parameter_bits", C.c_int)]
+                ("velocity_groups", C.c_int), ("parameter_bits", C.c_int), ("sweep_streams", C.c_int)]
 
 
 _P = C.POINTER(C.c_double)
@@ -61,6 +61,7 @@ EXPORTS = {
     "dvm_set_solid_mask": ([C.c_void_p, C.c_void_p, _P, C.c_double], C.c_int),
     "dvm_set_schedule": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
     "dvm_set_parameter_precision": ([C.c_void_p, C.c_int], C.c_int),
+    "dvm_set_sweep_streams": ([C.c_void_p, C.c_int], C.c_int),
     "dvm_set_closed": ([C.c_void_p, C.c_int], C.c_int),
     "dvm_set_spacing": ([C.c_void_p, _P, _P, _P], C.c_int),
     "dvm_set_velocity_groups": ([C.c_void_p, C.c_int], C.c_int),
@@ -82,6 +83,7 @@ EXPORTS = {
     "dvm_get_info": ([C.c_void_p, C.POINTER(Info)], C.c_int),
     "dvm_set_timing": ([C.c_void_p, C.c_int], C.c_int),
     "dvm_get_timings": ([C.c_void_p, _P, _P, _P, C.POINTER(C.c_int)], C.c_int),
+    "dvm_get_launch_timings": ([C.c_void_p, _P, C.POINTER(C.c_longlong)], C.c_int),
     "dvm_selftest_wave_reduce": ([_P, _P], C.c_int),
     "dvm_last_error": ([], C.c_char_p),
     "dvm_destroy": ([C.c_void_p], None),

@@ -14,6 +14,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -124,8 +125,19 @@ struct dvm_ctx {
     double kind_rho[8] = {0};
     int kind_wall[8] = {0};
 
-    // timing
-    bool timing = false;
+    // the per-diagonal sweep launches of disjoint octant sets go to separate
+    // streams (forked from and joined back into `stream` around the sweep):
+    // the octants are independent within an iteration, so one set's next
+    // diagonal fills the device while another's launch drains
+    int nstreams = 2;
+    hipStream_t sub[8] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[8] = {};
+
+    // timing (level 2 also times every sweep launch on its own stream)
+    int timing = 0;
+    std::vector<hipEvent_t> lev;  // launch events: start, end per launch
+    double t_launch = 0;
+    long long n_launch = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double t_params = 0, t_sweep = 0, t_final = 0;
     int t_iters = 0;
@@ -197,12 +209,13 @@ void derive_schedule(dvm_ctx* c)
     if (!sweep_variant_available(c->prec, vl, default_bx(vl), default_by(vl), c->nonuniform, o2, es)) vl = 1;
     int bx = default_bx(vl), by = default_by(vl);
     int pf = vl >= 2 ? 1 : 0;
-    // cells per brick column: 12 for FP64 with 4 per lane and for the
-    // second-order FP64 form (141 GPt/s against 137 at 8), (cavity 64^3 x
-    // 32^3: 3x2 bricks 277 GPt/s against 268 at 8 and 270 at 16; 4x2 265
-    // against 262 at 8 and 256 at 16), 8 otherwise (FP32: 12 is 1-2 %
-    // slower on 96^3 x 28^3 and the cube)
-    int bz = (f64 && (vl == 4 || o2)) ? 12 : 8;
+    // cells per brick column: 16 for the first-order FP64 sweep with 4 per
+    // lane (cavity 64^3 x 32^3 with the launches on two streams: 3x2 bricks
+    // 292 GPt/s against 286 at 12, 287 at 14, 283 at 20 and 24, 277 at 32;
+    // 4x2 288 at 16, 282 at 12), 12 for the second-order FP64 form (141
+    // GPt/s against 137 at 8) and the ES-BGK one, 8 otherwise (FP32: 12 is
+    // 1-2 % slower on 96^3 x 28^3 and the cube)
+    int bz = (f64 && vl == 4 && !o2 && !es) ? 16 : (f64 && (vl == 4 || o2)) ? 12 : 8;
     c->req_ok = true;
     if (c->req_vl || c->req_bx || c->req_by || c->req_bz || c->req_body) {
         const int rv = c->req_vl ? c->req_vl : vl;
@@ -533,8 +546,27 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
     const int phases = c->spec_on ? 2 : 1;
     const bool dyn = c->PF == 2;
     const int nbricks = (int)(c->bricks.size() / 4);
+    // octants swept per phase, and the streams that share them
+    const int oct_phase = c->spec_on ? 4 : 8;
+    const int ns = dyn ? 1 : std::min(c->nstreams, oct_phase);
+    int nlaunch = 0;
+    if (ns > 1 && !c->fork_ev) {
+        HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        for (int k = 0; k < ns; ++k) {
+            HIPCHK(hipStreamCreateWithFlags(&c->sub[k], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming));
+        }
+    }
     for (int grp = 0; grp < c->ngroups; ++grp) {
     const int t0 = c->gt0[grp], gnt = c->gt0[grp + 1] - t0;
+    if (ns > 1) {
+        HIPCHK(hipEventRecord(c->fork_ev, st));
+        for (int k = 0; k < ns; ++k) HIPCHK(hipStreamWaitEvent(c->sub[k], c->fork_ev, 0));
+    }
+    for (int sk = 0; sk < ns; ++sk) {
+    hipStream_t ss = ns > 1 ? c->sub[sk] : st;
+    // with a specular plane each stream keeps a mirror pair (o, o + 4) of
+    // octants: the +z one reads the plane its -z partner wrote in phase 0
     for (int ph = 0; ph < phases; ++ph) {
         // per-diagonal launches, or one dependency-driven launch over all
         // bricks (diagonal 0 standing for all of them)
@@ -566,8 +598,8 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.nbx = c->nbx; a.nby = c->nby; a.nbz = c->nbz; a.bz = c->BZ;
                 a.ntiles = gnt; a.slots = gnt * 64; a.lstride = c->lstride;
                 a.brick_off = dyn ? 0 : c->diag_off[T]; a.brick_cnt = cnt;
-                a.oct_base = c->spec_on ? 4 * ph : 0;
-                a.noct = c->spec_on ? 4 : 8;
+                a.oct_base = (c->spec_on ? 4 * ph : 0) + sk * (oct_phase / ns);
+                a.noct = oct_phase / ns;
                 a.spec_on = c->spec_on ? 1 : 0;
                 a.has_solid = c->nfluid < c->N ? 1 : 0;
                 a.nblocks = a.noct * cnt * gnt;
@@ -580,23 +612,41 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.launched = &launched;
             };
             hipError_t e;
+            const size_t li = (size_t)nlaunch * 2;
+            if (c->timing == 2) {
+                while (c->lev.size() < li + 2) {
+                    hipEvent_t ev;
+                    HIPCHK(hipEventCreate(&ev));
+                    c->lev.push_back(ev);
+                }
+                HIPCHK(hipEventRecord(c->lev[li], ss));
+            }
             if (c->prec == DVM_F64) {
                 SweepArgs<double> a;
                 fill(a);
                 e = launch_sweep(0, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, 0, &a,
-                                 st);
+                                 ss);
             } else {
                 SweepArgs<float> a;
                 fill(a);
                 e = launch_sweep(1, c->VL, c->BX, c->BY, c->PF, c->nonuniform, c->order == 2, c->model == 1, c->wide,
-                                 &a, st);
+                                 &a, ss);
             }
             if (e != hipSuccess) return fail(DVM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+            if (c->timing == 2) HIPCHK(hipEventRecord(c->lev[li + 1], ss));
+            ++nlaunch;
             if (dyn) {
                 // every started wave ends with one failed take of the counter
                 c->epoch += 1;
                 c->qbase += (unsigned long long)cnt * (c->spec_on ? 4 : 8) * gnt + (unsigned long long)launched;
             }
+        }
+    }
+    }
+    if (ns > 1) {
+        for (int k = 0; k < ns; ++k) {
+            HIPCHK(hipEventRecord(c->join_ev[k], c->sub[k]));
+            HIPCHK(hipStreamWaitEvent(st, c->join_ev[k], 0));
         }
     }
     if (c->ngroups > 1)
@@ -627,6 +677,14 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
         c->t_sweep += b;
         c->t_final += d;
         c->t_iters++;
+        if (c->timing == 2) {
+            for (int k = 0; k < nlaunch; ++k) {
+                float t = 0;
+                HIPCHK(hipEventElapsedTime(&t, c->lev[2 * k], c->lev[2 * k + 1]));
+                c->t_launch += t;
+            }
+            c->n_launch += nlaunch;
+        }
     }
     return DVM_OK;
 }
@@ -917,6 +975,17 @@ dvm_status dvm_set_schedule(dvm_ctx* c, int vel_per_lane, int bx, int by, int bz
 dvm_status dvm_set_solid_mask(dvm_ctx* c, const unsigned char* mask, const double u_wall[3], double T_wall)
 {
     return dvm_set_solid(c, mask, u_wall, T_wall);
+}
+
+dvm_status dvm_set_sweep_streams(dvm_ctx* c, int streams)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (streams != 1 && streams != 2 && streams != 4 && streams != 8)
+        return fail(DVM_ERR_ARG, "streams must be 1, 2, 4 or 8 (got %d)", streams);
+    if (c->fork_ev && streams > c->nstreams)
+        return fail(DVM_ERR_STATE, "the sweep streams are created; more cannot be added");
+    c->nstreams = streams;
+    return DVM_OK;
 }
 
 dvm_status dvm_set_velocity_groups(dvm_ctx* c, int groups)
@@ -1266,22 +1335,37 @@ dvm_status dvm_get_info(dvm_ctx* c, dvm_info* info)
     info->tiles_per_octant = c->ntiles;
     int launches = 0;
     for (int T = 0; T < c->ndiag; ++T) launches += c->diag_cnt[T] > 0;
-    info->sweep_launches = (c->PF == 2 ? 1 : launches) * (c->spec_on ? 2 : 1) * c->ngroups;
+    const int ns = c->PF == 2 ? 1 : std::min(c->nstreams, c->spec_on ? 4 : 8);
+    info->sweep_launches = (c->PF == 2 ? 1 : launches) * (c->spec_on ? 2 : 1) * c->ngroups * ns;
     info->workspace_bytes = c->off.end;
     info->pipelined = c->PF;
     info->velocity_groups = c->ngroups;
     info->parameter_bits = c->pprec() == DVM_F64 ? 64 : 32;
+    info->sweep_streams = ns;
     return DVM_OK;
 }
 
 dvm_status dvm_set_timing(dvm_ctx* c, int enable)
 {
     if (check_ctx(c)) return DVM_ERR_ARG;
+    if (enable < 0 || enable > 2) return fail(DVM_ERR_ARG, "timing level must be 0, 1 or 2 (got %d)", enable);
     if (enable && !c->ev[0])
         for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&c->ev[k]));
-    c->timing = enable != 0;
+    c->timing = enable;
     c->t_params = c->t_sweep = c->t_final = 0;
     c->t_iters = 0;
+    c->t_launch = 0;
+    c->n_launch = 0;
+    return DVM_OK;
+}
+
+dvm_status dvm_get_launch_timings(dvm_ctx* c, double* ms_total, long long* launches)
+{
+    if (check_ctx(c)) return DVM_ERR_ARG;
+    if (ms_total) *ms_total = c->t_launch;
+    if (launches) *launches = c->n_launch;
+    c->t_launch = 0;
+    c->n_launch = 0;
     return DVM_OK;
 }
 
@@ -1322,6 +1406,12 @@ void dvm_destroy(dvm_ctx* c)
     }
     for (int k = 0; k < 4; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    for (hipEvent_t e : c->lev) (void)hipEventDestroy(e);
+    for (int k = 0; k < 8; ++k) {
+        if (c->sub[k]) (void)hipStreamDestroy(c->sub[k]);
+        if (c->join_ev[k]) (void)hipEventDestroy(c->join_ev[k]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     delete c;
 }
 

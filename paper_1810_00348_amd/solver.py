@@ -26,7 +26,7 @@ class Solver:
     def __init__(self, case: Case, precision: str = "f64", device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, velocity_groups: Optional[int] = None,
                  memory_fraction: float = 0.9, schedule: Optional[dict] = None,
-                 static_workspace: bool = False, parameter_bits: int = 0):
+                 static_workspace: bool = False, parameter_bits: int = 0, sweep_streams: int = 0):
         """velocity_groups: sweep the velocity set in that many parts per
         iteration (None: the fewest parts whose workspace fits
         memory_fraction of the device's free memory).  schedule: a sweep
@@ -39,7 +39,9 @@ class Solver:
         dvm_bind_static_workspace) instead of a torch buffer.
         parameter_bits: 64 with precision "f32" keeps the per-cell
         parameters, Gaussian tables and the equilibrium evaluation in FP64
-        (see dvm_set_parameter_precision); 0 keeps the default."""
+        (see dvm_set_parameter_precision); 0 keeps the default.
+        sweep_streams: streams for the per-diagonal sweep launches (see
+        dvm_set_sweep_streams); 0 keeps the default."""
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
         self.case = case
@@ -85,6 +87,8 @@ class Solver:
             L.check(lib.dvm_set_order(h, int(case.order)))
         if parameter_bits:
             L.check(lib.dvm_set_parameter_precision(h, int(parameter_bits)))
+        if sweep_streams:
+            L.check(lib.dvm_set_sweep_streams(h, int(sweep_streams)))
         if schedule:
             unknown = set(schedule) - {"vl", "bx", "by", "bz", "pipelined"}
             if unknown:
@@ -234,10 +238,18 @@ class Solver:
                 "vel_per_lane": inf.vel_per_lane, "tiles_per_octant": inf.tiles_per_octant,
                 "sweep_launches": inf.sweep_launches, "workspace_bytes": inf.workspace_bytes,
                 "sweep_kernel": ("sweep_kernel", "sweep_kernel_pf", "sweep_kernel_dyn")[inf.pipelined],
-                "velocity_groups": inf.velocity_groups, "parameter_bits": inf.parameter_bits}
+                "velocity_groups": inf.velocity_groups, "parameter_bits": inf.parameter_bits,
+                "sweep_streams": inf.sweep_streams}
 
-    def set_timing(self, enable: bool = True):
+    def set_timing(self, enable: int = 1):
+        """1: per-phase events; 2: also every sweep launch (see dvm_set_timing)."""
         L.check(L.lib().dvm_set_timing(self._h, int(enable)))
+
+    def launch_timings(self):
+        ms = C.c_double()
+        n = C.c_longlong()
+        L.check(L.lib().dvm_get_launch_timings(self._h, C.byref(ms), C.byref(n)))
+        return {"launch_ms_total": ms.value, "launches": n.value}
 
     def timings(self):
         a = C.c_double(); b = C.c_double(); d = C.c_double(); n = C.c_int()

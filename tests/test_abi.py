@@ -247,7 +247,7 @@ def test_model_arguments(L):
 
 @pytest.mark.parametrize("name,prec,order,model,expect", [
     # (VL, BX, BY, BZ, pipelined) chosen by the library for the benchmark workloads
-    ("c2", 0, 1, 0, (4, 3, 2, 12, 1)),    # FP64, 16 nodes per x half
+    ("c2", 0, 1, 0, (4, 3, 2, 16, 1)),    # FP64, 16 nodes per x half
     ("c2", 0, 1, 1, (4, 4, 2, 12, 1)),    # ES-BGK FP64
     ("c2", 0, 2, 0, (2, 4, 2, 12, 1)),    # second order FP64: 2 per lane
     ("c3", 1, 1, 0, (4, 4, 2, 8, 1)),     # FP32, 14 nodes per half (empty slots)
@@ -283,17 +283,17 @@ def test_brick_columns_shortened_for_32bit_face_offsets(L):
     # 2000 x 2000 x 2 cells, 64^3 velocities, FP64: an octant has 32^3
     # velocities = 8192 lanes of 4 = 128 tiles, so one face cell holds
     # 128 x 64 x 4 x 8 bytes = 256 KiB and 4 GiB holds 16384 of them:
-    # (BZ - 1) * 2000 + 3 < 16384 -> BZ <= 9; halving from 12 gives 6
+    # (BZ - 1) * 2000 + 3 < 16384 -> BZ <= 9; halving from 16 gives 8
     case = cases.cavity((2000, 2000, 2), 64, kn=1.0)
     h = _ctx(L, case, 0)
     info = L.Info()
     assert lib.dvm_get_info(h, C.byref(info)) == 0
     assert (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 3, 2)
-    assert info.brick[2] == 6, tuple(info.brick)
+    assert info.brick[2] == 8, tuple(info.brick)
     lib.dvm_destroy(h)
-    # the benchmark grid keeps its 12-cell columns
+    # the benchmark grid keeps its 16-cell columns
     h = _ctx(L, cases.config("c2"), 0)
-    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.brick[2] == 12
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.brick[2] == 16
     lib.dvm_destroy(h)
 
 
@@ -317,7 +317,7 @@ def test_schedule_requests(L):
     # all zero: the library's choice again
     assert lib.dvm_set_schedule(h, 0, 0, 0, 0, 0) == 0
     assert lib.dvm_get_info(h, C.byref(info)) == 0
-    assert (info.vel_per_lane, *info.brick, info.pipelined) == (4, 3, 2, 12, 1)
+    assert (info.vel_per_lane, *info.brick, info.pipelined) == (4, 3, 2, 16, 1)
     # velocities per lane alone: the brick defaults of that width
     assert lib.dvm_set_schedule(h, 1, 0, 0, 0, 0) == 0
     assert lib.dvm_get_info(h, C.byref(info)) == 0
