@@ -493,6 +493,8 @@ def main():
     ap.add_argument("--precision-error", action="store_true",
                     help="instead of the throughput line: per-field error of the FP32 storage form against "
                          "FP64 on the same inputs (after 1, 5, 20 iterations and at the FP32 floor)")
+    ap.add_argument("--floor-iters", type=int, default=60,
+                    help="--precision-error: FP32 iterations run to reach its residual floor")
     ap.add_argument("--no-ttr", action="store_true",
                     help="skip the time-to-residual runs of the default line (64^3 x 32^3 cavity, Kn 1)")
     ap.add_argument("--traffic", default=None)
@@ -549,7 +551,8 @@ def main():
 
     if args.precision_error:
         case, _ = workload(args.workload, args.kn)
-        print(json.dumps(precision_error(args.workload, case, parameter_bits=args.param_bits)), flush=True)
+        print(json.dumps(precision_error(args.workload, case, floor_iters=args.floor_iters,
+                                         parameter_bits=args.param_bits)), flush=True)
         return
 
     if args.time_to_residual:

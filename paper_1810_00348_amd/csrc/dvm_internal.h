@@ -90,6 +90,9 @@ struct SweepArgs {
     S* zgface;
     S* specg;
     double* partial;      // [8*ntiles][N][PREC]
+    // second order on a stretched mesh: per axis (x, y, z) and direction
+    // (+, -) the weight h_i / (h_i + h_upwind) of each cell index
+    const double* theta;
     double rdx;           // 1 / h_x on a uniform mesh, 1 on a non-uniform one
     int nx, ny, nz, N, mx, my, MT, NV;
     int nbx, nby, nbz, bz;

@@ -1436,6 +1436,16 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
     const int shX = 4 * sideX, shY = 4 * sideY, shZ = 4 * sideZ;
     const int ridx = reduce13_index(lane);
     const bool writer = (lane & 3) == 0;  // one lane per slot 0..15 of the record
+    // second order on a stretched mesh: the slope weights of this octant's
+    // direction along each axis, per cell index
+    const double* thxt = nullptr;
+    const double* thyt = nullptr;
+    const double* thzt = nullptr;
+    if constexpr (O2 && NU) {
+        thxt = A.theta + (px ? 0 : nx);
+        thyt = A.theta + 2 * nx + (py ? 0 : ny);
+        thzt = A.theta + 2 * nx + 2 * ny + (pz ? 0 : nz);
+    }
     const unsigned oridx = (unsigned)ridx * 8u;
     double* part = partial + ((size_t)(o * A.ntiles + tile) * A.N) * PREC;
 
@@ -1594,6 +1604,19 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
 
         const int cell = cell0 + ii * si + jj * sj + kk * sk;
         const PT* P = params + (size_t)cell * PSTRIDE;
+        // second order: the weight of this cell's own slope in the value
+        // it carries through its downstream face along each axis, h / (h +
+        // h_up) (1/2 on a uniform mesh), and that of the row behind along y
+        S thx = (S)0.5, thy = (S)0.5, thz = (S)0.5, thyb = (S)0.5;
+        if constexpr (O2 && NU) {
+            const int ri = px ? ir0 + ii : nx - 1 - (ir0 + ii);
+            const int rj = py ? jr0 + jj : ny - 1 - (jr0 + jj);
+            const int rk = pz ? kr0 + kk : nz - 1 - (kr0 + kk);
+            thx = (S)thxt[ri];
+            thy = (S)thyt[rj];
+            thz = (S)thzt[rk];
+            if (jj > 0) thyb = (S)thyt[py ? rj - 1 : rj + 1];
+        }
         if (!(info & SOLID_BIT)) {
             S fx[VL], fy[VL], fz[VL];
             S ux[VL], uy[VL], uz[VL];
@@ -1606,7 +1629,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
 #pragma unroll
                         for (int v = 0; v < VL; ++v) {
                             ux[v] = ii > 0 ? S(prev[v]) : S(fxp[v]);
-                            fx[v] = (ii > 0 ? S(prevF[v]) : S(gxp[v])) + (S)0.5 * ux[v];
+                            fx[v] = (ii > 0 ? S(prevF[v]) : S(gxp[v])) + thx * ux[v];
                         }
                     } else {
 #pragma unroll
@@ -1635,13 +1658,13 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                                 const S fu = lds(jj - 1, ii, v);
                                 const S f2 = jj >= 2 ? S(lds(jj - 2, ii, v)) : S(fyp[v]);
                                 uy[v] = fu;
-                                fy[v] = (edge ? fu : (S)1.5 * fu - (S)0.5 * f2) + (S)0.5 * fu;
+                                fy[v] = (edge ? fu : ((S)1 + thyb) * fu - thyb * f2) + thy * fu;
                             }
                         } else {
 #pragma unroll
                             for (int v = 0; v < VL; ++v) {
                                 uy[v] = fyp[v];
-                                fy[v] = gyp[v] + (S)0.5 * fyp[v];
+                                fy[v] = gyp[v] + thy * fyp[v];
                             }
                         }
                     } else if (jj > 0) {
@@ -1683,7 +1706,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
 #pragma unroll
                     for (int v = 0; v < VL; ++v) {
                         uz[v] = zl[v];
-                        fz[v] = zg[v] + (S)0.5 * uz[v];
+                        fz[v] = zg[v] + thz * uz[v];
                     }
                 } else if (O2 && code == CODE_SPECULAR) {
                     // the mirror image beyond the symmetry plane
@@ -1745,8 +1768,8 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
             double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
             double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // second order: sum w (F_d - f)
             S Fy[VL], Fz[VL];
-            const S kx = O2 && ixf ? (S)1.5 : (S)1, ky = O2 && iyf ? (S)1.5 : (S)1;
-            const S kz = O2 && izf ? (S)1.5 : (S)1;
+            const S kx = O2 && ixf ? (S)1 + thx : (S)1, ky = O2 && iyf ? (S)1 + thy : (S)1;
+            const S kz = O2 && izf ? (S)1 + thz : (S)1;
             const S ayk = ayc * ky, azk = azc * kz;
 #pragma unroll
             for (int v = 0; v < VL; ++v) {
@@ -1770,9 +1793,9 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                 S f;
                 if constexpr (O2) {
                     f = num * fast_rcp(axv * kx + ayk + azk + (S)nu);
-                    const S dx = ixf ? (S)0.5 * (f - ux[v]) : (S)0;
-                    const S dy = iyf ? (S)0.5 * (f - uy[v]) : (S)0;
-                    const S dz = izf ? (S)0.5 * (f - uz[v]) : (S)0;
+                    const S dx = ixf ? thx * (f - ux[v]) : (S)0;
+                    const S dy = iyf ? thy * (f - uy[v]) : (S)0;
+                    const S dz = izf ? thz * (f - uz[v]) : (S)0;
                     prevF[v] = f + dx;
                     Fy[v] = f + dy;
                     Fz[v] = f + dz;
@@ -1971,13 +1994,13 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 // second-order upwind and/or ES-BGK (uniform meshes), pipelined body
 // (occupancy: FP32 ES-BGK with 4 per lane fits 4 waves per SIMD without
 // spills in the loop; the FP64 and second-order forms would spill there)
-template <typename S, int VL, int BX, int BY, bool O2, bool ES>
+template <typename S, int VL, int BX, int BY, bool O2, bool ES, bool NU = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VL == 4 && !O2 && sizeof(S) == 4 ? 4 : 1)))
 void sweep_kernel_pfx(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
-    sweep_body_pf<S, VL, BX, BY, false, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.xface, A.yface, A.zface,
-                                                A.spec, A.partial, plane, diagonal_unit(A, A.bricks));
+    sweep_body_pf<S, VL, BX, BY, NU, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.xface, A.yface, A.zface,
+                                             A.spec, A.partial, plane, diagonal_unit(A, A.bricks));
 }
 
 // second-order upwind and/or ES-BGK (uniform meshes, plain body)
@@ -2009,7 +2032,9 @@ bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, i
 #define X(T, V, BXX, BYY) \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) return true;
     if (order2 || esbgk) {
-        if (nonuniform) return false;
+        // on a stretched mesh: the second-order Shakhov sweep, pipelined
+        // body (two or more velocities per lane)
+        if (nonuniform && (esbgk || vl < 2)) return false;
         DVM_SWEEP_VARIANTS_O2(X)
     } else if (nonuniform) {
         DVM_SWEEP_VARIANTS_NU(X)
@@ -2057,11 +2082,16 @@ hipError_t launch_sweep_t(int pipelined, const void* args, hipStream_t st)
 }
 
 template <typename T, int V, int BXX, int BYY>
-hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, const void* args, hipStream_t st)
+hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, int nonuniform, const void* args, hipStream_t st)
 {
     const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
     // the plane of f, and with the second order the plane of F along z
     const size_t lds = (size_t)(order2 ? 2 : 1) * BYY * BXX * V * 64 * sizeof(T);
+    if (nonuniform) {
+        if (!order2 || esbgk || !pipelined || V < 2) return hipErrorInvalidValue;
+        sweep_kernel_pfx<T, V, BXX, BYY, true, false, true><<<a.nblocks, 64, lds, st>>>(a);
+        return hipGetLastError();
+    }
     if (pipelined) {
         if (order2 && esbgk)
             sweep_kernel_pfx<T, V, BXX, BYY, true, true><<<a.nblocks, 64, lds, st>>>(a);
@@ -2094,10 +2124,9 @@ hipError_t launch_sweep(int prec, int vl, int bx, int by, int pipelined, int non
         return launch_sweep_t<float, 4, 4, 2, false, double>(pipelined, args, st);
     }
     if (order2 || esbgk) {
-        if (nonuniform) return hipErrorInvalidValue;
 #define X(T, V, BXX, BYY)                                                     \
         if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) \
-            return launch_sweep_x<T, V, BXX, BYY>(pipelined, order2, esbgk, args, st);
+            return launch_sweep_x<T, V, BXX, BYY>(pipelined, order2, esbgk, nonuniform, args, st);
         DVM_SWEEP_VARIANTS_O2(X)
 #undef X
         return hipErrorInvalidValue;

@@ -85,6 +85,7 @@ struct dvm_ctx {
     std::vector<double> vnode[3], vweight[3];
     std::vector<double> h[3];  // cell sizes along x, y, z (empty: uniform)
     std::vector<double> hstage;  // host copy of the uploaded sizes
+    std::vector<double> thstage; // host copy of the uploaded second-order slope weights
     bool nonuniform = false;
     int nbx = 0, nby = 0, nbz = 0;
     int ntiles = 0, slots = 0, lstride = 0;
@@ -106,7 +107,7 @@ struct dvm_ctx {
     struct {
         size_t axes, spacing, cellinfo, bricks, lanetab, kstate, ghat, ghat64, gout, W, q, rw, params, etab,
             partial, acc, xface, yface, zface, spec, xg, yg, zg, specg, stress, blockmass, respart, out, flag,
-            ready, head, end;
+            ready, head, theta, end;
     } off;
     size_t Ssz = 8;
     int nbF = 0;  // blocks of the per-cell kernels (256 threads)
@@ -358,6 +359,9 @@ void layout(dvm_ctx* c)
     c->off.flag = take(sizeof(int) * 4);
     c->off.ready = take(c->PF == 2 ? sizeof(unsigned) * 8 * (size_t)c->gtiles * c->nbx * c->nby * c->nbz : 0);
     c->off.head = take(c->PF == 2 ? sizeof(unsigned long long) : 0);
+    // second order on a stretched mesh: the slope weights per axis, direction and index
+    c->off.theta = take(c->order == 2 && c->nonuniform ? sizeof(double) * 2 * (size_t)(c->g.nx + c->g.ny + c->g.nz)
+                                                         : 0);
     c->off.end = o;
 }
 
@@ -592,6 +596,7 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.zgface = o2 ? c->P<S>(c->off.zg) : nullptr;
                 a.specg = o2 && c->spec_on ? c->P<S>(c->off.specg) : nullptr;
                 a.partial = c->P<double>(c->off.partial);
+                a.theta = c->order == 2 && c->nonuniform ? c->P<double>(c->off.theta) : nullptr;
                 a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.N = c->N;
                 a.mx = c->vg.m[0]; a.my = c->vg.m[1]; a.MT = C.MT; a.NV = c->NV;
                 a.rdx = c->nonuniform ? 1.0 : 1.0 / c->dx[0];
@@ -837,7 +842,6 @@ dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const
             c->h[d].assign(n3[d], c->dx[d]);
         }
     }
-    if (any && c->order == 2) return fail(DVM_ERR_ARG, "the second-order sweep needs a uniform mesh");
     if (any && c->model == 1) return fail(DVM_ERR_ARG, "the ES-BGK sweep needs a uniform mesh");
     c->nonuniform = any;
     derive_schedule(c);
@@ -925,7 +929,6 @@ dvm_status dvm_set_order(dvm_ctx* c, int order)
     if (check_ctx(c)) return DVM_ERR_ARG;
     if (c->bound) return fail(DVM_ERR_STATE, "the order must be set before binding the workspace");
     if (order != 1 && order != 2) return fail(DVM_ERR_ARG, "order must be 1 or 2 (got %d)", order);
-    if (order == 2 && c->nonuniform) return fail(DVM_ERR_ARG, "the second-order sweep needs a uniform mesh");
     c->order = order;
     derive_schedule(c);
     return DVM_OK;
@@ -1026,6 +1029,11 @@ dvm_status check_bindable(dvm_ctx* c)
     if (!c->fits32)
         return fail(DVM_ERR_ARG, "a face row of this grid and velocity set exceeds the 32-bit offsets of the "
                     "sweep even with one-cell brick columns: use more velocity groups");
+    if (!sweep_variant_available(c->prec, c->VL, c->BX, c->BY, c->nonuniform, c->order == 2, c->model == 1) ||
+        (c->order == 2 && c->nonuniform && c->PF != 1))
+        return fail(DVM_ERR_ARG, "no sweep kernel is built for %d velocities per lane, %dx%d bricks and body %d with "
+                    "this precision, mesh kind, order and model (a stretched mesh at second order takes the "
+                    "pipelined body with 2 or more velocities per lane)", c->VL, c->BX, c->BY, c->PF + 1);
     if (c->wide && (c->PF == 0 || !sweep_wide_params_available(c->prec, c->VL, c->BX, c->BY, c->nonuniform,
                                                                 c->order == 2, c->model == 1)))
         return fail(DVM_ERR_ARG, "FP64 parameters beside FP32 storage are built for the first-order Shakhov sweep "
@@ -1082,6 +1090,26 @@ dvm_status bind_impl(dvm_ctx* c, void* ptr, size_t bytes)
                               hipMemcpyHostToDevice, st));
     }
     HIPCHK(hipMemcpyAsync(c->ws + c->off.cellinfo, c->cellinfo.data(), sizeof(uint32_t) * c->N, hipMemcpyHostToDevice, st));
+    if (c->order == 2 && c->nonuniform) {
+        // the weight of a cell's own slope in the value it carries through
+        // its downstream face: the straight line through its centre and its
+        // upwind neighbour's, at the face, is f + theta (f - f_up) with
+        // theta = h / (h + h_up); per axis, the + direction (upwind i - 1)
+        // then the - direction (upwind i + 1); 1/2 where the upwind side is
+        // the box (a symmetry plane's mirror cell has the cell's own size)
+        std::vector<double>& th = c->thstage;
+        th.clear();
+        const int n3[3] = {c->g.nx, c->g.ny, c->g.nz};
+        for (int d = 0; d < 3; ++d)
+            for (int dir = 0; dir < 2; ++dir)
+                for (int i = 0; i < n3[d]; ++i) {
+                    const int up = dir == 0 ? i - 1 : i + 1;
+                    const double h = cell_size(c, d, i);
+                    th.push_back(up < 0 || up >= n3[d] ? 0.5 : h / (h + cell_size(c, d, up)));
+                }
+        HIPCHK(hipMemcpyAsync(c->ws + c->off.theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice,
+                              st));
+    }
     HIPCHK(hipMemcpyAsync(c->ws + c->off.bricks, c->bricks.data(), sizeof(int) * c->bricks.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(c->ws + c->off.lanetab, lt.data(), sizeof(double) * lt.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(c->ws + c->off.kstate, ks.data(), sizeof(double) * ks.size(), hipMemcpyHostToDevice, st));

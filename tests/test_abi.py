@@ -166,9 +166,10 @@ def test_velocity_groups_arguments_and_workspace(L):
 
 
 def test_order_arguments(L):
-    """dvm_set_order: 1 or 2, uniform meshes only, before binding; the
-    second order re-derives the schedule (FP64: 2 per lane, pipelined body)
-    and doubles the face buffers."""
+    """dvm_set_order: 1 or 2, before binding; the second order re-derives
+    the schedule (FP64: 2 per lane, pipelined body) and doubles the face
+    buffers; on a stretched mesh it adds the table of slope weights and
+    needs the pipelined body."""
     import numpy as np
     from paper_1810_00348_amd import cases
     lib = L.lib()
@@ -187,11 +188,16 @@ def test_order_arguments(L):
     assert n2.value > n1.value
     P = C.POINTER(C.c_double)
     hy = cases.stretched_axis(5, 1.0, 1.3)
-    assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(P), None) == -1
-    assert b"uniform" in lib.dvm_last_error()
-    assert lib.dvm_set_order(h, 1) == 0
     assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(P), None) == 0
-    assert lib.dvm_set_order(h, 2) == -1
+    n3 = C.c_size_t()
+    assert lib.dvm_required_workspace(h, C.byref(n3)) == 0
+    assert n3.value > n2.value
+    assert lib.dvm_set_order(h, 1) == 0
+    assert lib.dvm_set_order(h, 2) == 0
+    # the plain body has no stretched second-order form: binding refuses
+    assert lib.dvm_set_schedule(h, 0, 0, 0, 0, 1) == 0
+    assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 1 << 40) == -1
+    assert b"pipelined" in lib.dvm_last_error()
     lib.dvm_destroy(h)
 
 
