@@ -42,6 +42,17 @@
  *   - Call order: dvm_create -> dvm_set_face_bc / dvm_set_solid /
  *     dvm_set_closed -> dvm_required_workspace -> dvm_bind_workspace ->
  *     dvm_init_uniform | dvm_init_fields | dvm_set_state -> dvm_iterate ...
+ *
+ * Against the interface planned for this library the calls differ in
+ * these ways: dvm_set_solid_mask is also available as dvm_set_solid (the
+ * same call); dvm_init_fields takes the target total mass (double, 0 = keep
+ * the given density) where an integer flag normalised to the unit mass;
+ * dvm_get_state / dvm_set_state also carry M0, the reference mass of the
+ * closed-domain rescaling, so that a resumed run continues bit for bit;
+ * dvm_create takes the precision as int (a dvm_precision value) so that the
+ * ABI does not depend on the size of an enum; and the calls after
+ * dvm_set_velocity_groups (schedule, streams, parameter precision, the
+ * static workspace, stress, launch timings) are additions.
  */
 #ifndef DVM_H
 #define DVM_H

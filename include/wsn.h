@@ -27,6 +27,9 @@
  *   - base is a multiple of 8 in [8, 64].
  *   - Every call returns 0 on success, -1 on a bad argument, -4 on a HIP
  *     error; wsn_last_error() describes the failure.
+ *   - The number of levels is fixed at 3; wsn_create takes the channel
+ *     counts, the base width and the largest grid (where the planned
+ *     interface took levels and base).
  */
 #ifndef WSN_H
 #define WSN_H
@@ -62,6 +65,23 @@ int wsn_zero_grad(wsn_ctx* ctx);
 
 /* One Adam step (bias-corrected, step counter kept inside). */
 int wsn_adam_step(wsn_ctx* ctx, float lr, float beta1, float beta2, float eps);
+
+/* One training step over a batch of n grids: zero the gradient, forward and
+   masked-MSE backward of every item with weight 1/n (the batch's mean
+   loss), then one Adam step with learning rate lr (beta1 0.9, beta2 0.999,
+   eps 1e-8).  d_inputs[i] [D][H][W][cin], d_targets[i] [D][H][W][cout],
+   d_masks[i] [D][H][W] on the device, dims[3 i .. 3 i + 2] = (D, H, W) of
+   item i (host).  *host_loss (nullable) = the batch's mean loss before the
+   step. */
+int wsn_train_step(wsn_ctx* ctx, int n, const float* const* d_inputs, const float* const* d_targets,
+                   const float* const* d_masks, const int* dims, float lr, double* host_loss);
+
+/* Parameters and optimiser state (Adam moments and step count) to and from
+   a file: magic "WSNET001", int32 cin, cout, base, step, uint64 parameter
+   count, then the FP32 parameters, first and second moments.  wsn_load
+   refuses (-1) a file of another network shape. */
+int wsn_save(wsn_ctx* ctx, const char* path);
+int wsn_load(wsn_ctx* ctx, const char* path);
 
 /* Kernel-level checks for the tests: one 3x3x3 (taps = 27) or 1x1x1 (taps =
    1) convolution on BF16-rounded FP32 host arrays, through the same kernels

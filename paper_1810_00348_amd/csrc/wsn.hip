@@ -734,9 +734,20 @@ int wsn_zero_grad(wsn_ctx* c)
     return 0;
 }
 
+namespace {
+// the forward pass; out (nullable) takes a copy of the network output
+int forward_impl(wsn_ctx* c, const float* in, int D, int H, int W, float* out);
+}  // namespace
+
 int wsn_forward(wsn_ctx* c, const float* in, int D, int H, int W, float* out)
 {
     if (!c || !in || !out) return wfail(-1, "NULL");
+    return forward_impl(c, in, D, H, W, out);
+}
+
+namespace {
+int forward_impl(wsn_ctx* c, const float* in, int D, int H, int W, float* out)
+{
     if (D < 4 || H < 4 || W < 4 || D % 4 || H % 4 || W % 4 || D > c->maxD || H > c->maxH || W > c->maxW)
         return wfail(-1, "grid %dx%dx%d: must be multiples of 4 within the created maximum", D, H, W);
     c->D = D;
@@ -766,9 +777,10 @@ int wsn_forward(wsn_ctx* c, const float* in, int D, int H, int W, float* out)
     rc |= conv(c, lo, c->a10, b1, D, H, W, c->y, c->cout, nullptr, 0, c->cout, false, lo.w, lo.cip, lo.cop);
     if (rc) return rc;
     WCHK(hipGetLastError());
-    WCHK(hipMemcpyAsync(out, c->y, sizeof(float) * V1 * c->cout, hipMemcpyDeviceToDevice, c->st));
+    if (out) WCHK(hipMemcpyAsync(out, c->y, sizeof(float) * V1 * c->cout, hipMemcpyDeviceToDevice, c->st));
     return 0;
 }
+}  // namespace
 
 int wsn_backward_mse(wsn_ctx* c, const float* target, const float* mask, float weight, double* host_loss)
 {
@@ -823,6 +835,75 @@ int wsn_adam_step(wsn_ctx* c, float lr, float b1, float b2, float eps)
     adam_kernel<<<nblk(c->np), 256, 0, c->st>>>(c->th, c->m, c->v, c->g, c->np, lr, b1, b2, eps, c1, c2);
     WCHK(hipGetLastError());
     return pack_all(c);
+}
+
+int wsn_train_step(wsn_ctx* c, int n, const float* const* inputs, const float* const* targets,
+                   const float* const* masks, const int* dims, float lr, double* host_loss)
+{
+    if (!c || n < 1 || !inputs || !targets || !masks || !dims) return wfail(-1, "NULL or empty batch");
+    for (int i = 0; i < n; ++i)
+        if (!inputs[i] || !targets[i] || !masks[i]) return wfail(-1, "batch item %d: NULL array", i);
+    int rc = wsn_zero_grad(c);
+    if (rc) return rc;
+    double loss = 0.0;
+    for (int i = 0; i < n; ++i) {
+        rc = forward_impl(c, inputs[i], dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], nullptr);
+        if (rc) return rc;
+        rc = wsn_backward_mse(c, targets[i], masks[i], 1.0f / (float)n, &loss);
+        if (rc) return rc;
+    }
+    rc = wsn_adam_step(c, lr, 0.9f, 0.999f, 1e-8f);
+    if (rc) return rc;
+    if (host_loss) *host_loss = loss;
+    return 0;
+}
+
+namespace {
+constexpr char kWsnMagic[8] = {'W', 'S', 'N', 'E', 'T', '0', '0', '1'};
+}
+
+int wsn_save(wsn_ctx* c, const char* path)
+{
+    if (!c || !path) return wfail(-1, "NULL");
+    std::vector<float> buf(3 * c->np);
+    WCHK(hipMemcpyAsync(buf.data(), c->th, sizeof(float) * c->np, hipMemcpyDeviceToHost, c->st));
+    WCHK(hipMemcpyAsync(buf.data() + c->np, c->m, sizeof(float) * c->np, hipMemcpyDeviceToHost, c->st));
+    WCHK(hipMemcpyAsync(buf.data() + 2 * c->np, c->v, sizeof(float) * c->np, hipMemcpyDeviceToHost, c->st));
+    WCHK(hipStreamSynchronize(c->st));
+    FILE* f = fopen(path, "wb");
+    if (!f) return wfail(-1, "cannot open %s for writing", path);
+    const int32_t hdr[4] = {c->cin, c->cout, c->base, c->step};
+    const uint64_t np = c->np;
+    bool ok = fwrite(kWsnMagic, 1, 8, f) == 8 && fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+              fwrite(&np, sizeof np, 1, f) == 1 && fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return wfail(-1, "writing %s failed", path);
+    return 0;
+}
+
+int wsn_load(wsn_ctx* c, const char* path)
+{
+    if (!c || !path) return wfail(-1, "NULL");
+    FILE* f = fopen(path, "rb");
+    if (!f) return wfail(-1, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[4];
+    uint64_t np = 0;
+    std::vector<float> buf(3 * c->np);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kWsnMagic, 8) == 0 && fread(hdr, sizeof hdr, 1, f) == 1 &&
+              fread(&np, sizeof np, 1, f) == 1;
+    if (ok && (hdr[0] != c->cin || hdr[1] != c->cout || hdr[2] != c->base || np != c->np)) {
+        fclose(f);
+        return wfail(-1, "%s holds a network (cin %d, cout %d, base %d, %llu parameters) of another shape", path,
+                     hdr[0], hdr[1], hdr[2], (unsigned long long)np);
+    }
+    ok = ok && fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok) return wfail(-1, "%s is not a complete network file", path);
+    WCHK(hipMemcpyAsync(c->m, buf.data() + c->np, sizeof(float) * c->np, hipMemcpyHostToDevice, c->st));
+    WCHK(hipMemcpyAsync(c->v, buf.data() + 2 * c->np, sizeof(float) * c->np, hipMemcpyHostToDevice, c->st));
+    c->step = hdr[3];
+    return wsn_set_params(c, buf.data());
 }
 
 int wsn_test_conv(int D, int H, int W, int ci, int co, int taps, const float* x, const float* w, const float* b,

@@ -51,6 +51,10 @@ def wsn_lib():
                                   C.POINTER(C.c_double)], C.c_int),
             "wsn_zero_grad": ([C.c_void_p], C.c_int),
             "wsn_adam_step": ([C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+            "wsn_train_step": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                C.POINTER(C.c_double)], C.c_int),
+            "wsn_save": ([C.c_void_p, C.c_char_p], C.c_int),
+            "wsn_load": ([C.c_void_p, C.c_char_p], C.c_int),
             "wsn_test_conv": ([C.c_int] * 6 + [C.c_void_p] * 8, C.c_int),
             "wsn_selftest_mfma": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
             "wsn_last_error": ([], C.c_char_p),
@@ -136,6 +140,24 @@ class WarmStartNet:
 
     def adam_step(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
         _chk(wsn_lib().wsn_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def train_step(self, batch, lr: float) -> float:
+        """One step over ``batch`` = [(x, target, mask), ...] of device
+        tensors (see wsn_train_step); returns the batch's mean loss."""
+        n = len(batch)
+        ins = (C.c_void_p * n)(*[_P(x) for x, _, _ in batch])
+        tgs = (C.c_void_p * n)(*[_P(t) for _, t, _ in batch])
+        mks = (C.c_void_p * n)(*[_P(m) for _, _, m in batch])
+        dims = (C.c_int * (3 * n))(*[d for x, _, _ in batch for d in x.shape[:3]])
+        loss = C.c_double(0.0)
+        _chk(wsn_lib().wsn_train_step(self._h, n, ins, tgs, mks, dims, lr, C.byref(loss)))
+        return loss.value
+
+    def save(self, path: str):
+        _chk(wsn_lib().wsn_save(self._h, path.encode()))
+
+    def load(self, path: str):
+        _chk(wsn_lib().wsn_load(self._h, path.encode()))
 
 
 # ------------------------------------------------------------------ data

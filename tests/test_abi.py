@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(L):
 def test_every_warm_start_symbol_is_exported(L):
     lib = L.lib()
     syms = declared_symbols("wsn.h", "wsn_")
-    assert len(syms) == 13, syms
+    assert len(syms) == 16, syms
     for s in syms:
         assert hasattr(lib, s), s
     assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["dvm.h", "wsn.h"]

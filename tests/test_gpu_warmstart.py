@@ -221,6 +221,50 @@ def test_adam_kernel_matches_reference():
         assert np.abs(got - theta).max() > 0.5 * lr
 
 
+
+def test_train_step_and_save_load(tmp_path):
+    """wsn_train_step equals its parts (zero grad, forward and weighted
+    backward per item, one Adam step) bit for bit; wsn_save / wsn_load
+    carry parameters and Adam state, so a restored network takes the same
+    next step; a file of another network shape is refused."""
+    ws = _ws()
+    import torch
+    specs = U.layer_specs(3, 5, 8)
+    theta = U.init_params(specs, seed=31).astype(np.float32)
+    rng = np.random.default_rng(32)
+    dev = torch.device("cuda")
+    batch = []
+    for shape in ((8, 8, 8), (4, 8, 4)):
+        x = torch.from_numpy(rng.standard_normal(shape + (3,)).astype(np.float32)).to(dev)
+        t = torch.from_numpy(rng.standard_normal(shape + (5,)).astype(np.float32)).to(dev)
+        m = torch.from_numpy((rng.random(shape) > 0.2).astype(np.float32)).to(dev)
+        batch.append((x, t, m))
+    a = ws.WarmStartNet(max_grid=(8, 8, 8), base=8, cin=3)
+    b = ws.WarmStartNet(max_grid=(8, 8, 8), base=8, cin=3)
+    a.set_params(theta)
+    b.set_params(theta)
+    loss_a = a.train_step(batch, 1e-3)
+    b.zero_grad()
+    loss_b = 0.0
+    for x, t, m in batch:
+        b.forward(x)
+        loss_b += b.backward_mse(t, m, 1.0 / len(batch))
+    b.adam_step(1e-3)
+    assert np.array_equal(a.params(), b.params())
+    assert loss_a == loss_b and loss_a > 0
+    path = str(tmp_path / "net.wsn")
+    a.save(path)
+    c = ws.WarmStartNet(max_grid=(8, 8, 8), base=8, cin=3)
+    c.load(path)
+    assert np.array_equal(c.params(), a.params())
+    a.train_step(batch, 1e-3)
+    c.train_step(batch, 1e-3)
+    assert np.array_equal(c.params(), a.params())
+    d = ws.WarmStartNet(max_grid=(8, 8, 8), base=16, cin=3)
+    with pytest.raises(RuntimeError):
+        d.load(path)
+
+
 WEIGHTS = os.path.join(ROOT, "paper_1810_00348_amd", "data", "warmstart_unet.npz")
 
 
