@@ -277,22 +277,30 @@ def test_trained_warm_start_gains_over_uniform_start():
     if not os.path.exists(WEIGHTS):
         pytest.skip("no trained weights yet: python -m paper_1810_00348_amd.warmstart --out DIR")
     theta, chan_std, meta = ws.load_weights(WEIGHTS)
-    held = sorted(ws.heldout_cases(), key=lambda c: c.ncells * c.nvel)[:4]
+    # all 32 held-out cavities (uneven spatial sizes, Kn 0.05 - 10)
+    held = ws.heldout_cases()
+    assert len(held) == 32
     big = max(max(c.n) for c in held)
     net = ws.WarmStartNet(max_grid=(big, big, big))
     net.set_params(theta)
     plain_total = warm_total = 0
+    plain_s = warm_s = 0.0
     for c in held:
         plain = ws.solve(c, tol=1e-6, max_iters=4000)
         warm = ws.warm_started_solve(net, c, chan_std, tol=1e-6, max_iters=4000)
         assert plain["converged"] and warm["converged"] and not warm["fallback"], c.name
         assert warm["residual"] <= 1e-6
         diff = ws.field_difference(warm["fields"], plain["fields"])
-        print(c.name, c.kn, plain["iters"], warm["iters"], diff)
+        print(c.name, c.kn, plain["iters"], warm["iters"], diff, flush=True)
         assert max(diff.values()) < 2e-3, (c.name, diff)
         plain_total += plain["iters"]
         warm_total += warm["iters"]
-    # the bound a perfect prediction of rho, U, T reaches on such cases is
-    # about 25 % fewer iterations (the non-equilibrium part of f and the wall
-    # densities still have to develop)
+        plain_s += plain["seconds"]
+        warm_s += warm["seconds"]
+    print("iterations", plain_total, warm_total, "seconds", plain_s, warm_s)
+    # the bound a perfect prediction of rho, U, T reaches on these cases is
+    # 25 % fewer iterations (965 against 1282, seeding with the plain
+    # solve's own converged fields): the non-equilibrium part of f and the
+    # wall densities still have to develop
     assert warm_total <= 0.85 * plain_total, (warm_total, plain_total)
+    assert warm_s <= 0.9 * plain_s, (warm_s, plain_s)
