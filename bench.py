@@ -157,7 +157,7 @@ def summarize_trace(db_path: str, out_md: str, title: str, command: str, bench_j
         lines += ["", f"The bench line printed by the same profiled command: {d['value']} GPt/s, "
                   f"{d['ms_per_step']} ms per iteration, sweep phase {d['config']['phase_ms']['sweep']} ms per "
                   f"iteration by HIP events over the {iters} timed iterations (the trace above also holds the "
-                  f"{d['warmup']} warm-up iterations)."]
+                  f"{d['warmup']} warm-up iterations and the 3 iterations of the per-launch timing pass)."]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))

@@ -29,7 +29,9 @@ namespace dvm {
 // --------------------------------------------------------------------------
 
 // Reciprocal of a positive normal number: hardware estimate refined by Newton
-// steps (each squares the relative error: two for FP64, one for FP32).
+// steps (each squares the relative error: two for FP64, one for FP32; the
+// FP32 estimate alone is biased enough to move the FP32 form's fixed point
+// by 3-5x its rounding-level distance from the FP64 one).
 __device__ __forceinline__ double fast_rcp(double d)
 {
     double r = __builtin_amdgcn_rcp(d);
@@ -41,7 +43,7 @@ __device__ __forceinline__ double fast_rcp(double d)
 
 __device__ __forceinline__ float fast_rcp(float d)
 {
-    float r = __builtin_amdgcn_rcpf(d);
+    const float r = __builtin_amdgcn_rcpf(d);
     const float e = fmaf(-d, r, 1.0f);
     return fmaf(r, e, r);
 }
@@ -147,61 +149,87 @@ __device__ bool correction_lambda(const double Mx[6], const double My[6], const 
 // --------------------------------------------------------------------------
 
 template <typename S>
-__global__ __launch_bounds__(128) void params_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
-                                                     const double* __restrict__ q,
-                                                     const double* __restrict__ rho_w, S* __restrict__ params,
-                                                     S* __restrict__ etab, int* __restrict__ flag)
+__device__ __forceinline__ S info_bits(uint32_t info)
 {
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= C.N) return;
-    const uint32_t info = D.cellinfo[cell];
-    reinterpret_cast<uint32_t*>(params + (size_t)cell * PSTRIDE + P_INFO)[0] = info;
-    if (info & SOLID_BIT) return;
-    {
+    // the info word as the bit pattern of a record slot (its low 32 bits)
+    if constexpr (sizeof(S) == 8)
+        return __hiloint2double(0, (int)info);
+    else
+        return __int_as_float((int)info);
+}
+
+// One wave per 64 consecutive cells, one lane per cell.  A cell's record
+// (PSTRIDE slots) and Gaussian tables (MT entries) are rows; the wave stages
+// its rows in LDS and writes them out with consecutive lanes on consecutive
+// entries, 32 table entries of an axis at a time, so that every store
+// instruction covers whole cache lines (a lane writing its own row would
+// touch 64 lines per instruction).  Solid cells get the info word and zeros.
+constexpr int PCH = 32;  // table entries per staged chunk
+template <typename S>
+__global__ __launch_bounds__(64) void params_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
+                                                    const double* __restrict__ q,
+                                                    const double* __restrict__ rho_w, S* __restrict__ params,
+                                                    S* __restrict__ etab, int* __restrict__ flag)
+{
+    __shared__ S stage[64 * (PCH + 1)];
+    static_assert(PCH + 1 >= PSTRIDE, "a record fits a staged row");
+    const int lane = threadIdx.x;
+    const int N = C.N;
+    const int c0 = blockIdx.x * 64;
+    const int nrow = min(64, N - c0);
+    const int cell = c0 + lane;
+    const bool live = lane < nrow;
+    const uint32_t info = live ? D.cellinfo[cell] : SOLID_BIT;
+    const bool fluid = !(info & SOLID_BIT);
+    S rec[PSTRIDE];
+#pragma unroll
+    for (int k = 0; k < PSTRIDE; ++k) rec[k] = (S)0;
+    rec[P_INFO] = info_bits<S>(info);
+    bool eq = false;  // the equilibrium parameters are computed
+    double rho = 1.0, Ux = 0.0, Uy = 0.0, Uz = 0.0, T = 1.0;
+    if (fluid) {
         // inverse cell sizes (the upwind coefficients |xi_d| / h_d of a
         // non-uniform mesh)
-        S* P = params + (size_t)cell * PSTRIDE;
         const int i = cell % C.nx, j = (cell / C.nx) % C.ny, k = cell / (C.nx * C.ny);
-        P[P_IDX] = (S)(1.0 / D.h[i]);
-        P[P_IDY] = (S)(1.0 / D.h[C.nx + j]);
-        P[P_IDZ] = (S)(1.0 / D.h[C.nx + C.ny + k]);
-    }
-    {
+        rec[P_IDX] = (S)(1.0 / D.h[i]);
+        rec[P_IDY] = (S)(1.0 / D.h[C.nx + j]);
+        rec[P_IDZ] = (S)(1.0 / D.h[C.nx + C.ny + k]);
         // inflow density of each side: the wall density of iteration n at a
         // diffuse wall, the free-stream density at a free-stream face
-        S* P = params + (size_t)cell * PSTRIDE;
-        for (int s = 0; s < 6; ++s) {
-            const uint32_t code = (info >> (4 * s)) & 15u;
+        for (int sd = 0; sd < 6; ++sd) {
+            const uint32_t code = (info >> (4 * sd)) & 15u;
             double rf = 0.0;
             if (code != 0 && code != CODE_SPECULAR)
-                rf = C.kind_wall[code - 1] ? rho_w[(size_t)s * C.N + cell] : C.kind_rho[code - 1];
-            P[P_RHO_SIDE + s] = (S)rf;
+                rf = C.kind_wall[code - 1] ? rho_w[(size_t)sd * N + cell] : C.kind_rho[code - 1];
+            rec[P_RHO_SIDE + sd] = (S)rf;
+        }
+        rho = W[cell];
+        Ux = W[N + cell] / rho;
+        Uy = W[2 * N + cell] / rho;
+        Uz = W[3 * N + cell] / rho;
+        T = (W[4 * N + cell] - 0.5 * rho * (Ux * Ux + Uy * Uy + Uz * Uz)) / (0.75 * rho);
+        eq = rho > 0.0 && T > 0.0 && isfinite(Ux) && isfinite(Uy) && isfinite(Uz) && isfinite(T);
+        if (!eq) {
+            // neutral equilibrium parameters (zero tables); the info word,
+            // inverse sizes and inflow densities stay
+            atomicOr(flag, 1);
+            rec[P_NU] = (S)1;
         }
     }
-    const int N = C.N;
-    const double rho = W[cell];
-    const double Ux = W[N + cell] / rho, Uy = W[2 * N + cell] / rho, Uz = W[3 * N + cell] / rho;
-    const double T = (W[4 * N + cell] - 0.5 * rho * (Ux * Ux + Uy * Uy + Uz * Uz)) / (0.75 * rho);
-    S* P = params + (size_t)cell * PSTRIDE;
-    S* E = etab + (size_t)cell * C.MT;
-    if (!(rho > 0.0) || !(T > 0.0) || !isfinite(Ux) || !isfinite(Uy) || !isfinite(Uz) ||
-        !isfinite(T)) {
-        atomicOr(flag, 1);
-        // neutral equilibrium parameters; the info word, inverse sizes and
-        // inflow densities written above stay
-        for (int k = 0; k < P_INFO; ++k) P[k] = (S)0;
-        P[P_NU] = (S)1;
-        for (int k = 0; k < C.MT; ++k) E[k] = (S)0;
-        return;
+    double qx = 0.0, qy = 0.0, qz = 0.0, nu = 0.0, pre = 0.0, sig = 0.0, invT = 1.0;
+    if (eq) {
+        qx = q[cell];
+        qy = q[N + cell];
+        qz = q[2 * N + cell];
+        nu = rho * pow(T, 1.0 - C.omega) / C.kappa_kn;
+        pre = rho * pow(M_PI * T, -1.5);
+        sig = (1.0 - C.pr) * 4.0 / (5.0 * rho * T * T);
+        invT = 1.0 / T;
     }
-    const double qx = q[cell], qy = q[N + cell], qz = q[2 * N + cell];
-    const double nu = rho * pow(T, 1.0 - C.omega) / C.kappa_kn;
-    const double pre = rho * pow(M_PI * T, -1.5);
-    const double sig = (1.0 - C.pr) * 4.0 / (5.0 * rho * T * T);
-    const double invT = 1.0 / T;
     double Mx[6], My[6], Mz[6];
     const double U3[3] = {Ux, Uy, Uz};
     const int m3[3] = {C.mx, C.my, C.mz};
+    const int ce = lane & (PCH - 1), half = lane / PCH;
     int off = 0;
     for (int d = 0; d < 3; ++d) {
         double* M = d == 0 ? Mx : d == 1 ? My : Mz;
@@ -209,50 +237,72 @@ __global__ __launch_bounds__(128) void params_kernel(Consts C, DevPtrs D, const 
         const double scale = d == 2 ? nu * pre : 1.0;
         const double* xi = D.xi + d * MAXM;
         const double* wt = D.wt + d * MAXM;
-        for (int a = 0; a < m3[d]; ++a) {
-            const double c = xi[a] - U3[d];
-            const double g = exp(-c * c * invT);
-            E[off + a] = (S)(g * scale);
-            double t = wt[a] * g;
+        for (int a0 = 0; a0 < m3[d]; a0 += PCH) {
+            const int len = min(PCH, m3[d] - a0);
+            for (int e = 0; e < len; ++e) {
+                const int a = a0 + e;
+                S ev = (S)0;
+                if (eq) {
+                    const double c = xi[a] - U3[d];
+                    const double g = exp(-c * c * invT);
+                    ev = (S)(g * scale);
+                    double t = wt[a] * g;
 #pragma unroll
-            for (int p = 0; p < 6; ++p) {
-                M[p] += t;
-                t *= c;
+                    for (int p = 0; p < 6; ++p) {
+                        M[p] += t;
+                        t *= c;
+                    }
+                }
+                stage[lane * (PCH + 1) + e] = ev;
             }
+            __syncthreads();
+            if (ce < len) {
+                for (int r = half; r < nrow; r += 64 / PCH)
+                    etab[(size_t)(c0 + r) * C.MT + off + a0 + ce] = stage[r * (PCH + 1) + ce];
+            }
+            __syncthreads();
         }
         off += m3[d];
     }
-    double lam[5] = {0, 0, 0, 0, 0};
-    if (C.correct) {
-        if (!correction_lambda(Mx, My, Mz, pre, rho, T, sig, qx, qy, qz, lam)) {
-            atomicOr(flag, 2);
+    if (eq) {
+        double lam[5] = {0, 0, 0, 0, 0};
+        if (C.correct) {
+            if (!correction_lambda(Mx, My, Mz, pre, rho, T, sig, qx, qy, qz, lam)) {
+                atomicOr(flag, 2);
+            }
         }
+        rec[P_NU] = (S)nu;
+        rec[P_UX] = (S)Ux;
+        rec[P_UY] = (S)Uy;
+        rec[P_UZ] = (S)Uz;
+        rec[P_L0] = (S)(1.0 + lam[0]);
+        rec[P_L1] = (S)lam[1];
+        rec[P_L2] = (S)lam[2];
+        rec[P_L3] = (S)lam[3];
+        rec[P_L4] = (S)lam[4];
+        rec[P_QX] = (S)(sig * qx);
+        rec[P_QY] = (S)(sig * qy);
+        rec[P_QZ] = (S)(sig * qz);
+        rec[P_TWO_T] = (S)(2.0 * invT);
     }
-    P[P_NU] = (S)nu;
-    P[P_UX] = (S)Ux;
-    P[P_UY] = (S)Uy;
-    P[P_UZ] = (S)Uz;
-    P[P_L0] = (S)(1.0 + lam[0]);
-    P[P_L1] = (S)lam[1];
-    P[P_L2] = (S)lam[2];
-    P[P_L3] = (S)lam[3];
-    P[P_L4] = (S)lam[4];
-    P[P_QX] = (S)(sig * qx);
-    P[P_QY] = (S)(sig * qy);
-    P[P_QZ] = (S)(sig * qz);
-    P[P_TWO_T] = (S)(2.0 * invT);
+    // the block's records are one contiguous run of nrow * PSTRIDE slots
+#pragma unroll
+    for (int k = 0; k < PSTRIDE; ++k) stage[lane * PSTRIDE + k] = rec[k];
+    __syncthreads();
+    S* out = params + (size_t)c0 * PSTRIDE;
+    for (int idx = lane; idx < nrow * PSTRIDE; idx += 64) out[idx] = stage[idx];
 }
 
 hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, const double* q,
                          const double* rho_w, void* params, void* etab, int prec, int* flag,
                          hipStream_t st)
 {
-    const int tpb = 128;
-    const int nb = (C.N + tpb - 1) / tpb;
+    // one wave per 64 cells (the kernel stages its rows in LDS per wave)
+    const int nb = (C.N + 63) / 64;
     if (prec == 0)
-        params_kernel<double><<<nb, tpb, 0, st>>>(C, D, W, q, rho_w, (double*)params, (double*)etab, flag);
+        params_kernel<double><<<nb, 64, 0, st>>>(C, D, W, q, rho_w, (double*)params, (double*)etab, flag);
     else
-        params_kernel<float><<<nb, tpb, 0, st>>>(C, D, W, q, rho_w, (float*)params, (float*)etab, flag);
+        params_kernel<float><<<nb, 64, 0, st>>>(C, D, W, q, rho_w, (float*)params, (float*)etab, flag);
     return hipGetLastError();
 }
 
@@ -1519,12 +1569,6 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
     S pFy[VL], pFz[VL];
 #pragma unroll
     for (int v = 0; v < VL; ++v) pFy[v] = pFz[v] = (S)0;
-    // first order: the values the last flush stored, kept allocated until
-    // the next cell's wait (the second-order form has no registers for it)
-    S sd[VL];
-    double sdt = 0.0;
-#pragma unroll
-    for (int v = 0; v < VL; ++v) sd[v] = (S)0;
     auto flush_faces = [&]() {
         if (pcell < 0) return;
         if (pii == BX - 1 && wx) {
@@ -1558,11 +1602,6 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
         if (pcell >= 0 && writer) stb_nt(part + (size_t)pcell * PREC, oridx, ptot);
     };
     auto flush = [&]() {
-        if constexpr (!O2) {
-#pragma unroll
-            for (int v = 0; v < VL; ++v) sd[v] = prev[v];
-            sdt = ptot;
-        }
         flush_faces();
         flush_partial();
     };
@@ -1592,15 +1631,6 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
         // counters left alone): nothing issued before this point is waited
         // for later in the cell
         wait_vector_memory();
-        // the data registers of the previous cell's stores stay allocated
-        // until here, where those stores are known to be done: reusing one
-        // earlier would wait for the stores and, the counter being in order,
-        // for the loads issued after them
-        if constexpr (!O2) {
-#pragma unroll
-            for (int v = 0; v < VL; ++v) keep_alive(sd[v]);
-            keep_alive(sdt);
-        }
 
         const int cell = cell0 + ii * si + jj * sj + kk * sk;
         const PT* P = params + (size_t)cell * PSTRIDE;
