@@ -106,14 +106,19 @@ def _ragged_cases():
     c = cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=10, vmax=7.0, mach=2.0, kn=0.5)
     d = dataclasses.replace(cases.cavity((8, 8, 8), 16, kn=10.0, lid=0.16), correction=False)
     e = cases.cavity((6, 5, 9), 12, kn=0.1, lid=0.5, pr=1.0)            # BGK
-    return {"ragged": a, "oddM": b, "cube": c, "nocorr": d, "bgk": e}
+    # more than 32 nodes per axis (the parameter pass writes each axis's
+    # Gaussian table in chunks of 32) on a cell count that is no multiple
+    # of 64 (its waves cover 64 cells each); with solid cells
+    f = cases.cavity((7, 6, 5), 36, kn=0.5, lid=0.3)
+    g = cases.cube_half(nx=10, ny=8, nz=7, edge=4, x0=3, m=34, vmax=9.0, mach=3.0, kn=0.5)
+    return {"ragged": a, "oddM": b, "cube": c, "nocorr": d, "bgk": e, "wide": f, "cube_wide": g}
 
 
-@pytest.mark.parametrize("name", ["ragged", "oddM", "cube", "nocorr", "bgk"])
+@pytest.mark.parametrize("name", ["ragged", "oddM", "cube", "nocorr", "bgk", "wide", "cube_wide"])
 def test_small_cases_match_oracle(oracle_mod, name):
     case = _ragged_cases()[name]
     init = None
-    if name in ("ragged", "bgk"):
+    if name in ("ragged", "bgk", "wide"):
         init = cases.random_fields(case, seed=7)
     s, o = run_pair(case, 3, oracle_mod, init=init)
     err = field_errors(s.fields(), o.fields())
