@@ -817,6 +817,25 @@ __device__ __forceinline__ void stb(T* base, unsigned off, T v)
 {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
+// gather through a raw buffer resource made from the (wave-uniform) base:
+// the resource in SGPRs plus the 32-bit lane offset, no per-lane 64-bit
+// address arithmetic (a plain load adds the lane offset, held as a 64-bit
+// register pair, to the base for every gather)
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, unsigned off)
+{
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, -1, 0x00020000);
+    T v;
+    if constexpr (sizeof(T) == 8) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        __builtin_memcpy(&v, &w, 8);
+    } else {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        __builtin_memcpy(&v, &w, 4);
+    }
+    return v;
+}
 // wait until no vector-memory load or store of this wave is outstanding,
 // leaving the other counters alone: s_waitcnt with vmcnt 0 (bits 3:0 and
 // 15:14), expcnt 7 (bits 6:4) and lgkmcnt 15 (bits 11:8), i.e. no wait on
@@ -1537,10 +1556,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
         nu_n = Pn[P_NU];
         info_n = reinterpret_cast<const uint32_t*>(Pn + P_INFO)[0];
         const PT* E = etab + (size_t)cn * MT;
-        eb_n = ldb(E, ob);
-        ec_n = ldb(E, oc);
+        eb_n = ldg(E, ob);
+        ec_n = ldg(E, oc);
 #pragma unroll
-        for (int v = 0; v < VL; ++v) ex_n[v] = ldb(E, oa[v]);
+        for (int v = 0; v < VL; ++v) ex_n[v] = ldg(E, oa[v]);
         if (ii == 0 && ir0 > 0) {
             load_face<COH>(xin, (unsigned)(kk * ny + jj) * rowb, lofs, fx_n);
             if constexpr (O2) load_face<COH>(xgin, (unsigned)(kk * ny + jj) * rowb, lofs, gx_n);
@@ -1669,7 +1688,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                     const S rf = (S)P[P_RHO_SIDE + sideX];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fx[v] = rf * ldb(g, oal[v]);
+                    for (int v = 0; v < VL; ++v) fx[v] = rf * ldg(g, oal[v]);
                 }
             }
             {
@@ -1698,8 +1717,14 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                             }
                         }
                     } else if (jj > 0) {
+                        // the row behind as an opaque scalar: its values
+                        // are then read at small positive offsets from one
+                        // address (derived from this row's address, they
+                        // would sit at negative offsets, one address each)
+                        int rowy = (jj - 1) * BX + ii;
+                        asm("" : "+s"(rowy));
 #pragma unroll
-                        for (int v = 0; v < VL; ++v) fy[v] = lds(jj - 1, ii, v);
+                        for (int v = 0; v < VL; ++v) fy[v] = plane[(rowy * VL + v) * 64 + lane];
                     } else {
 #pragma unroll
                         for (int v = 0; v < VL; ++v) fy[v] = fyp[v];
@@ -1708,7 +1733,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                     const S rf = (S)P[P_RHO_SIDE + sideY];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fy[v] = rf * ldb(g, oal[v]);
+                    for (int v = 0; v < VL; ++v) fy[v] = rf * ldg(g, oal[v]);
                 }
             }
             {
@@ -1763,7 +1788,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                     const S rf = (S)P[P_RHO_SIDE + sideZ];
                     const S* g = ghat + (size_t)(code - 1) * A.NV;
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) fz[v] = rf * ldb(g, oal[v]);
+                    for (int v = 0; v < VL; ++v) fz[v] = rf * ldg(g, oal[v]);
                 }
             }
 
