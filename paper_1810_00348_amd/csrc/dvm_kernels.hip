@@ -1488,6 +1488,12 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
     // mesh, whose cells bring their own inverse size): fewer live registers
     S xix[VL];
     double xd[VL], wd[VL];
+    // first order, FP32 storage: the lane's x-moment weights w, w xi_x,
+    // w xi_x^2, w xi_x^3 of each velocity, so that each moment sum takes one
+    // FMA per velocity (FP64 storage gains nothing from it, being bound by
+    // memory, and its dependency-driven form has no registers left for it)
+    constexpr bool WP = !O2 && !PD && sizeof(S) == 4;
+    double wx1[VL], wx2[VL], wx3[VL];
     unsigned oa[VL], oal[VL];
 #pragma unroll
     for (int v = 0; v < VL; ++v) {
@@ -1497,6 +1503,9 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
         xix[v] = (S)xd[v];
         oa[v] = (unsigned)a * PB;
         oal[v] = (unsigned)(a + A.mx * (vb + A.my * vc)) * SB;
+        wx1[v] = wd[v] * xd[v];
+        wx2[v] = wx1[v] * xd[v];
+        wx3[v] = wx2[v] * xd[v];
     }
     const unsigned ob = (unsigned)(A.mx + vb) * PB, oc = (unsigned)(A.mx + A.my + vc) * PB;
     const S sgx = px ? (S)A.rdx : -(S)A.rdx;
@@ -1863,13 +1872,21 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                 }
                 prev[v] = f;
                 lds(jj, ii, v) = f;
-                const double t0 = wd[v] * (double)f;
-                const double t1 = t0 * xd[v];
-                const double t2 = t1 * xd[v];
-                u0 += t0;
-                u1 += t1;
-                u2 += t2;
-                u3 += t2 * xd[v];
+                if constexpr (WP) {
+                    const double fd = (double)f;
+                    u0 = fma(wd[v], fd, u0);
+                    u1 = fma(wx1[v], fd, u1);
+                    u2 = fma(wx2[v], fd, u2);
+                    u3 = fma(wx3[v], fd, u3);
+                } else {
+                    const double t0 = wd[v] * (double)f;
+                    const double t1 = t0 * xd[v];
+                    const double t2 = t1 * xd[v];
+                    u0 += t0;
+                    u1 += t1;
+                    u2 += t2;
+                    u3 += t2 * xd[v];
+                }
             }
             if constexpr (O2) {
                 // second order: the previous cell's moment record and this
