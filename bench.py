@@ -36,6 +36,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -56,15 +57,17 @@ TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
 def kernel_sha() -> str:
-    """Hash of the sweep kernel's source: the wave reduction, the sweep
-    bodies and kernels (up to the list of instantiated variants) and the
-    shared layout header; a measured traffic file is used only while this
-    matches."""
+    """Hash of the sweep kernel's code: the wave reduction, the sweep bodies
+    and kernels (up to the list of instantiated variants) and the shared
+    layout header, without comments and blank space; a measured traffic
+    file is used only while this matches."""
     src = open(KERNEL_SRC).read()
     a = src.index("// Wave-level reduction of 13 FP64 values")
     b = src.index("#define DVM_SWEEP_VARIANTS")
     hdr = open(os.path.join(os.path.dirname(KERNEL_SRC), "dvm_internal.h")).read()
-    return hashlib.sha256((hdr + src[a:b]).encode()).hexdigest()[:16]
+    code = re.sub(r"//[^\n]*", "", hdr + src[a:b])
+    code = " ".join(code.split())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def _pmc_sum(path: str, counter: str, kernel_substr: str):

@@ -5,11 +5,14 @@
 //   params_kernel     per cell: U, T, 1/tau, Shakhov and conservative-correction
 //                     parameters in FP64, and the three 1-D Gaussian factor
 //                     tables of the Maxwellian (eqs. "feq", "mom", "mu_ref").
-//   sweep_kernel      the hot path: first-order upwind implicit sweep of every
+//   sweep_kernel_pf   the hot path: first-order upwind implicit sweep of every
 //                     discrete velocity (eq. "sweeping_example") over 3-D bricks
-//                     scheduled along brick diagonals, equilibrium evaluated on
-//                     the fly, 13 raw moments reduced across the wave
-//                     (eq. "macros") into deterministic per-tile partials.
+//                     scheduled along brick diagonals (software-pipelined cell
+//                     loop; sweep_kernel is the plain body, sweep_kernel_pfx the
+//                     second-order and ES-BGK forms, sweep_kernel_dyn one
+//                     dependency-driven launch), equilibrium evaluated on the
+//                     fly, 13 raw moments reduced across the wave (eq. "macros")
+//                     into deterministic per-tile partials.
 //   finalize_kernel   per cell: sum of the partials, new conserved moments,
 //                     heat flux about the new bulk velocity, wall densities from
 //                     the non-penetration condition (eq. "rho_wall").
@@ -2004,7 +2007,7 @@ __device__ __forceinline__ bool wait_upwind(const unsigned* fx, const unsigned* 
 // so every wait ends -- waits until its three upwind bricks of the same
 // octant and tile have published this launch's epoch, sweeps the brick,
 // waits for its own stores and publishes.  Faces move through
-// device-coherent loads and stores (load_vl / store_vl with COH), the ready
+// device-coherent loads and stores (load_face / store_face with COH), the ready
 // flags through relaxed device-scope atomics; the counter is never reset:
 // the host passes the value it held before the launch (every wave ends with
 // one failed take, so a launch of G waves advances it by units + G).
