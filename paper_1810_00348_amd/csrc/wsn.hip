@@ -164,6 +164,90 @@ __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// The same convolution for 3x3x3 stencils on inputs whose padded channel
+// count is a multiple of 32, with the input tile in LDS.  A block computes an
+// 8 (z) x 4 (y) x 4 (x) tile of voxels by 16 NT output channels; per 32
+// input channels it stages the tile's 10 x 6 x 6 neighbourhood (zero outside
+// the grid) and takes the A fragments of all 27 taps from there, so that an
+// input value is read from memory about 2.8 times instead of 27.  Wave w
+// covers z-planes 2w and 2w + 1 of the tile (16 voxels, 4 y x 4 x, each: one
+// 16-row A fragment per plane, so that every B fragment feeds two steps).
+// ---------------------------------------------------------------------------
+constexpr int HZ = 10, HY = 6, HX = 6, HVOX = HZ * HY * HX;
+constexpr int HST = 40;  // bf16 per staged voxel: 32 channels, 8 of padding (80 bytes)
+
+template <int NT>
+__global__ __launch_bounds__(256) void conv_halo_kernel(const ConvArgs A, int tx, int ty)
+{
+    __shared__ __align__(16) bf16 halo[HVOX * HST];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, bz = blockIdx.x / (tx * ty);
+    const int x0 = bx * 4, y0 = by * 4, z0 = bz * 8;
+    const int co0 = blockIdx.y * 16 * NT;
+    const int r = lane & 15, g = lane >> 4;
+    const int ry = r >> 2, rx = r & 3;
+    floatx4 acc[2][NT];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[p][n] = {0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < A.cinp; c0 += 32) {
+        // the neighbourhood, 8 channels (16 bytes) per thread and step
+        for (int u = threadIdx.x; u < HVOX * 4; u += 256) {
+            const int hv = u >> 2, gg = u & 3;
+            const int hz = hv / (HY * HX), hy = (hv / HX) % HY, hx = hv % HX;
+            const int zz = z0 - 1 + hz, yy = y0 - 1 + hy, xx = x0 - 1 + hx;
+            bf16x8 val = zero8();
+            if (zz >= 0 && zz < A.D && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+                val = load8(A.x + ((size_t)(zz * A.H + yy) * A.W + xx) * A.xs + c0 + 8 * gg);
+            *reinterpret_cast<bf16x8*>(&halo[hv * HST + 8 * gg]) = val;
+        }
+        __syncthreads();
+        for (int tap = 0; tap < 27; ++tap) {
+            // tap offsets (dz, dy, dx) + 1: positions in the neighbourhood
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+            const bf16* wp = A.w + ((size_t)tap * A.coutp + co0 + r) * A.cinp + c0 + 8 * g;
+            bf16x8 b[NT];
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                b[n] = co0 + 16 * n + r < A.coutp ? load8(wp + (size_t)16 * n * A.cinp) : zero8();
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int hv = ((2 * wv + p + dz) * HY + ry + dy) * HX + rx + dx;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&halo[hv * HST + 8 * g]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[p][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[n], acc[p][n], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // lane holds rows 4g..4g+3 of column r of each tile: row 4g + i is the
+    // tile voxel (y0 + g, x0 + i) of the plane
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int z = z0 + 2 * wv + p, y = y0 + g;
+        if (z >= A.D || y >= A.H) continue;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int c = co0 + 16 * n + r;
+            if (c >= A.cout_valid) continue;
+            const float bb = A.bias ? A.bias[c] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + i;
+                if (x >= A.W) continue;
+                const size_t v = (size_t)(z * A.H + y) * A.W + x;
+                float val = acc[p][n][i] + bb;
+                if (A.relu) val = fmaxf(val, 0.f);
+                if (A.yf) A.yf[v * A.yfs + c] = val;
+                if (A.yb) A.yb[v * A.ybs + c] = f2bf(val);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient: gw[tap][o][i] += sum_v gy[v][o] x[v + tap][i].
 // GEMM with M = output channels, N = input channels, K = voxels; one wave per
 // (tap, 16x16 channel tile, chunk of voxels), FP32 atomics into the flat
@@ -536,6 +620,22 @@ int conv(wsn_ctx* c, const Layer& l, const bf16* x, int xs, int D, int H, int W,
     const int V = D * H * W;
     const int tiles = (coutp + 15) / 16;
     const int nt = tiles >= 4 ? 4 : tiles >= 2 ? 2 : 1;
+    if (l.taps == 27 && cinp % 32 == 0) {
+        const int tx = (W + 3) / 4, ty = (H + 3) / 4, tz = (D + 7) / 8;
+        // fewer output-channel tiles per block on small grids, so that the
+        // launch still has a few blocks per compute unit
+        int nth = nt;
+        while (nth > 1 && tx * ty * tz * ((tiles + nth - 1) / nth) < 512) nth /= 2;
+        dim3 hgrid(tx * ty * tz, (tiles + nth - 1) / nth);
+        if (nth == 4)
+            conv_halo_kernel<4><<<hgrid, 256, 0, c->st>>>(a, tx, ty);
+        else if (nth == 2)
+            conv_halo_kernel<2><<<hgrid, 256, 0, c->st>>>(a, tx, ty);
+        else
+            conv_halo_kernel<1><<<hgrid, 256, 0, c->st>>>(a, tx, ty);
+        WCHK(hipGetLastError());
+        return 0;
+    }
     dim3 grid((V / 16 + 3) / 4 + 1, (tiles + nt - 1) / nt);
     if (nt == 4)
         conv_kernel<4><<<grid, 256, 0, c->st>>>(a);
@@ -582,7 +682,7 @@ int bwd_conv(wsn_ctx* c, int li, const float* gy, int gys, const bf16* act, int 
     dim3 grid(l.taps * w.cotiles * w.citiles, (V + w.vchunk - 1) / w.vchunk);
     wgrad_kernel<<<grid, 64, 0, c->st>>>(w);
     WCHK(hipGetLastError());
-    bgrad_kernel<<<(V + 1023) / 1024, 256, 0, c->st>>>(c->gpre, l.cop, l.co, V, 1024, c->g + l.boff);
+    bgrad_kernel<<<(V + 127) / 128, 256, 0, c->st>>>(c->gpre, l.cop, l.co, V, 128, c->g + l.boff);
     WCHK(hipGetLastError());
     if (gx) {
         // input gradient: convolution of the pre-activation gradient with the

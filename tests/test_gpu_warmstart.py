@@ -36,7 +36,10 @@ def test_mfma_tile_layout():
 
 
 @pytest.mark.parametrize("shape,ci,co,taps", [((4, 6, 5), 3, 5, 27), ((8, 4, 4), 16, 32, 27),
-                                              ((5, 5, 5), 32, 5, 1), ((4, 4, 8), 96, 32, 27)])
+                                              ((5, 5, 5), 32, 5, 1), ((4, 4, 8), 96, 32, 27),
+                                              # LDS-tiled form (channels a multiple of 32) on
+                                              # grids that are no multiple of its 8 x 4 x 4 tile
+                                              ((5, 6, 7), 32, 64, 27), ((9, 5, 3), 64, 48, 27)])
 def test_conv_kernels_match_reference(shape, ci, co, taps):
     ws = _ws()
     D, H, W = shape
