@@ -188,12 +188,11 @@ void derive_schedule(dvm_ctx* c)
     // VL: 4 velocities per lane, halved while more than 1/8 of the lanes'
     // velocity slots of the larger x half would be empty.  Brick and body by
     // measurement (cavity 64^3 x 32^3 FP64, 96^3 x 28^3 and cube FP32):
-    // 4x2 bricks and the software-pipelined body, except FP64 with 4 per
-    // lane: 3x2 bricks (64^3 x 32^3: 277 GPt/s against 267 at 4x2 -- the
-    // 12 KB LDS plane lets 3 waves per SIMD stay resident where 4x2's 16 KB
-    // allows 2.5), 4x2 for ES-BGK (its registers allow 2 waves anyway: 195
-    // against 187 at 2x2); the second-order FP64 form takes 2 per lane and
-    // 4x2x12 bricks (141 GPt/s against 131 with 4 per lane at 2x2, the most
+    // 4x2 bricks and the software-pipelined body (FP64 with 4 per lane:
+    // 64^3 x 32^3 298 GPt/s against 295 at 3x2, whose 12 KB LDS plane lets
+    // more waves stay resident but moves a third more x-face traffic; ES-BGK
+    // 195 against 187 at 2x2); the second-order FP64 form takes 2 per lane
+    // and 4x2 bricks (141 GPt/s against 131 with 4 per lane at 2x2, the most
     // its registers and two LDS planes allow); 1 per lane: plain body, 4x4.
     // FP64 with 2 per lane (96^3 x 28^3): pipelined 234 GPt/s, plain 214.
     const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
@@ -205,18 +204,20 @@ void derive_schedule(dvm_ctx* c)
     // the first-order forms
     if (f64 && (nax % 4 || o2)) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
-    auto default_bx = [&](int v) { return (f64 && v == 4) ? (o2 ? 2 : es ? 4 : 3) : 4; };
+    auto default_bx = [&](int v) { return (f64 && v == 4 && o2) ? 2 : 4; };
     auto default_by = [&](int v) { return v == 1 ? 4 : 2; };
     if (!sweep_variant_available(c->prec, vl, default_bx(vl), default_by(vl), c->nonuniform, o2, es)) vl = 1;
     int bx = default_bx(vl), by = default_by(vl);
     int pf = vl >= 2 ? 1 : 0;
     // cells per brick column: 16 for the first-order FP64 sweep with 4 per
-    // lane (cavity 64^3 x 32^3 with the launches on two streams: 3x2 bricks
-    // 292 GPt/s against 286 at 12, 287 at 14, 283 at 20 and 24, 277 at 32;
-    // 4x2 288 at 16, 282 at 12), 12 for the second-order FP64 form (141
-    // GPt/s against 137 at 8) and the ES-BGK one, 8 otherwise (FP32: 12 is
-    // 1-2 % slower on 96^3 x 28^3 and the cube)
-    int bz = (f64 && vl == 4 && !o2 && !es) ? 16 : (f64 && (vl == 4 || o2)) ? 12 : 8;
+    // lane (cavity 64^3 x 32^3 with the launches on two streams, 4x2 bricks:
+    // 298 GPt/s against 291 at 12, 283 at 20, 290 at 24), 12 for the
+    // first-order FP32 one with 4 per lane (cube 510 against 499 at 8 and 502
+    // at 10; 96^3 x 28^3 426 against 422 at 8 and 425 at 16), for the
+    // second-order FP64 form (141 GPt/s against 137 at 8) and the ES-BGK one,
+    // 8 otherwise
+    int bz = (f64 && vl == 4 && !o2 && !es) ? 16
+             : ((f64 && (vl == 4 || o2)) || (!f64 && vl == 4 && !o2 && !es)) ? 12 : 8;
     c->req_ok = true;
     if (c->req_vl || c->req_bx || c->req_by || c->req_bz || c->req_body) {
         const int rv = c->req_vl ? c->req_vl : vl;

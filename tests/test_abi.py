@@ -125,8 +125,8 @@ def test_spacing_arguments(L):
     assert lib.dvm_set_spacing(h, good.ctypes.data_as(P), hy.ctypes.data_as(P), None) == 0
     inf = L.Info()
     assert lib.dvm_get_info(h, C.byref(inf)) == 0
-    # FP64 with 8 nodes per x half: 4 per lane, 3x2 bricks, pipelined body
-    assert (inf.vel_per_lane, inf.brick[0], inf.brick[1], inf.pipelined) == (4, 3, 2, 1)
+    # FP64 with 8 nodes per x half: 4 per lane, 4x2 bricks, pipelined body
+    assert (inf.vel_per_lane, inf.brick[0], inf.brick[1], inf.pipelined) == (4, 4, 2, 1)
     n = C.c_size_t()
     assert lib.dvm_required_workspace(h, C.byref(n)) == 0
     assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 16) == -3
@@ -253,12 +253,12 @@ def test_model_arguments(L):
 
 @pytest.mark.parametrize("name,prec,order,model,expect", [
     # (VL, BX, BY, BZ, pipelined) chosen by the library for the benchmark workloads
-    ("c2", 0, 1, 0, (4, 3, 2, 16, 1)),    # FP64, 16 nodes per x half
+    ("c2", 0, 1, 0, (4, 4, 2, 16, 1)),    # FP64, 16 nodes per x half
     ("c2", 0, 1, 1, (4, 4, 2, 12, 1)),    # ES-BGK FP64
     ("c2", 0, 2, 0, (2, 4, 2, 12, 1)),    # second order FP64: 2 per lane
-    ("c3", 1, 1, 0, (4, 4, 2, 8, 1)),     # FP32, 14 nodes per half (empty slots)
+    ("c3", 1, 1, 0, (4, 4, 2, 12, 1)),    # FP32, 14 nodes per half (empty slots)
     ("c3", 0, 1, 0, (2, 4, 2, 8, 1)),     # FP64, 14 nodes per half -> 2 per lane
-    ("c4", 1, 1, 0, (4, 4, 2, 8, 1)),     # FP32, 24 nodes per half
+    ("c4", 1, 1, 0, (4, 4, 2, 12, 1)),    # FP32, 24 nodes per half
     ("c1", 0, 1, 0, (2, 4, 2, 8, 1)),     # FP64, 6 nodes per half
 ])
 def test_default_schedule_of_the_benchmark_workloads(L, name, prec, order, model, expect):
@@ -289,12 +289,12 @@ def test_brick_columns_shortened_for_32bit_face_offsets(L):
     # 2000 x 2000 x 2 cells, 64^3 velocities, FP64: an octant has 32^3
     # velocities = 8192 lanes of 4 = 128 tiles, so one face cell holds
     # 128 x 64 x 4 x 8 bytes = 256 KiB and 4 GiB holds 16384 of them:
-    # (BZ - 1) * 2000 + 3 < 16384 -> BZ <= 9; halving from 16 gives 8
+    # (BZ - 1) * 2000 + 4 < 16384 -> BZ <= 9; halving from 16 gives 8
     case = cases.cavity((2000, 2000, 2), 64, kn=1.0)
     h = _ctx(L, case, 0)
     info = L.Info()
     assert lib.dvm_get_info(h, C.byref(info)) == 0
-    assert (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 3, 2)
+    assert (info.vel_per_lane, info.brick[0], info.brick[1]) == (4, 4, 2)
     assert info.brick[2] == 8, tuple(info.brick)
     lib.dvm_destroy(h)
     # the benchmark grid keeps its 16-cell columns
@@ -323,7 +323,7 @@ def test_schedule_requests(L):
     # all zero: the library's choice again
     assert lib.dvm_set_schedule(h, 0, 0, 0, 0, 0) == 0
     assert lib.dvm_get_info(h, C.byref(info)) == 0
-    assert (info.vel_per_lane, *info.brick, info.pipelined) == (4, 3, 2, 16, 1)
+    assert (info.vel_per_lane, *info.brick, info.pipelined) == (4, 4, 2, 16, 1)
     # velocities per lane alone: the brick defaults of that width
     assert lib.dvm_set_schedule(h, 1, 0, 0, 0, 0) == 0
     assert lib.dvm_get_info(h, C.byref(info)) == 0
@@ -356,11 +356,11 @@ def test_z_face_offsets_bound_the_schedule(L):
     info = L.Info()
     # 64^3 velocities, FP64, 4 per lane: 256 KiB per face cell, 16384 face
     # cells in 4 GiB; a 20000-cell x extent puts the second z-face row of a
-    # 3x2 brick beyond that
+    # 4x2 brick beyond that
     case = cases.cavity((20000, 2, 2), 64, kn=1.0)
     h = _ctx(L, case, 0)
     assert lib.dvm_get_info(h, C.byref(info)) == 0
-    assert (info.vel_per_lane, info.brick[0], info.brick[1], info.brick[2]) == (4, 3, 2, 1)
+    assert (info.vel_per_lane, info.brick[0], info.brick[1], info.brick[2]) == (4, 4, 2, 1)
     assert lib.dvm_bind_workspace(h, C.c_void_p(4096), 1 << 40) == -1
     assert b"32-bit" in lib.dvm_last_error()
     # velocity groups shrink the face rows and let it through the check
