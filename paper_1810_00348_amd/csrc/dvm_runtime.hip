@@ -190,8 +190,10 @@ void derive_schedule(dvm_ctx* c)
     // measurement (cavity 64^3 x 32^3 FP64, 96^3 x 28^3 and cube FP32):
     // 4x2 bricks and the software-pipelined body (FP64 with 4 per lane:
     // 64^3 x 32^3 298 GPt/s against 295 at 3x2, whose 12 KB LDS plane lets
-    // more waves stay resident but moves a third more x-face traffic; ES-BGK
-    // 195 against 187 at 2x2); the second-order FP64 form takes 2 per lane
+    // more waves stay resident but moves a third more x-face traffic -- on a
+    // stretched mesh 3x2 stays ahead: 286 against 274 at 4x2, the paper cube
+    // 298 against 285; ES-BGK 195 against 187 at 2x2); the second-order FP64
+    // form takes 2 per lane
     // and 4x2 bricks (141 GPt/s against 131 with 4 per lane at 2x2, the most
     // its registers and two LDS planes allow); 1 per lane: plain body, 4x4.
     // FP64 with 2 per lane (96^3 x 28^3): pipelined 234 GPt/s, plain 214.
@@ -204,7 +206,7 @@ void derive_schedule(dvm_ctx* c)
     // the first-order forms
     if (f64 && (nax % 4 || o2)) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
-    auto default_bx = [&](int v) { return (f64 && v == 4 && o2) ? 2 : 4; };
+    auto default_bx = [&](int v) { return (f64 && v == 4) ? (o2 ? 2 : (c->nonuniform && !es) ? 3 : 4) : 4; };
     auto default_by = [&](int v) { return v == 1 ? 4 : 2; };
     if (!sweep_variant_available(c->prec, vl, default_bx(vl), default_by(vl), c->nonuniform, o2, es)) vl = 1;
     int bx = default_bx(vl), by = default_by(vl);
