@@ -211,15 +211,14 @@ void derive_schedule(dvm_ctx* c)
     if (!sweep_variant_available(c->prec, vl, default_bx(vl), default_by(vl), c->nonuniform, o2, es)) vl = 1;
     int bx = default_bx(vl), by = default_by(vl);
     int pf = vl >= 2 ? 1 : 0;
-    // cells per brick column: 16 for the first-order FP64 sweep with 4 per
-    // lane (cavity 64^3 x 32^3 with the launches on two streams, 4x2 bricks:
-    // 298 GPt/s against 291 at 12, 283 at 20, 290 at 24), 12 for the
-    // first-order FP32 one with 4 per lane (cube 510 against 499 at 8 and 502
-    // at 10; 96^3 x 28^3 426 against 422 at 8 and 425 at 16), for the
-    // second-order FP64 form (141 GPt/s against 137 at 8) and the ES-BGK one,
-    // 8 otherwise
-    int bz = (f64 && vl == 4 && !o2 && !es) ? 16
-             : ((f64 && (vl == 4 || o2)) || (!f64 && vl == 4 && !o2 && !es)) ? 12 : 8;
+    // cells per brick column: 16 for the FP64 sweeps with 2 or 4 per lane
+    // (cavity 64^3 x 32^3 with the launches on two streams, 4x2 bricks: 298
+    // GPt/s against 291 at 12, 283 at 20, 290 at 24; second order 151
+    // against 145 at 12, ES-BGK 205 against 203; 96^3 x 28^3 with 2 per
+    // lane 255 against 250 at 8), 12 for the FP32 ones with 4 per lane (cube
+    // 510 against 499 at 8 and 502 at 10; 96^3 x 28^3 426 against 422 at 8
+    // and 425 at 16, second order 231 against 227), 8 otherwise
+    int bz = f64 ? (vl >= 2 ? 16 : 8) : (vl == 4 ? 12 : 8);
     c->req_ok = true;
     if (c->req_vl || c->req_bx || c->req_by || c->req_bz || c->req_body) {
         const int rv = c->req_vl ? c->req_vl : vl;
