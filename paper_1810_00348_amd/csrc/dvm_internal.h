@@ -64,6 +64,7 @@ struct Consts {
 struct DevPtrs {
     const double* xi;     // [3][MAXM] axis nodes
     const double* wt;     // [3][MAXM] axis weights
+    const double* xmom;   // [MAXM][5] x axis: w xi^p, p = 0..4
     const uint32_t* cellinfo;
     const int* bricks;    // int4 (I, J, K, 0) per brick, grouped by diagonal
     const double* lanetab;

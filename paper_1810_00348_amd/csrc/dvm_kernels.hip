@@ -309,6 +309,22 @@ hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, con
     return hipGetLastError();
 }
 
+__device__ __forceinline__ double wave_reduce16(const double v[16]);
+
+__device__ __forceinline__ double readlane_d(double x, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// a lane that holds the sum of value k after wave_reduce16 (lane 16 r + 4 b
+// holds value 4 bitreverse2(b) + bitreverse2(r))
+__host__ __device__ constexpr int reduce16_lane(int k)
+{
+    return 16 * (((k & 1) << 1) | ((k >> 1) & 1)) + 4 * ((((k >> 2) & 1) << 1) | (k >> 3));
+}
+
 // ES-BGK (the ellipsoidal statistical model; the scheme applies to model
 // equations other than Shakhov's, Sec. 2.1).  In the normalised units
 // (R T = T/2) the target is the Gaussian
@@ -319,7 +335,8 @@ hipError_t launch_params(const Consts& C, const DevPtrs& D, const double* W, con
 // cell record, for the cross factor exp(-(A_xy cx cy + A_xz cx cz + A_yz cy cz))
 // the sweep takes per point.  The correction multipliers need the discrete
 // moments of G, which does not factor over the axes: one pass over the whole
-// velocity set per cell (one exponential per node), shared by a wave.
+// velocity set per cell, shared by a wave (on a uniform x axis two products
+// and five FMAs per node against the axis's w xi^p).
 template <typename S>
 __global__ __launch_bounds__(64) void params_es_kernel(Consts C, DevPtrs D, const double* __restrict__ W,
                                                        const double* __restrict__ stress,
@@ -411,27 +428,47 @@ __global__ __launch_bounds__(64) void params_es_kernel(Consts C, DevPtrs D, cons
             const double d1 = d0 + Axx * hx * hx * (C.mx - 2);      // q(M-1) - q(M-2)
             const bool rec = C.xuniform && fabs(q0) < 600.0 && fabs(q1) < 600.0 && fabs(d0) < 600.0 &&
                              fabs(d1) < 600.0;
-            double g = rec ? exp(-q0) : 0.0, rr = rec ? exp(-d0) : 0.0;
-            // the row's sums of w e cx^p, p = 0..4; the y and z factors of
-            // the monomials are applied once per row
-            double r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0;
-            for (int kx = 0; kx < C.mx; ++kx) {
-                const double cx = D.xi[kx] - Ux;
-                double e;
-                if (rec) {
-                    e = g;
+            // the row's raw sums R_p = sum of w e xi_x^p, p = 0..4 (the axis's
+            // w xi^p from a table), then taken about U_x; the y and z factors
+            // of the monomials are applied once per row
+            double R0 = 0, R1 = 0, R2 = 0, R3 = 0, R4 = 0;
+            // the table through the constant address space: one scalar load
+            // for the wave (the address is the same on every lane)
+            using CT = const __attribute__((address_space(4))) double;
+            CT* xm = (CT*)D.xmom;
+            if (rec) {
+                double g = exp(-q0), rr = exp(-d0);
+#pragma unroll 4
+                for (int kx = 0; kx < C.mx; ++kx) {
+                    CT* t = xm + 5 * kx;
+                    const double e = g;
                     g *= rr;
                     rr *= sx;
-                } else {
-                    e = exp(-(0.5 * Axx * cx * cx + cx * B + row));
+                    R0 = fma(t[0], e, R0);
+                    R1 = fma(t[1], e, R1);
+                    R2 = fma(t[2], e, R2);
+                    R3 = fma(t[3], e, R3);
+                    R4 = fma(t[4], e, R4);
                 }
-                const double t0 = D.wt[kx] * e, t1 = t0 * cx, t2 = t1 * cx, t3 = t2 * cx;
-                r0 += t0;
-                r1 += t1;
-                r2 += t2;
-                r3 += t3;
-                r4 += t3 * cx;
+            } else {
+                for (int kx = 0; kx < C.mx; ++kx) {
+                    CT* t = xm + 5 * kx;
+                    const double cx = D.xi[kx] - Ux;
+                    const double e = exp(-(0.5 * Axx * cx * cx + cx * B + row));
+                    R0 = fma(t[0], e, R0);
+                    R1 = fma(t[1], e, R1);
+                    R2 = fma(t[2], e, R2);
+                    R3 = fma(t[3], e, R3);
+                    R4 = fma(t[4], e, R4);
+                }
             }
+            // sum of w e (xi - U)^p = sum over j of C(p, j) (-U)^(p-j) R_j
+            const double u1 = -Ux, u2 = u1 * u1, u3 = u2 * u1, u4 = u2 * u2;
+            double r0 = R0;
+            double r1 = R1 + u1 * R0;
+            double r2 = R2 + 2.0 * u1 * R1 + u2 * R0;
+            double r3 = R3 + 3.0 * u1 * R2 + 3.0 * u2 * R1 + u3 * R0;
+            double r4 = R4 + 4.0 * u1 * R3 + 6.0 * u2 * R2 + 4.0 * u3 * R1 + u4 * R0;
             const double f = wyz * pre;
             r0 *= f;
             r1 *= f;
@@ -454,8 +491,16 @@ __global__ __launch_bounds__(64) void params_es_kernel(Consts C, DevPtrs D, cons
             sm[12] += cz * (r2 + cyz2 * r0);      // cz |c|^2
             sm[13] += r4 + 2.0 * cyz2 * r2 + cyz2 * cyz2 * r0;  // |c|^4
         }
-        for (int k = 0; k < 14; ++k)
-            for (int o = 32; o > 0; o >>= 1) sm[k] += __shfl_xor(sm[k], o, 64);
+        // the 14 sums over the wave: the 16-value form of the sweep's moment
+        // reduction (two slots unused), each sum then read from a lane that
+        // holds it, so that every lane solves the same system
+        double v16[16];
+#pragma unroll
+        for (int k = 0; k < 14; ++k) v16[k] = sm[k];
+        v16[14] = v16[15] = 0.0;
+        const double red = wave_reduce16(v16);
+#pragma unroll
+        for (int k = 0; k < 14; ++k) sm[k] = readlane_d(red, reduce16_lane(k));
         const double sc2 = sm[4] + sm[5] + sm[6];
         double A[5][5] = {{sm[0], sm[1], sm[2], sm[3], sc2},
                           {sm[1], sm[4], sm[7], sm[8], sm[10]},

@@ -326,7 +326,7 @@ void layout(dvm_ctx* c)
     const size_t N = (size_t)c->N, S = c->Ssz;
     // faces, mirror planes and partials hold one velocity group
     const size_t fst = (size_t)c->gtiles * 64 * c->VL;
-    c->off.axes = take(sizeof(double) * 2 * 3 * MAXM);
+    c->off.axes = take(sizeof(double) * (2 * 3 + 5) * MAXM);
     c->off.spacing = take(sizeof(double) * (size_t)(c->g.nx + c->g.ny + c->g.nz));
     c->off.cellinfo = take(sizeof(uint32_t) * N);
     c->off.bricks = take(sizeof(int) * c->bricks.size());
@@ -402,6 +402,7 @@ DevPtrs make_ptrs(const dvm_ctx* c)
     DevPtrs D;
     D.xi = c->P<double>(c->off.axes);
     D.wt = c->P<double>(c->off.axes) + 3 * MAXM;
+    D.xmom = c->P<double>(c->off.axes) + 6 * MAXM;
     D.cellinfo = c->P<uint32_t>(c->off.cellinfo);
     D.bricks = c->P<int>(c->off.bricks);
     D.lanetab = c->P<double>(c->off.lanetab);
@@ -1055,7 +1056,7 @@ dvm_status bind_impl(dvm_ctx* c, void* ptr, size_t bytes)
 
     // velocity axes: uniform (exactly antisymmetric nodes) with trapezoid
     // weights, or the nodes and weights given to dvm_set_velocity_axes
-    std::vector<double> axes(2 * 3 * MAXM, 0.0);
+    std::vector<double> axes((2 * 3 + 5) * MAXM, 0.0);
     std::vector<double> xi[3];
     for (int d = 0; d < 3; ++d) {
         const int M = c->vg.m[d];
@@ -1068,6 +1069,11 @@ dvm_status bind_impl(dvm_ctx* c, void* ptr, size_t bytes)
             axes[d * MAXM + a] = xi[d][a];
             axes[3 * MAXM + d * MAXM + a] = given ? c->vweight[d][a] : (a == 0 || a == M - 1) ? 0.5 * h : h;
         }
+    }
+    // the x axis's w xi^p, p = 0..4, five per node
+    for (int a = 0; a < c->vg.m[0]; ++a) {
+        double t = axes[3 * MAXM + a];
+        for (int p = 0; p < 5; ++p, t *= xi[0][a]) axes[6 * MAXM + 5 * a + p] = t;
     }
     build_cellinfo(c);
     std::vector<double> lt = build_lanetab(c, xi);
