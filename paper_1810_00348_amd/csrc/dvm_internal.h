@@ -102,6 +102,7 @@ struct SweepArgs {
     int oct_base, noct;
     int spec_on;
     int has_solid;
+    int xuni;             // the x velocity axis is uniform (nodes a fixed step apart)
     int nblocks;
     // dependency-driven launches (sweep_kernel_dyn): ready flags
     // [8][ntiles][nbz][nby][nbx] holding the epoch of the launch that last

@@ -1007,6 +1007,43 @@ __device__ __forceinline__ void store_face(S* base, unsigned cofs, unsigned lofs
 // ES: the ES-BGK Gaussian in place of the Shakhov polynomial: no heat-flux
 // term, and the per-point cross factor exp(-(cx B + C)) of the anisotropic
 // Gaussian, B = A_xy cy + A_xz cz and C = A_yz cy cz fixed per lane and cell.
+// ES-BGK: the cross factor exp(-(c_x B + C)) of each of a lane's velocities.
+// With REC (a uniform x axis) the lane's nodes lie one step apart, or repeat
+// the last node of the half axis in its unused slots, so each factor follows
+// from the one before by one product with exp(-step B): two exponentials per
+// lane and cell instead of one per velocity (taken where an exponential costs
+// many instructions, in FP64); otherwise one exponential per velocity.
+template <typename T>
+__device__ __forceinline__ T es_exp(T a)
+{
+    if constexpr (sizeof(T) == 8)
+        return exp(a);
+    else
+        return __expf(a);
+}
+
+template <typename T, bool REC>
+struct EsCross {
+    T cur, step;
+    __device__ __forceinline__ EsCross(T x0, T x1, T Ux, T B, T Cc) : cur(0), step(0)
+    {
+        if constexpr (REC) {
+            cur = es_exp(-((x0 - Ux) * B + Cc));
+            step = es_exp(-(x1 - x0) * B);
+        }
+    }
+    // the factor of velocity v (called for v = 0, 1, ... in order)
+    __device__ __forceinline__ T at(int v, T xv, T xprev, T cx, T B, T Cc)
+    {
+        if constexpr (REC) {
+            if (v > 0 && xv != xprev) cur *= step;
+            return cur;
+        } else {
+            return es_exp(-(cx * B + Cc));
+        }
+    }
+};
+
 template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __restrict__ params,
                                            const S* __restrict__ etab, const S* __restrict__ ghat,
@@ -1284,6 +1321,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                 const S Qyz = qy * cy + qz * cz;
                 // ES-BGK: qx, qy, qz hold A_xy, A_xz, A_yz
                 const S Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
+                EsCross<S, false> cross(xix[0], xix[0], Ux, Bes, Ces);
                 // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
                 // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
                 S ayc = ay, azc = az, sx = sgx;
@@ -1307,13 +1345,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<S>& A, const S* __res
                     S nfs;
                     if constexpr (ES) {
                         const S poly = Lyz + L1 * cx + L4 * c2;
-                        const S arg = -(cx * Bes + Ces);
-                        S cross;
-                        if constexpr (sizeof(S) == 8)
-                            cross = exp(arg);
-                        else
-                            cross = __expf(arg);
-                        nfs = gyz * ldb(E, oa[v]) * poly * cross;
+                        nfs = gyz * ldb(E, oa[v]) * poly * cross.at(v, xix[v], xix[v > 0 ? v - 1 : 0], cx, Bes, Ces);
                     } else {
                         const S poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (S)5);
                         nfs = gyz * ldb(E, oa[v]) * poly;
@@ -1468,8 +1500,10 @@ __device__ __forceinline__ WorkUnit diagonal_unit(const SweepArgs<S>& A, const i
 // PT: type of the per-cell parameter record, the Gaussian factor tables and
 // the equilibrium evaluation (S, or double beside FP32 storage of f: the
 // equilibrium then enters the FP32 update rounded once).
+// XU: the x velocity axis is uniform (ES-BGK takes its cross factors by
+// recurrence along the lane's nodes).
 template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false, bool COH = false,
-          typename PT = S>
+          typename PT = S, bool XU = false>
 __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* __restrict__ params,
                                               const PT* __restrict__ etab, const S* __restrict__ ghat,
                                               const double* __restrict__ lanetab,
@@ -1868,6 +1902,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
             const PT Qyz = qy * cy + qz * cz;
             // ES-BGK: qx, qy, qz hold A_xy, A_xz, A_yz
             const PT Bes = qx * cy + qy * cz, Ces = qz * cy * cz;
+            PT xn[VL];
+#pragma unroll
+            for (int v = 0; v < VL; ++v) xn[v] = PD ? (PT)xd[v] : (PT)xix[v];
+            EsCross<PT, ES && XU && sizeof(PT) == 8 && (VL > 1)> cross(xn[0], xn[VL > 1 ? 1 : 0], Ux, Bes, Ces);
             // upwind coefficients: lane constants |xi_d| / h_d (uniform mesh),
             // or |xi_d| times the cell's inverse sizes (non-uniform mesh)
             S ayc = ay, azc = az, sx = sgx;
@@ -1889,13 +1927,7 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                 const PT c2 = cx * cx + cyz2;
                 PT nfs;
                 if constexpr (ES) {
-                    const PT arg = -(cx * Bes + Ces);
-                    PT cross;
-                    if constexpr (sizeof(PT) == 8)
-                        cross = exp(arg);
-                    else
-                        cross = __expf(arg);
-                    nfs = gyz * ex[v] * (Lyz + L1 * cx + L4 * c2) * cross;
+                    nfs = gyz * ex[v] * (Lyz + L1 * cx + L4 * c2) * cross.at(v, xn[v], xn[v > 0 ? v - 1 : 0], cx, Bes, Ces);
                 } else {
                     const PT poly = Lyz + L1 * cx + L4 * c2 + (Qyz + qx * cx) * (c2 * tT - (PT)5);
                     nfs = gyz * ex[v] * poly;
@@ -2114,13 +2146,14 @@ __global__ __launch_bounds__(64) void sweep_kernel(const SweepArgs<S> A)
 // second-order upwind and/or ES-BGK (uniform meshes), pipelined body
 // (occupancy: FP32 ES-BGK with 4 per lane fits 4 waves per SIMD without
 // spills in the loop; the FP64 and second-order forms would spill there)
-template <typename S, int VL, int BX, int BY, bool O2, bool ES, bool NU = false>
+template <typename S, int VL, int BX, int BY, bool O2, bool ES, bool NU = false, bool XU = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VL == 4 && !O2 && sizeof(S) == 4 ? 4 : 1)))
 void sweep_kernel_pfx(const SweepArgs<S> A)
 {
     S* plane = reinterpret_cast<S*>(dvm_sweep_lds);
-    sweep_body_pf<S, VL, BX, BY, NU, O2, ES>(A, A.params, A.etab, A.ghat, A.lanetab, A.xface, A.yface, A.zface,
-                                             A.spec, A.partial, plane, diagonal_unit(A, A.bricks));
+    sweep_body_pf<S, VL, BX, BY, NU, O2, ES, false, S, XU>(A, A.params, A.etab, A.ghat, A.lanetab, A.xface,
+                                                           A.yface, A.zface, A.spec, A.partial, plane,
+                                                           diagonal_unit(A, A.bricks));
 }
 
 // second-order upwind and/or ES-BGK (uniform meshes, plain body)
@@ -2213,10 +2246,17 @@ hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, int nonuniform, 
         return hipGetLastError();
     }
     if (pipelined) {
-        if (order2 && esbgk)
+        // FP64 ES-BGK on a uniform x axis: the cross factors by recurrence
+        constexpr bool XR = sizeof(T) == 8 && V > 1;
+        const bool xr = XR && esbgk && a.xuni;
+        if (order2 && esbgk && xr)
+            sweep_kernel_pfx<T, V, BXX, BYY, true, true, false, XR><<<a.nblocks, 64, lds, st>>>(a);
+        else if (order2 && esbgk)
             sweep_kernel_pfx<T, V, BXX, BYY, true, true><<<a.nblocks, 64, lds, st>>>(a);
         else if (order2)
             sweep_kernel_pfx<T, V, BXX, BYY, true, false><<<a.nblocks, 64, lds, st>>>(a);
+        else if (xr)
+            sweep_kernel_pfx<T, V, BXX, BYY, false, true, false, XR><<<a.nblocks, 64, lds, st>>>(a);
         else
             sweep_kernel_pfx<T, V, BXX, BYY, false, true><<<a.nblocks, 64, lds, st>>>(a);
         return hipGetLastError();

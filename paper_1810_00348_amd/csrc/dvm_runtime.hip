@@ -610,6 +610,7 @@ dvm_status run_iteration(dvm_ctx* c, double* hout)
                 a.noct = oct_phase / ns;
                 a.spec_on = c->spec_on ? 1 : 0;
                 a.has_solid = c->nfluid < c->N ? 1 : 0;
+                a.xuni = c->vnode[0].empty() ? 1 : 0;
                 a.nblocks = a.noct * cnt * gnt;
                 a.ready = dyn ? c->P<unsigned>(c->off.ready) : nullptr;
                 a.head = dyn ? c->P<unsigned long long>(c->off.head) : nullptr;
