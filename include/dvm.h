@@ -162,7 +162,8 @@ dvm_status dvm_set_closed(dvm_ctx* ctx, int closed);
    (relative 1e-9).  The upwind coefficient of a cell along d is
    |xi_d| / h_d(cell) (finite-volume flux form) and cell volumes weigh the
    total mass.  Before binding the workspace; DVM_ERR_STATE after it,
-   DVM_ERR_ARG for bad sizes. */
+   DVM_ERR_ARG for bad sizes, or with the ES-BGK model where the velocity
+   set leaves 1 velocity per lane (the mesh is then left as it was). */
 dvm_status dvm_set_spacing(dvm_ctx* ctx, const double* hx, const double* hy, const double* hz);
 
 /* Collision model: 0 Shakhov (default; Sec. 2.1), 1 ES-BGK -- the scheme
@@ -172,9 +173,11 @@ dvm_status dvm_set_spacing(dvm_ctx* ctx, const double* hx, const double* hy, con
    Theta the stress per unit mass of the iterate (kept as state, computed
    with the other moments about U^{n+1}), relaxation frequency Pr p / mu,
    the same conservative correction.  Needs Pr >= 2/3 (Lam positive
-   definite) and a uniform mesh; the sweep has one exponential per phase-
-   space point more, the parameter pass one pass over the velocity set per
-   cell.  The stress starts (dvm_init_*) and restarts (dvm_set_state) at
+   definite); on a stretched mesh (dvm_set_spacing, in either order) a
+   velocity set that fills 2 or more velocities per lane (DVM_ERR_ARG
+   otherwise, the previous model kept).  The sweep has one cross factor
+   exp(-(A_xy cx cy + A_xz cx cz + A_yz cy cz)) per phase-space point
+   more, the parameter pass one pass over the velocity set per cell.  The stress starts (dvm_init_*) and restarts (dvm_set_state) at
    the equilibrium (T/2) I of the state.  Before binding the workspace
    (DVM_ERR_STATE after it); DVM_ERR_ARG otherwise. */
 dvm_status dvm_set_model(dvm_ctx* ctx, int model);
@@ -209,10 +212,14 @@ dvm_status dvm_set_velocity_axes(dvm_ctx* ctx, const double* xi_x, const double*
    its own upwind neighbour, f + (f - f_up)/2 (f alone when that cell's
    upwind side is a boundary); a boundary face carries its inflow value; a
    symmetry plane is an interior face whose far side is the mirror image;
-   the wall densities are balanced with what crosses the wall faces.
-   Uniform meshes only.  Before binding the workspace (DVM_ERR_STATE after
-   it); DVM_ERR_ARG for another order or on a non-uniform mesh.  Order 2
-   doubles the face and mirror-plane buffers and the sweep's LDS plane. */
+   the wall densities are balanced with what crosses the wall faces.  On a
+   stretched mesh the extrapolation follows the straight line through the
+   two cell centres, f + theta (f - f_up) with theta = h / (h + h_up) along
+   that axis, and the sweep takes the pipelined body with 2 or more
+   velocities per lane (a schedule without one fails at binding).  Before
+   binding the workspace (DVM_ERR_STATE after it); DVM_ERR_ARG for another
+   order.  Order 2 doubles the face and mirror-plane buffers and the
+   sweep's LDS plane. */
 dvm_status dvm_set_order(dvm_ctx* ctx, int order);
 
 /* Sweep the velocity set in `groups` parts, one after another, within each

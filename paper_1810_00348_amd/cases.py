@@ -75,7 +75,7 @@ class Case:
     # None for a uniform mesh
     spacing: Optional[Tuple[Optional[np.ndarray], Optional[np.ndarray], Optional[np.ndarray]]] = None
     # spatial order of the upwind scheme: 1 (the paper's), or 2 (linear
-    # upwind extrapolation from two upwind cells; uniform meshes only)
+    # upwind extrapolation from the cell and its upwind neighbour)
     order: int = 1
     # velocity nodes and quadrature weights per axis, (xi, w) pairs of
     # length m[d] (None: m[d] uniform nodes on [-vmax, vmax], trapezoid)

@@ -2185,9 +2185,9 @@ bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, i
 #define X(T, V, BXX, BYY) \
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) return true;
     if (order2 || esbgk) {
-        // on a stretched mesh: the second-order Shakhov sweep, pipelined
-        // body (two or more velocities per lane)
-        if (nonuniform && (esbgk || vl < 2)) return false;
+        // on a stretched mesh: pipelined body with two or more velocities
+        // per lane
+        if (nonuniform && vl < 2) return false;
         DVM_SWEEP_VARIANTS_O2(X)
     } else if (nonuniform) {
         DVM_SWEEP_VARIANTS_NU(X)
@@ -2240,15 +2240,26 @@ hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, int nonuniform, 
     const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
     // the plane of f, and with the second order the plane of F along z
     const size_t lds = (size_t)(order2 ? 2 : 1) * BYY * BXX * V * 64 * sizeof(T);
+    // FP64 ES-BGK on a uniform x axis: the cross factors by recurrence
+    constexpr bool XR = sizeof(T) == 8 && V > 1;
+    const bool xr = XR && esbgk && a.xuni;
     if (nonuniform) {
-        if (!order2 || esbgk || !pipelined || V < 2) return hipErrorInvalidValue;
-        sweep_kernel_pfx<T, V, BXX, BYY, true, false, true><<<a.nblocks, 64, lds, st>>>(a);
+        // stretched mesh: pipelined body, two or more velocities per lane
+        if (!pipelined || V < 2) return hipErrorInvalidValue;
+        if constexpr (V < 2) return hipErrorInvalidValue;
+        else if (order2 && esbgk && xr)
+            sweep_kernel_pfx<T, V, BXX, BYY, true, true, true, XR><<<a.nblocks, 64, lds, st>>>(a);
+        else if (order2 && esbgk)
+            sweep_kernel_pfx<T, V, BXX, BYY, true, true, true><<<a.nblocks, 64, lds, st>>>(a);
+        else if (order2)
+            sweep_kernel_pfx<T, V, BXX, BYY, true, false, true><<<a.nblocks, 64, lds, st>>>(a);
+        else if (xr)
+            sweep_kernel_pfx<T, V, BXX, BYY, false, true, true, XR><<<a.nblocks, 64, lds, st>>>(a);
+        else
+            sweep_kernel_pfx<T, V, BXX, BYY, false, true, true><<<a.nblocks, 64, lds, st>>>(a);
         return hipGetLastError();
     }
     if (pipelined) {
-        // FP64 ES-BGK on a uniform x axis: the cross factors by recurrence
-        constexpr bool XR = sizeof(T) == 8 && V > 1;
-        const bool xr = XR && esbgk && a.xuni;
         if (order2 && esbgk && xr)
             sweep_kernel_pfx<T, V, BXX, BYY, true, true, false, XR><<<a.nblocks, 64, lds, st>>>(a);
         else if (order2 && esbgk)

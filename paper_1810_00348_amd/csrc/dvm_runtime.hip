@@ -838,6 +838,8 @@ dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const
         if (fabs(sum - L3[d]) > 1e-9 * L3[d]) return fail(DVM_ERR_ARG, "axis %d: cell sizes sum to %.17g, not the length %.17g", d, sum, L3[d]);
     }
     bool any = false;
+    std::vector<double> old_h[3] = {c->h[0], c->h[1], c->h[2]};
+    const bool old_nu = c->nonuniform;
     for (int d = 0; d < 3; ++d) {
         if (in[d]) {
             c->h[d].assign(in[d], in[d] + n3[d]);
@@ -846,9 +848,15 @@ dvm_status dvm_set_spacing(dvm_ctx* c, const double* hx, const double* hy, const
             c->h[d].assign(n3[d], c->dx[d]);
         }
     }
-    if (any && c->model == 1) return fail(DVM_ERR_ARG, "the ES-BGK sweep needs a uniform mesh");
     c->nonuniform = any;
     derive_schedule(c);
+    if (any && c->model == 1 && c->VL < 2) {
+        for (int d = 0; d < 3; ++d) c->h[d] = old_h[d];
+        c->nonuniform = old_nu;
+        derive_schedule(c);
+        return fail(DVM_ERR_ARG, "ES-BGK on a stretched mesh takes the pipelined sweep with 2 or more velocities "
+                    "per lane, which this velocity set does not fill (the mesh is left as it was)");
+    }
     return DVM_OK;
 }
 
@@ -890,11 +898,17 @@ dvm_status dvm_set_model(dvm_ctx* c, int model)
     if (check_ctx(c)) return DVM_ERR_ARG;
     if (c->bound) return fail(DVM_ERR_STATE, "the model must be set before binding the workspace");
     if (model != 0 && model != 1) return fail(DVM_ERR_ARG, "model must be 0 (Shakhov) or 1 (ES-BGK), got %d", model);
-    if (model == 1 && c->nonuniform) return fail(DVM_ERR_ARG, "the ES-BGK sweep needs a uniform mesh");
     if (model == 1 && !(c->gas.pr >= 2.0 / 3.0 - 1e-12))
         return fail(DVM_ERR_ARG, "ES-BGK needs Pr >= 2/3 (a positive-definite Gaussian), got %g", c->gas.pr);
+    const int old = c->model;
     c->model = model;
     derive_schedule(c);
+    if (model == 1 && c->nonuniform && c->VL < 2) {
+        c->model = old;
+        derive_schedule(c);
+        return fail(DVM_ERR_ARG, "ES-BGK on a stretched mesh takes the pipelined sweep with 2 or more velocities "
+                    "per lane, which this velocity set does not fill");
+    }
     return DVM_OK;
 }
 
@@ -1034,10 +1048,10 @@ dvm_status check_bindable(dvm_ctx* c)
         return fail(DVM_ERR_ARG, "a face row of this grid and velocity set exceeds the 32-bit offsets of the "
                     "sweep even with one-cell brick columns: use more velocity groups");
     if (!sweep_variant_available(c->prec, c->VL, c->BX, c->BY, c->nonuniform, c->order == 2, c->model == 1) ||
-        (c->order == 2 && c->nonuniform && c->PF != 1))
+        ((c->order == 2 || c->model == 1) && c->nonuniform && c->PF != 1))
         return fail(DVM_ERR_ARG, "no sweep kernel is built for %d velocities per lane, %dx%d bricks and body %d with "
-                    "this precision, mesh kind, order and model (a stretched mesh at second order takes the "
-                    "pipelined body with 2 or more velocities per lane)", c->VL, c->BX, c->BY, c->PF + 1);
+                    "this precision, mesh kind, order and model (a stretched mesh at second order or with ES-BGK "
+                    "takes the pipelined body with 2 or more velocities per lane)", c->VL, c->BX, c->BY, c->PF + 1);
     if (c->wide && (c->PF == 0 || !sweep_wide_params_available(c->prec, c->VL, c->BX, c->BY, c->nonuniform,
                                                                 c->order == 2, c->model == 1)))
         return fail(DVM_ERR_ARG, "FP64 parameters beside FP32 storage are built for the first-order Shakhov sweep "

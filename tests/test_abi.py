@@ -280,6 +280,37 @@ def test_default_schedule_of_the_benchmark_workloads(L, name, prec, order, model
     lib.dvm_destroy(h)
 
 
+def test_esbgk_on_a_stretched_mesh_schedule(L):
+    """ES-BGK on a stretched mesh takes the pipelined sweep with 2 or more
+    velocities per lane; a velocity set that leaves 1 per lane is refused
+    and the mesh left uniform (host-only: no device work)."""
+    import numpy as np
+    from paper_1810_00348_amd import cases
+    lib = L.lib()
+    case = cases.config("c2")
+    h = _ctx(L, case, 0)
+    assert lib.dvm_set_model(h, 1) == 0
+    hx = cases.stretched_axis(case.n[0], case.L[0], 1.02)
+    assert lib.dvm_set_spacing(h, hx.ctypes.data_as(C.POINTER(C.c_double)), None, None) == 0
+    info = L.Info()
+    assert lib.dvm_get_info(h, C.byref(info)) == 0
+    got = (info.vel_per_lane, info.brick[0], info.brick[1], info.brick[2], info.pipelined)
+    assert got == (4, 4, 2, 16, 1), got
+    lib.dvm_destroy(h)
+    # 5 nodes per x half in FP64: 1 per lane, no stretched ES-BGK kernel
+    small = cases.cavity((6, 5, 4), 10, kn=1.0)
+    h = _ctx(L, small)
+    assert lib.dvm_set_model(h, 1) == 0
+    hy = cases.stretched_axis(5, 1.0, 1.3)
+    assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(C.POINTER(C.c_double)), None) == -1
+    assert b"stretched" in lib.dvm_last_error()
+    assert lib.dvm_get_info(h, C.byref(info)) == 0 and info.vel_per_lane == 1
+    assert lib.dvm_set_model(h, 0) == 0
+    assert lib.dvm_set_spacing(h, None, hy.ctypes.data_as(C.POINTER(C.c_double)), None) == 0
+    assert lib.dvm_set_model(h, 1) == -1 and b"stretched" in lib.dvm_last_error()
+    lib.dvm_destroy(h)
+
+
 def test_brick_columns_shortened_for_32bit_face_offsets(L):
     """The sweep addresses a face cell of its brick by a 32-bit byte offset:
     on a wide grid with many velocities the library shortens the brick

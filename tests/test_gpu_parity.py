@@ -515,6 +515,53 @@ def test_esbgk_matches_oracle(oracle_mod, name):
     assert np.abs(Pg - Po).max() <= FP64_TOL * np.abs(Po).max()
 
 
+def _es_stretched_cases():
+    a = cases.stretched(cases.cavity((13, 10, 11), 12, kn=0.3, lid=0.4, vmax=4.5), 1.15)   # 2 per lane
+    b = cases.stretched(cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=12, vmax=7.0, mach=2.0, kn=0.5),
+                        1.1, centres=(1.5, 1.25, None))                  # mirror plane and body
+    c = cases.cube_paper(n_body=3, n_side=4, n_front=3, n_rear=5, m=18, front=1.5, rear=2.5, side=1.5)
+    d = cases.stretched(cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2), 1.2)   # 4 per lane
+    out = {k: dataclasses.replace(v, model="esbgk") for k, v in
+           {"cavity": a, "cube_half": b, "cube_paper_small": c, "cavity_m16": d}.items()}
+    out["order2"] = dataclasses.replace(out["cavity"], order=2)
+    gr = cases.graded_velocity_axis(12, 5.0, 1.2)
+    out["graded_axes"] = dataclasses.replace(out["cube_half"], velocity_axes=(gr, gr, gr))   # no x recurrence
+    return out
+
+
+@pytest.mark.parametrize("name", ["cavity", "cube_half", "cube_paper_small", "cavity_m16", "order2",
+                                  "graded_axes"])
+def test_esbgk_on_stretched_meshes_matches_oracle(oracle_mod, name):
+    """ES-BGK on stretched meshes (the model of one extension on the meshes
+    of another): fields, wall densities and the stress state against the
+    oracle."""
+    case = _es_stretched_cases()[name]
+    assert case.spacing is not None and case.model == "esbgk"
+    init = cases.random_fields(case, seed=71) if name in ("cavity", "cavity_m16", "order2") else None
+    s, o = run_pair(case, 3, oracle_mod, init=init)
+    assert s.info()["vel_per_lane"] >= 2 and s.info()["sweep_kernel"] == "sweep_kernel_pf"
+    err = field_errors(s.fields(), o.fields())
+    print(name, err, s.info())
+    for k in ("rho", "ux", "uy", "uz", "T", "qx", "qy"):
+        assert err[k] <= FP64_TOL, (k, err)
+    rwg, rwo = s.state()[2], o.state()[2]
+    assert np.abs(rwg - rwo).max() <= FP64_TOL * np.abs(rwo).max()
+    Pg, Po = s.stress(), o.stress()
+    assert np.abs(Pg - Po).max() <= FP64_TOL * np.abs(Po).max()
+    assert abs(s.state()[3] - o.initial_mass()) <= 1e-14 * o.initial_mass()
+
+
+def test_esbgk_on_a_stretched_mesh_fp32(oracle_mod):
+    case = _es_stretched_cases()["cavity_m16"]
+    s, o = run_pair(case, 4, oracle_mod, precision="f32")
+    assert s.info()["vel_per_lane"] == 4
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "T"):
+        assert err[k] <= 1e-5, (k, err)
+    for k in ("ux", "uy", "uz"):
+        assert err[k] <= 1e-4, (k, err)
+
+
 def test_esbgk_with_velocity_groups_and_fp32(oracle_mod):
     case = dataclasses.replace(cases.cavity((9, 8, 7), 24, kn=0.5, lid=0.3, vmax=5.0), model="esbgk")
     s, o = run_pair(case, 2, oracle_mod, init=cases.random_fields(case, seed=8), groups=3)
