@@ -208,16 +208,18 @@ def _stretched_cases():
     b = cases.stretched(cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=10, vmax=7.0, mach=2.0, kn=0.5),
                         1.1, centres=(1.5, 1.25, None))
     c = cases.stretched(cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2), 1.2)   # 4 per lane, 3x2 bricks
-    return {"cavity": a, "cube": b, "cavity_m16": c}
+    gr = cases.graded_velocity_axis(10, 7.0, 1.3)
+    d = dataclasses.replace(b, velocity_axes=(gr, gr, gr))                     # non-uniform velocity axes
+    return {"cavity": a, "cube": b, "cavity_m16": c, "cube_graded_axes": d}
 
 
 @pytest.mark.parametrize("pf", [None, 0, 1])
-@pytest.mark.parametrize("name", ["cavity", "cube", "cavity_m16"])
+@pytest.mark.parametrize("name", ["cavity", "cube", "cavity_m16", "cube_graded_axes"])
 def test_stretched_mesh_matches_oracle(oracle_mod, name, pf):
     """Non-uniform (stretched) meshes: per-cell upwind coefficients and cell
     volumes, against the oracle (FP64)."""
     case = _stretched_cases()[name]
-    init = cases.random_fields(case, seed=21) if name != "cube" else None
+    init = cases.random_fields(case, seed=21) if not name.startswith("cube") else None
     sched = None if pf is None else dict(pipelined=bool(pf))
     s, o = run_pair(case, 3, oracle_mod, init=init, schedule=sched)
     if pf is not None:
