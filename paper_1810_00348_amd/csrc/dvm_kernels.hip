@@ -1500,6 +1500,21 @@ __device__ __forceinline__ WorkUnit diagonal_unit(const SweepArgs<S>& A, const i
 // PT: type of the per-cell parameter record, the Gaussian factor tables and
 // the equilibrium evaluation (S, or double beside FP32 storage of f: the
 // equilibrium then enters the FP32 update rounded once).
+// Cells of the pipelined body's brick plane whose z inflow stays in
+// registers: an FP64 plane of 4 x 2 cells with 4 velocities per lane takes
+// 16 KB of LDS per wave, which leaves 2.5 waves per SIMD where the registers
+// allow 3; holding the last row's last two cells (16 VGPRs) brings it to
+// 12 KB.  Those cells are only ever read for their own z inflow (the row
+// behind a cell is the row before it, and the faces are stored from the
+// registers of the cell just computed).  Shakhov's first-order form only:
+// the ES-BGK form would pass 168 VGPRs (2 waves per SIMD), the second-order
+// and dependency-driven forms have no registers to spare.
+template <typename S, int VL, int BX, int BY, bool O2, bool ES, bool COH>
+__host__ __device__ constexpr int zreg_cells()
+{
+    return (!O2 && !ES && !COH && sizeof(S) == 8 && VL == 4 && BX == 4 && BY == 2) ? 2 : 0;
+}
+
 // XU: the x velocity axis is uniform (ES-BGK takes its cross factors by
 // recurrence along the lane's nodes).
 template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false, bool COH = false,
@@ -1558,6 +1573,13 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
     auto ldz = [&](int jj, int ii, int v) -> S& {
         return plane[((BY * BX + jj * BX + ii) * VL + v) * 64 + lane];
     };
+    // the z inflow of the last row's last two cells in registers (ZR = 2):
+    // their plane slots are the last two, which the launch does not allocate
+    constexpr int ZR = zreg_cells<S, VL, BX, BY, O2, ES, COH>();
+    S zr0[VL], zr1[VL];
+#pragma unroll
+    for (int v = 0; v < VL; ++v) zr0[v] = zr1[v] = (S)0;
+    auto zreg = [&](int jj, int ii) { return ZR == 2 && jj == BY - 1 && ii >= BX - 2; };
 
     // ---- lane constants
     const double* lt = lanetab + ((size_t)o * A.slots + slot) * A.lstride;
@@ -1615,8 +1637,18 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
             for (int ii = 0; ii < iend; ++ii) {
                 S t[VL];
                 load_face<COH>(zin, (unsigned)(jj * nx + ii) * rowb, lofs, t);
+                if (zreg(jj, ii)) {
+                    if (ii == BX - 1) {
 #pragma unroll
-                for (int v = 0; v < VL; ++v) lds(jj, ii, v) = t[v];
+                        for (int v = 0; v < VL; ++v) zr1[v] = t[v];
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) zr0[v] = t[v];
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) lds(jj, ii, v) = t[v];
+                }
                 if constexpr (O2) {
                     load_face<COH>(zgin, (unsigned)(jj * nx + ii) * rowb, lofs, t);
 #pragma unroll
@@ -1836,11 +1868,20 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                 // wait for every load in flight, those issued one cell
                 // ahead included)
                 S zl[VL], zg[VL];
+                if (zreg(jj, ii)) {
+                    if (ii == BX - 1) {
 #pragma unroll
-                for (int v = 0; v < VL; ++v) {
-                    zl[v] = lds(jj, ii, v);
-                    zg[v] = O2 ? S(ldz(jj, ii, v)) : (S)0;
+                        for (int v = 0; v < VL; ++v) zl[v] = zr1[v];
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) zl[v] = zr0[v];
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VL; ++v) zl[v] = lds(jj, ii, v);
                 }
+#pragma unroll
+                for (int v = 0; v < VL; ++v) zg[v] = O2 ? S(ldz(jj, ii, v)) : (S)0;
                 // pinned here: not moved below the loads of the branches
                 // (first order; the second-order form has no registers to spare)
                 if constexpr (!O2) {
@@ -1951,7 +1992,12 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                     f = num * fast_rcp(axv + aynu);
                 }
                 prev[v] = f;
-                lds(jj, ii, v) = f;
+                if (!zreg(jj, ii))
+                    lds(jj, ii, v) = f;
+                else if (ii == BX - 1)
+                    zr1[v] = f;
+                else
+                    zr0[v] = f;
                 if constexpr (WP) {
                     const double fd = (double)f;
                     u0 = fma(wd[v], fd, u0);
@@ -2202,7 +2248,8 @@ template <typename T, int V, int BXX, int BYY, bool NU, typename PT = T>
 hipError_t launch_sweep_t(int pipelined, const void* args, hipStream_t st)
 {
     const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
-    const size_t lds = (size_t)BYY * BXX * V * 64 * sizeof(T);
+    const int zr = pipelined == 1 ? zreg_cells<T, V, BXX, BYY, false, false, false>() : 0;
+    const size_t lds = (size_t)(BYY * BXX - zr) * V * 64 * sizeof(T);
     if (pipelined == 2) {
         // as many waves as stay resident (more would only wait for a CU)
         static thread_local int resident = 0, cached_dev = -1;

@@ -188,11 +188,12 @@ void derive_schedule(dvm_ctx* c)
     // VL: 4 velocities per lane, halved while more than 1/8 of the lanes'
     // velocity slots of the larger x half would be empty.  Brick and body by
     // measurement (cavity 64^3 x 32^3 FP64, 96^3 x 28^3 and cube FP32):
-    // 4x2 bricks and the software-pipelined body (FP64 with 4 per lane:
-    // 64^3 x 32^3 298 GPt/s against 295 at 3x2, whose 12 KB LDS plane lets
-    // more waves stay resident but moves a third more x-face traffic -- on a
-    // stretched mesh 3x2 stays ahead: 286 against 274 at 4x2, the paper cube
-    // 298 against 285; ES-BGK 195 against 187 at 2x2); the second-order FP64
+    // 4x2 bricks and the software-pipelined body (FP64 with 4 per lane,
+    // whose first-order Shakhov body keeps two cells of the 4x2 plane in
+    // registers so that 3 waves per SIMD stay resident: 64^3 x 32^3 307
+    // GPt/s against 289 at 3x2, which moves a third more x-face traffic; on
+    // the mesh stretched 1.02 per cell 302 against 289, the paper cube 318
+    // against 303; ES-BGK 195 against 187 at 2x2); the second-order FP64
     // form takes 2 per lane
     // and 4x2 bricks (141 GPt/s against 131 with 4 per lane at 2x2, the most
     // its registers and two LDS planes allow); 1 per lane: plain body, 4x4.
@@ -206,14 +207,15 @@ void derive_schedule(dvm_ctx* c)
     // the first-order forms
     if (f64 && (nax % 4 || o2)) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
-    auto default_bx = [&](int v) { return (f64 && v == 4) ? (o2 ? 2 : (c->nonuniform && !es) ? 3 : 4) : 4; };
+    auto default_bx = [&](int v) { return (f64 && v == 4 && o2) ? 2 : 4; };
     auto default_by = [&](int v) { return v == 1 ? 4 : 2; };
     if (!sweep_variant_available(c->prec, vl, default_bx(vl), default_by(vl), c->nonuniform, o2, es)) vl = 1;
     int bx = default_bx(vl), by = default_by(vl);
     int pf = vl >= 2 ? 1 : 0;
     // cells per brick column: 16 for the FP64 sweeps with 2 or 4 per lane
-    // (cavity 64^3 x 32^3 with the launches on two streams, 4x2 bricks: 298
-    // GPt/s against 291 at 12, 283 at 20, 290 at 24; second order 151
+    // (cavity 64^3 x 32^3 with the launches on two streams, 4x2 bricks:
+    // 303-307 GPt/s against 305-307 at 12, 299 at 20, 296 at 24, 278 at 32;
+    // on the 1.02-stretched mesh 300 against 296 at 12; second order 151
     // against 145 at 12, ES-BGK 205 against 203; 96^3 x 28^3 with 2 per
     // lane 255 against 250 at 8), 12 for the FP32 ones with 4 per lane (cube
     // 510 against 499 at 8 and 502 at 10; 96^3 x 28^3 426 against 422 at 8

@@ -125,9 +125,9 @@ def test_spacing_arguments(L):
     assert lib.dvm_set_spacing(h, good.ctypes.data_as(P), hy.ctypes.data_as(P), None) == 0
     inf = L.Info()
     assert lib.dvm_get_info(h, C.byref(inf)) == 0
-    # FP64 with 8 nodes per x half on a stretched mesh: 4 per lane, 3x2
+    # FP64 with 8 nodes per x half on a stretched mesh: 4 per lane, 4x2
     # bricks, pipelined body
-    assert (inf.vel_per_lane, inf.brick[0], inf.brick[1], inf.pipelined) == (4, 3, 2, 1)
+    assert (inf.vel_per_lane, inf.brick[0], inf.brick[1], inf.pipelined) == (4, 4, 2, 1)
     n = C.c_size_t()
     assert lib.dvm_required_workspace(h, C.byref(n)) == 0
     assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 16) == -3

@@ -207,7 +207,7 @@ def _stretched_cases():
     a = cases.stretched(cases.cavity((13, 10, 11), 8, kn=0.3, lid=0.4, vmax=4.5), 1.15)
     b = cases.stretched(cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=10, vmax=7.0, mach=2.0, kn=0.5),
                         1.1, centres=(1.5, 1.25, None))
-    c = cases.stretched(cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2), 1.2)   # 4 per lane, 3x2 bricks
+    c = cases.stretched(cases.cavity((9, 12, 8), 16, kn=1.0, lid=0.2), 1.2)   # 4 per lane, 4x2 bricks
     gr = cases.graded_velocity_axis(10, 7.0, 1.3)
     d = dataclasses.replace(b, velocity_axes=(gr, gr, gr))                     # non-uniform velocity axes
     return {"cavity": a, "cube": b, "cavity_m16": c, "cube_graded_axes": d}
