@@ -1497,24 +1497,26 @@ __device__ __forceinline__ WorkUnit diagonal_unit(const SweepArgs<S>& A, const i
     return u;
 }
 
-// PT: type of the per-cell parameter record, the Gaussian factor tables and
-// the equilibrium evaluation (S, or double beside FP32 storage of f: the
-// equilibrium then enters the FP32 update rounded once).
 // Cells of the pipelined body's brick plane whose z inflow stays in
 // registers: an FP64 plane of 4 x 2 cells with 4 velocities per lane takes
 // 16 KB of LDS per wave, which leaves 2.5 waves per SIMD where the registers
 // allow 3; holding the last row's last two cells (16 VGPRs) brings it to
-// 12 KB.  Those cells are only ever read for their own z inflow (the row
-// behind a cell is the row before it, and the faces are stored from the
-// registers of the cell just computed).  Shakhov's first-order form only:
-// the ES-BGK form would pass 168 VGPRs (2 waves per SIMD), the second-order
-// and dependency-driven forms have no registers to spare.
+// 12 KB.  The same for the second-order FP64 form with 2 per lane, whose f
+// and F planes take 16 KB together (its two cells' f and F: 16 VGPRs).
+// Those cells are only ever read for their own z inflow (the row behind a
+// cell is the row before it, and the faces are stored from the registers
+// of the cell just computed).  Shakhov's model only: the ES-BGK form would
+// pass 168 VGPRs (2 waves per SIMD); not in the dependency-driven form,
+// whose registers are full.
 template <typename S, int VL, int BX, int BY, bool O2, bool ES, bool COH>
 __host__ __device__ constexpr int zreg_cells()
 {
-    return (!O2 && !ES && !COH && sizeof(S) == 8 && VL == 4 && BX == 4 && BY == 2) ? 2 : 0;
+    return (!ES && !COH && sizeof(S) == 8 && BX == 4 && BY == 2 && (O2 ? VL == 2 : VL == 4)) ? 2 : 0;
 }
 
+// PT: type of the per-cell parameter record, the Gaussian factor tables and
+// the equilibrium evaluation (S, or double beside FP32 storage of f: the
+// equilibrium then enters the FP32 update rounded once).
 // XU: the x velocity axis is uniform (ES-BGK takes its cross factors by
 // recurrence along the lane's nodes).
 template <typename S, int VL, int BX, int BY, bool NU, bool O2 = false, bool ES = false, bool COH = false,
@@ -1570,15 +1572,15 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
     }
 
     auto lds = [&](int jj, int ii, int v) -> S& { return plane[((jj * BX + ii) * VL + v) * 64 + lane]; };
-    auto ldz = [&](int jj, int ii, int v) -> S& {
-        return plane[((BY * BX + jj * BX + ii) * VL + v) * 64 + lane];
-    };
     // the z inflow of the last row's last two cells in registers (ZR = 2):
     // their plane slots are the last two, which the launch does not allocate
     constexpr int ZR = zreg_cells<S, VL, BX, BY, O2, ES, COH>();
-    S zr0[VL], zr1[VL];
+    auto ldz = [&](int jj, int ii, int v) -> S& {
+        return plane[((BY * BX - ZR + jj * BX + ii) * VL + v) * 64 + lane];
+    };
+    S zr0[VL], zr1[VL], zg0[VL], zg1[VL];
 #pragma unroll
-    for (int v = 0; v < VL; ++v) zr0[v] = zr1[v] = (S)0;
+    for (int v = 0; v < VL; ++v) zr0[v] = zr1[v] = zg0[v] = zg1[v] = (S)0;
     auto zreg = [&](int jj, int ii) { return ZR == 2 && jj == BY - 1 && ii >= BX - 2; };
 
     // ---- lane constants
@@ -1651,8 +1653,18 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                 }
                 if constexpr (O2) {
                     load_face<COH>(zgin, (unsigned)(jj * nx + ii) * rowb, lofs, t);
+                    if (zreg(jj, ii)) {
+                        if (ii == BX - 1) {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) ldz(jj, ii, v) = t[v];
+                            for (int v = 0; v < VL; ++v) zg1[v] = t[v];
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < VL; ++v) zg0[v] = t[v];
+                        }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VL; ++v) ldz(jj, ii, v) = t[v];
+                    }
                 }
             }
     }
@@ -1871,17 +1883,24 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                 if (zreg(jj, ii)) {
                     if (ii == BX - 1) {
 #pragma unroll
-                        for (int v = 0; v < VL; ++v) zl[v] = zr1[v];
+                        for (int v = 0; v < VL; ++v) {
+                            zl[v] = zr1[v];
+                            zg[v] = O2 ? zg1[v] : (S)0;
+                        }
                     } else {
 #pragma unroll
-                        for (int v = 0; v < VL; ++v) zl[v] = zr0[v];
+                        for (int v = 0; v < VL; ++v) {
+                            zl[v] = zr0[v];
+                            zg[v] = O2 ? zg0[v] : (S)0;
+                        }
                     }
                 } else {
 #pragma unroll
-                    for (int v = 0; v < VL; ++v) zl[v] = lds(jj, ii, v);
+                    for (int v = 0; v < VL; ++v) {
+                        zl[v] = lds(jj, ii, v);
+                        zg[v] = O2 ? S(ldz(jj, ii, v)) : (S)0;
+                    }
                 }
-#pragma unroll
-                for (int v = 0; v < VL; ++v) zg[v] = O2 ? S(ldz(jj, ii, v)) : (S)0;
                 // pinned here: not moved below the loads of the branches
                 // (first order; the second-order form has no registers to spare)
                 if constexpr (!O2) {
@@ -1984,7 +2003,12 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                     prevF[v] = f + dx;
                     Fy[v] = f + dy;
                     Fz[v] = f + dz;
-                    ldz(jj, ii, v) = Fz[v];
+                    if (!zreg(jj, ii))
+                        ldz(jj, ii, v) = Fz[v];
+                    else if (ii == BX - 1)
+                        zg1[v] = Fz[v];
+                    else
+                        zg0[v] = Fz[v];
                     e0 += wd[v] * xd[v] * (double)dx;
                     e1 += wd[v] * (double)dy;
                     e2 += wd[v] * (double)dz;
@@ -2285,8 +2309,10 @@ template <typename T, int V, int BXX, int BYY>
 hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, int nonuniform, const void* args, hipStream_t st)
 {
     const SweepArgs<T>& a = *(const SweepArgs<T>*)args;
-    // the plane of f, and with the second order the plane of F along z
-    const size_t lds = (size_t)(order2 ? 2 : 1) * BYY * BXX * V * 64 * sizeof(T);
+    // the plane of f, and with the second order the plane of F along z (the
+    // pipelined second-order Shakhov body keeps zreg_cells of each in registers)
+    const int zr = pipelined && order2 && !esbgk ? zreg_cells<T, V, BXX, BYY, true, false, false>() : 0;
+    const size_t lds = ((size_t)(order2 ? 2 : 1) * BYY * BXX - 2 * zr) * V * 64 * sizeof(T);
     // FP64 ES-BGK on a uniform x axis: the cross factors by recurrence
     constexpr bool XR = sizeof(T) == 8 && V > 1;
     const bool xr = XR && esbgk && a.xuni;
