@@ -197,15 +197,14 @@ void derive_schedule(dvm_ctx* c)
     // form takes 2 per lane
     // and 4x2 bricks (141 GPt/s against 131 with 4 per lane at 2x2, the most
     // its registers and two LDS planes allow); 1 per lane: plain body, 4x4.
-    // FP64 with 2 per lane (96^3 x 28^3): pipelined 234 GPt/s, plain 214.
     const int nax = c->vg.m[0] - c->hsplit[0];  // larger half along x
     const bool f64 = c->prec == DVM_F64;
     const int o2 = c->order == 2, es = c->model == 1;
     int vl = 4;
-    // FP64 takes 4 per lane only without empty slots (measured: 96^3 x 28^3,
-    // 14 nodes per half, is faster with 2 per lane and 4x2 bricks) and in
-    // the first-order forms
-    if (f64 && (nax % 4 || o2)) vl = 2;
+    // FP64 takes 4 per lane in the first-order forms (96^3 x 28^3, 14 nodes
+    // per half: 263 GPt/s against 257 with 2 per lane, whose 22 tiles per
+    // octant write 70 % more moment records than 13), 2 at second order
+    if (f64 && o2) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
     auto default_bx = [&](int v) { return (f64 && v == 4 && o2) ? 2 : 4; };
     auto default_by = [&](int v) { return v == 1 ? 4 : 2; };

@@ -258,7 +258,7 @@ def test_model_arguments(L):
     ("c2", 0, 1, 1, (4, 4, 2, 16, 1)),    # ES-BGK FP64
     ("c2", 0, 2, 0, (2, 4, 2, 16, 1)),    # second order FP64: 2 per lane
     ("c3", 1, 1, 0, (4, 4, 2, 12, 1)),    # FP32, 14 nodes per half (empty slots)
-    ("c3", 0, 1, 0, (2, 4, 2, 16, 1)),    # FP64, 14 nodes per half -> 2 per lane
+    ("c3", 0, 1, 0, (4, 4, 2, 16, 1)),    # FP64, 14 nodes per half (empty slots)
     ("c4", 1, 1, 0, (4, 4, 2, 12, 1)),    # FP32, 24 nodes per half
     ("c1", 0, 1, 0, (2, 4, 2, 16, 1)),    # FP64, 6 nodes per half
 ])
