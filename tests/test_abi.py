@@ -255,7 +255,7 @@ def test_model_arguments(L):
 @pytest.mark.parametrize("name,prec,order,model,expect", [
     # (VL, BX, BY, BZ, pipelined) chosen by the library for the benchmark workloads
     ("c2", 0, 1, 0, (4, 4, 2, 16, 1)),    # FP64, 16 nodes per x half
-    ("c2", 0, 1, 1, (4, 4, 2, 16, 1)),    # ES-BGK FP64
+    ("c2", 0, 1, 1, (4, 3, 2, 16, 1)),    # ES-BGK FP64: 3x2 bricks
     ("c2", 0, 2, 0, (2, 4, 2, 16, 1)),    # second order FP64: 2 per lane
     ("c3", 1, 1, 0, (4, 4, 2, 12, 1)),    # FP32, 14 nodes per half (empty slots)
     ("c3", 0, 1, 0, (4, 4, 2, 16, 1)),    # FP64, 14 nodes per half (empty slots)
@@ -295,7 +295,11 @@ def test_esbgk_on_a_stretched_mesh_schedule(L):
     info = L.Info()
     assert lib.dvm_get_info(h, C.byref(info)) == 0
     got = (info.vel_per_lane, info.brick[0], info.brick[1], info.brick[2], info.pipelined)
-    assert got == (4, 4, 2, 16, 1), got
+    assert got == (4, 3, 2, 16, 1), got
+    # the plain body has no ES-BGK kernel on a stretched mesh or on 3x2 bricks
+    assert lib.dvm_set_schedule(h, 4, 3, 2, 0, 1) == 0
+    assert lib.dvm_bind_workspace(h, C.c_void_p(1 << 20), 1 << 40) == -1
+    assert b"pipelined" in lib.dvm_last_error()
     lib.dvm_destroy(h)
     # 5 nodes per x half in FP64: 1 per lane, no stretched ES-BGK kernel
     small = cases.cavity((6, 5, 4), 10, kn=1.0)

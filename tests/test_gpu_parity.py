@@ -680,6 +680,22 @@ def test_esbgk_sweep_variants(oracle_mod, vl, bx, by, pf):
     assert np.abs(s.stress() - o.stress()).max() <= FP64_TOL * np.abs(o.stress()).max()
 
 
+@pytest.mark.parametrize("name", ["ragged", "cavity_m16", "stretched_m16"])
+def test_esbgk_on_three_by_two_bricks(oracle_mod, name):
+    """The FP64 ES-BGK sweep's 3x2 bricks (its default with 4 per lane), on
+    ragged bricks, a full lane and a stretched mesh."""
+    case = _es_cases()[name] if name != "stretched_m16" else _es_stretched_cases()["cavity_m16"]
+    s, o = run_pair(case, 2, oracle_mod, init=cases.random_fields(case, seed=63),
+                    schedule=dict(vl=4, bx=3, by=2, pipelined=True))
+    info = s.info()
+    assert (info["vel_per_lane"], info["brick"][0], info["brick"][1], info["sweep_kernel"]) == \
+        (4, 3, 2, "sweep_kernel_pf"), info
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "uy", "uz", "T", "qx", "qy"):
+        assert err[k] <= FP64_TOL, (k, err)
+    assert np.abs(s.stress() - o.stress()).max() <= FP64_TOL * np.abs(o.stress()).max()
+
+
 @pytest.mark.parametrize("groups", [1, 3])
 def test_checkpoint_resume_and_run_to_run_are_bitwise(groups):
     """The iteration state is (W, q, wall densities, M0): resuming from a
