@@ -2246,10 +2246,11 @@ __global__ __launch_bounds__(64) void sweep_kernel_x(const SweepArgs<S> A)
     X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 4, 2) X(double, 4, 3, 2) \
     X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
 // and for the second-order and ES-BGK sweeps
-// (3x2 bricks: the pipelined first-order ES-BGK sweep only)
+// (3x2 bricks: the pipelined first-order ES-BGK sweep in FP64, the
+// pipelined second-order Shakhov sweep in FP32)
 #define DVM_SWEEP_VARIANTS_O2(X) \
     X(double, 1, 4, 4) X(double, 2, 4, 2) X(double, 4, 2, 2) X(double, 4, 4, 2) X(double, 4, 3, 2) \
-    X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2)
+    X(float, 1, 4, 4) X(float, 2, 4, 2) X(float, 4, 4, 2) X(float, 4, 3, 2)
 
 bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, int order2, int esbgk)
 {
@@ -2257,9 +2258,10 @@ bool sweep_variant_available(int prec, int vl, int bx, int by, int nonuniform, i
     if ((prec == 0) == (sizeof(T) == 8) && vl == V && bx == BXX && by == BYY) return true;
     if (order2 || esbgk) {
         // on a stretched mesh: pipelined body with two or more velocities
-        // per lane; 3x2 bricks for the first-order ES-BGK sweep only
+        // per lane; 3x2 bricks for the first-order ES-BGK sweep in FP64 and
+        // the second-order Shakhov sweep in FP32 only
         if (nonuniform && vl < 2) return false;
-        if (bx == 3 && (order2 || !esbgk)) return false;
+        if (bx == 3 && (prec == 0 ? (order2 || !esbgk) : (!order2 || esbgk))) return false;
         DVM_SWEEP_VARIANTS_O2(X)
     } else if (nonuniform) {
         DVM_SWEEP_VARIANTS_NU(X)
@@ -2318,14 +2320,19 @@ hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, int nonuniform, 
     // FP64 ES-BGK on a uniform x axis: the cross factors by recurrence
     constexpr bool XR = sizeof(T) == 8 && V > 1;
     const bool xr = XR && esbgk && a.xuni;
-    // 3x2 bricks: built for the pipelined first-order ES-BGK sweep only
-    constexpr bool ES_ONLY = BXX == 3;
+    // 3x2 bricks: built for the pipelined sweeps whose LDS plane would hold
+    // them below the waves their registers allow -- in FP64 the first-order
+    // ES-BGK form, in FP32 the second-order Shakhov form
+    constexpr bool ES_ONLY = BXX == 3 && sizeof(T) == 8, O2_ONLY = BXX == 3 && sizeof(T) == 4;
     if (ES_ONLY && (order2 || !esbgk || !pipelined)) return hipErrorInvalidValue;
+    if (O2_ONLY && (!order2 || esbgk || !pipelined)) return hipErrorInvalidValue;
     if (nonuniform) {
         // stretched mesh: pipelined body, two or more velocities per lane
         if (!pipelined || V < 2) return hipErrorInvalidValue;
         if constexpr (V < 2) {
             return hipErrorInvalidValue;
+        } else if constexpr (O2_ONLY) {
+            sweep_kernel_pfx<T, V, BXX, BYY, true, false, true><<<a.nblocks, 64, lds, st>>>(a);
         } else if constexpr (ES_ONLY) {
             if (xr)
                 sweep_kernel_pfx<T, V, BXX, BYY, false, true, true, XR><<<a.nblocks, 64, lds, st>>>(a);
@@ -2346,7 +2353,9 @@ hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, int nonuniform, 
         return hipGetLastError();
     }
     if (pipelined) {
-        if constexpr (ES_ONLY) {
+        if constexpr (O2_ONLY) {
+            sweep_kernel_pfx<T, V, BXX, BYY, true, false><<<a.nblocks, 64, lds, st>>>(a);
+        } else if constexpr (ES_ONLY) {
             if (xr)
                 sweep_kernel_pfx<T, V, BXX, BYY, false, true, false, XR><<<a.nblocks, 64, lds, st>>>(a);
             else
@@ -2365,7 +2374,7 @@ hipError_t launch_sweep_x(int pipelined, int order2, int esbgk, int nonuniform, 
         }
         return hipGetLastError();
     }
-    if constexpr (ES_ONLY) {
+    if constexpr (ES_ONLY || O2_ONLY) {
         return hipErrorInvalidValue;
     } else {
         if (order2 && esbgk)

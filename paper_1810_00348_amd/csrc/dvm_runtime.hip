@@ -195,7 +195,9 @@ void derive_schedule(dvm_ctx* c)
     // the mesh stretched 1.02 per cell 302 against 289, the paper cube 318
     // against 303; the FP64 ES-BGK body keeps its whole plane in LDS and
     // takes 3x2 bricks, whose 12 KB plane lets in the 3 waves per SIMD its
-    // registers allow: 240 GPt/s against 230 at 4x2); the second-order FP64
+    // registers allow: 240 GPt/s against 230 at 4x2; likewise the
+    // second-order FP32 form, whose two 8 KB planes 3x2 brings to 12 KB:
+    // 96^3 x 28^3 251 against 232); the second-order FP64
     // form takes 2 per lane
     // and 4x2 bricks (141 GPt/s against 131 with 4 per lane at 2x2, the most
     // its registers and two LDS planes allow); 1 per lane: plain body, 4x4.
@@ -208,7 +210,9 @@ void derive_schedule(dvm_ctx* c)
     // octant write 70 % more moment records than 13), 2 at second order
     if (f64 && o2) vl = 2;
     while (vl > 1 && 8 * (((nax + vl - 1) / vl) * vl - nax) > ((nax + vl - 1) / vl) * vl) vl /= 2;
-    auto default_bx = [&](int v) { return (f64 && v == 4) ? (o2 ? 2 : es ? 3 : 4) : 4; };
+    auto default_bx = [&](int v) {
+        return v != 4 ? 4 : f64 ? (o2 ? 2 : es ? 3 : 4) : (o2 && !es ? 3 : 4);
+    };
     auto default_by = [&](int v) { return v == 1 ? 4 : 2; };
     if (!sweep_variant_available(c->prec, vl, default_bx(vl), default_by(vl), c->nonuniform, o2, es)) vl = 1;
     int bx = default_bx(vl), by = default_by(vl);
@@ -1051,11 +1055,12 @@ dvm_status check_bindable(dvm_ctx* c)
         return fail(DVM_ERR_ARG, "a face row of this grid and velocity set exceeds the 32-bit offsets of the "
                     "sweep even with one-cell brick columns: use more velocity groups");
     if (!sweep_variant_available(c->prec, c->VL, c->BX, c->BY, c->nonuniform, c->order == 2, c->model == 1) ||
-        ((c->order == 2 || c->model == 1) && c->nonuniform && c->PF != 1) || (c->model == 1 && c->BX == 3 && c->PF != 1))
+        ((c->order == 2 || c->model == 1) && c->nonuniform && c->PF != 1) ||
+        ((c->order == 2 || c->model == 1) && c->BX == 3 && c->PF != 1))
         return fail(DVM_ERR_ARG, "no sweep kernel is built for %d velocities per lane, %dx%d bricks and body %d with "
                     "this precision, mesh kind, order and model (a stretched mesh at second order or with ES-BGK, "
-                    "and ES-BGK on 3x2 bricks, take the pipelined body with 2 or more velocities per lane)", c->VL,
-                    c->BX, c->BY, c->PF + 1);
+                    "and 3x2 bricks at second order or with ES-BGK, take the pipelined body with 2 or more "
+                    "velocities per lane)", c->VL, c->BX, c->BY, c->PF + 1);
     if (c->wide && (c->PF == 0 || !sweep_wide_params_available(c->prec, c->VL, c->BX, c->BY, c->nonuniform,
                                                                 c->order == 2, c->model == 1)))
         return fail(DVM_ERR_ARG, "FP64 parameters beside FP32 storage are built for the first-order Shakhov sweep "

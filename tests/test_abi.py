@@ -257,6 +257,7 @@ def test_model_arguments(L):
     ("c2", 0, 1, 0, (4, 4, 2, 16, 1)),    # FP64, 16 nodes per x half
     ("c2", 0, 1, 1, (4, 3, 2, 16, 1)),    # ES-BGK FP64: 3x2 bricks
     ("c2", 0, 2, 0, (2, 4, 2, 16, 1)),    # second order FP64: 2 per lane
+    ("c3", 1, 2, 0, (4, 3, 2, 12, 1)),    # second order FP32: 3x2 bricks
     ("c3", 1, 1, 0, (4, 4, 2, 12, 1)),    # FP32, 14 nodes per half (empty slots)
     ("c3", 0, 1, 0, (4, 4, 2, 16, 1)),    # FP64, 14 nodes per half (empty slots)
     ("c4", 1, 1, 0, (4, 4, 2, 12, 1)),    # FP32, 24 nodes per half

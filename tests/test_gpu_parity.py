@@ -386,6 +386,20 @@ def test_second_order_fp32_storage(oracle_mod):
         assert err[k] <= 2e-5, (k, err)
 
 
+@pytest.mark.parametrize("name", ["ragged", "cube_half"])
+def test_second_order_fp32_bricks(oracle_mod, name):
+    """The FP32 second-order sweep on its default 3x2 bricks and on 4x2,
+    against the FP64 oracle."""
+    case = _o2_cases()[name]
+    for bx in (3, 4):
+        s, o = run_pair(case, 3, oracle_mod, precision="f32", schedule=dict(vl=4, bx=bx, by=2, pipelined=True))
+        info = s.info()
+        assert (info["vel_per_lane"], info["brick"][0], info["brick"][1]) == (4, bx, 2), info
+        err = field_errors(s.fields(), o.fields())
+        for k in ("rho", "ux", "T"):
+            assert err[k] <= 2e-5, (bx, k, err)
+
+
 def _o2_stretched_cases():
     a = cases.stretched(cases.cavity((13, 10, 11), 8, kn=0.3, lid=0.4, vmax=4.5), 1.15)
     b = cases.stretched(cases.cube_half(nx=14, ny=10, nz=6, edge=4, x0=4, m=12, vmax=7.0, mach=2.0, kn=0.5),
