@@ -1573,7 +1573,9 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
 
     auto lds = [&](int jj, int ii, int v) -> S& { return plane[((jj * BX + ii) * VL + v) * 64 + lane]; };
     // the z inflow of the last row's last two cells in registers (ZR = 2):
-    // their plane slots are the last two, which the launch does not allocate
+    // their slots are the last two of the f plane, and of the F plane that
+    // follows it directly at second order (zr0/zr1 hold f, zg0/zg1 F);
+    // the launch does not allocate them
     constexpr int ZR = zreg_cells<S, VL, BX, BY, O2, ES, COH>();
     auto ldz = [&](int jj, int ii, int v) -> S& {
         return plane[((BY * BX - ZR + jj * BX + ii) * VL + v) * 64 + lane];
