@@ -111,16 +111,23 @@ def _ragged_cases():
     # of 64 (its waves cover 64 cells each); with solid cells
     f = cases.cavity((7, 6, 5), 36, kn=0.5, lid=0.3)
     g = cases.cube_half(nx=10, ny=8, nz=7, edge=4, x0=3, m=34, vmax=9.0, mach=3.0, kn=0.5)
-    return {"ragged": a, "oddM": b, "cube": c, "nocorr": d, "bgk": e, "wide": f, "cube_wide": g}
+    # 4 per lane in FP64 on 4x2 bricks whose last column is 3 cells wide and
+    # last row 1 cell deep (the plane cells the sweep keeps in registers)
+    h = cases.cavity((11, 9, 13), 8, kn=0.6, lid=0.35, vmax=4.5)
+    return {"ragged": a, "oddM": b, "cube": c, "nocorr": d, "bgk": e, "wide": f, "cube_wide": g, "ragged3": h}
 
 
-@pytest.mark.parametrize("name", ["ragged", "oddM", "cube", "nocorr", "bgk", "wide", "cube_wide"])
+@pytest.mark.parametrize("name", ["ragged", "oddM", "cube", "nocorr", "bgk", "wide", "cube_wide", "ragged3"])
 def test_small_cases_match_oracle(oracle_mod, name):
     case = _ragged_cases()[name]
     init = None
-    if name in ("ragged", "bgk", "wide"):
+    if name in ("ragged", "bgk", "wide", "ragged3"):
         init = cases.random_fields(case, seed=7)
     s, o = run_pair(case, 3, oracle_mod, init=init)
+    if name == "ragged3":
+        inf = s.info()
+        assert (inf["vel_per_lane"], inf["brick"][0], inf["brick"][1], inf["sweep_kernel"]) == \
+            (4, 4, 2, "sweep_kernel_pf"), inf
     err = field_errors(s.fields(), o.fields())
     print(name, err, s.info())
     for k in ("rho", "ux", "uy", "uz", "T"):
@@ -376,6 +383,22 @@ def test_second_order_with_velocity_groups(oracle_mod):
     err = field_errors(s.fields(), o.fields())
     for k in ("rho", "ux", "uy", "uz", "T", "qx"):
         assert err[k] <= FP64_TOL, (k, err)
+
+
+def test_second_order_register_cells_on_ragged_bricks(oracle_mod):
+    """Second order in FP64 (2 per lane, 4x2 bricks, the last row's last
+    two cells' f and F in registers) where the last brick column is 3 cells
+    wide and the last brick row 1 cell deep."""
+    case = dataclasses.replace(_ragged_cases()["ragged3"], order=2)
+    s, o = run_pair(case, 3, oracle_mod, init=cases.random_fields(case, seed=9))
+    inf = s.info()
+    assert (inf["vel_per_lane"], inf["brick"][0], inf["brick"][1], inf["sweep_kernel"]) == \
+        (2, 4, 2, "sweep_kernel_pf"), inf
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "uy", "uz", "T", "qx", "qy"):
+        assert err[k] <= FP64_TOL, (k, err)
+    rwg, rwo = s.state()[2], o.state()[2]
+    assert np.abs(rwg - rwo).max() <= FP64_TOL * np.abs(rwo).max()
 
 
 def test_second_order_fp32_storage(oracle_mod):
