@@ -51,6 +51,30 @@ __device__ __forceinline__ float fast_rcp(float d)
     return fmaf(r, e, r);
 }
 
+// reciprocals of a lane's VL denominators from one reciprocal of their
+// product (products of the others: 3 (VL - 1) multiplications in place of
+// VL - 1 reciprocals with their Newton steps)
+template <int VL>
+__device__ __forceinline__ void batch_rcp(const double (&d)[VL], double (&r)[VL])
+{
+    if constexpr (VL == 1) {
+        r[0] = fast_rcp(d[0]);
+    } else if constexpr (VL == 2) {
+        const double q = fast_rcp(d[0] * d[1]);
+        r[0] = q * d[1];
+        r[1] = q * d[0];
+    } else {
+        static_assert(VL == 4, "batch_rcp: 1, 2 or 4 values");
+        const double p01 = d[0] * d[1], p23 = d[2] * d[3];
+        const double q = fast_rcp(p01 * p23);
+        const double q01 = q * p23, q23 = q * p01;  // 1 / p01, 1 / p23
+        r[0] = q01 * d[1];
+        r[1] = q01 * d[0];
+        r[2] = q23 * d[3];
+        r[3] = q23 * d[2];
+    }
+}
+
 // 5x5 symmetric positive definite solve by Cholesky (FP64).
 __device__ bool chol5_solve(double A[5][5], const double b[5], double x[5])
 {
@@ -1983,6 +2007,20 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
             const S kx = O2 && ixf ? (S)1 + thx : (S)1, ky = O2 && iyf ? (S)1 + thy : (S)1;
             const S kz = O2 && izf ? (S)1 + thz : (S)1;
             const S ayk = ayc * ky, azk = azc * kz;
+            // FP64 ES-BGK: one reciprocal for the lane's denominators (in
+            // the Shakhov and second-order forms the products' registers
+            // would spill or cost a wave per SIMD)
+            constexpr bool BR = sizeof(S) == 8 && VL > 1 && ES && !O2;
+            double rden[VL];
+            if constexpr (BR) {
+                double dd[VL];
+#pragma unroll
+                for (int v = 0; v < VL; ++v) {
+                    const S axv = xix[v] * sx;
+                    dd[v] = O2 ? double(axv * kx + ayk + azk + (S)nu) : double(axv + aynu);
+                }
+                batch_rcp<VL>(dd, rden);
+            }
 #pragma unroll
             for (int v = 0; v < VL; ++v) {
                 const PT cx = (PD ? (PT)xd[v] : (PT)xix[v]) - Ux;
@@ -1998,7 +2036,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                 const S num = axv * fx[v] + ayc * fy[v] + azc * fz[v] + (S)nfs;
                 S f;
                 if constexpr (O2) {
-                    f = num * fast_rcp(axv * kx + ayk + azk + (S)nu);
+                    if constexpr (BR)
+                        f = num * (S)rden[v];
+                    else
+                        f = num * fast_rcp(axv * kx + ayk + azk + (S)nu);
                     const S dx = ixf ? thx * (f - ux[v]) : (S)0;
                     const S dy = iyf ? thy * (f - uy[v]) : (S)0;
                     const S dz = izf ? thz * (f - uz[v]) : (S)0;
@@ -2015,7 +2056,10 @@ __device__ __forceinline__ void sweep_body_pf(const SweepArgs<S>& A, const PT* _
                     e1 += wd[v] * (double)dy;
                     e2 += wd[v] * (double)dz;
                 } else {
-                    f = num * fast_rcp(axv + aynu);
+                    if constexpr (BR)
+                        f = num * (S)rden[v];
+                    else
+                        f = num * fast_rcp(axv + aynu);
                 }
                 prev[v] = f;
                 if (!zreg(jj, ii))
