@@ -241,11 +241,16 @@ def _tiny_cases():
     c5 = cases.stretched(cases.cavity((4, 3, 5), 4, kn=0.4, lid=0.3), 1.4)           # wall-clustered mesh
     c6 = cases.stretched(cases.cube_half(nx=6, ny=4, nz=3, edge=2, x0=2, m=6, vmax=6.0, mach=1.5, kn=0.5),
                          1.3, centres=(0.75, 1.0, None))                              # clustered at the cube
-    return [c1, c2, c3, c4, c5, c6]
+    # ES-BGK sources on the cube mesh (8 nodes per axis: on 6 the iterate's
+    # stress leaves the Gaussian's covariance indefinite after one step)
+    c7 = dataclasses.replace(
+        cases.stretched(cases.cube_half(nx=6, ny=4, nz=3, edge=2, x0=2, m=8, vmax=5.0, mach=1.5, kn=0.5),
+                        1.3, centres=(0.75, 1.0, None)), model="esbgk")
+    return [c1, c2, c3, c4, c5, c6, c7]
 
 
 @pytest.mark.parametrize("order", [1, 2])
-@pytest.mark.parametrize("ci", range(6))
+@pytest.mark.parametrize("ci", range(7))
 def test_sweep_matches_dense_solve(oracle_mod, ci, order):
     case = _tiny_cases()[ci]
     if order == 2:
