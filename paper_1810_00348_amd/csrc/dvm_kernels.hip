@@ -4,7 +4,9 @@
 // Per outer iteration (eq. "iter_outer"):
 //   params_kernel     per cell: U, T, 1/tau, Shakhov and conservative-correction
 //                     parameters in FP64, and the three 1-D Gaussian factor
-//                     tables of the Maxwellian (eqs. "feq", "mom", "mu_ref").
+//                     tables of the Maxwellian (eqs. "feq", "mom", "mu_ref");
+//                     params_es_kernel the same for the ES-BGK Gaussian, whose
+//                     correction sums run over the whole velocity set per cell.
 //   sweep_kernel_pf   the hot path: first-order upwind implicit sweep of every
 //                     discrete velocity (eq. "sweeping_example") over 3-D bricks
 //                     scheduled along brick diagonals (software-pipelined cell
