@@ -590,6 +590,19 @@ def test_esbgk_on_stretched_meshes_matches_oracle(oracle_mod, name):
     assert abs(s.state()[3] - o.initial_mass()) <= 1e-14 * o.initial_mass()
 
 
+def test_esbgk_on_a_stretched_mesh_with_velocity_groups(oracle_mod):
+    """ES-BGK on a stretched cube mesh with the velocity set swept in groups
+    (the paper cube's form) against the oracle: 2 tiles per octant, so a
+    request of 3 groups gives one tile per group."""
+    case = _es_stretched_cases()["cube_half"]
+    s, o = run_pair(case, 3, oracle_mod, groups=3)
+    assert s.info()["velocity_groups"] == 2 and s.info()["tiles_per_octant"] == 2
+    err = field_errors(s.fields(), o.fields())
+    for k in ("rho", "ux", "uy", "uz", "T"):
+        assert err[k] <= FP64_TOL, (k, err)
+    assert np.abs(s.stress() - o.stress()).max() <= FP64_TOL * np.abs(o.stress()).max()
+
+
 def test_esbgk_on_a_stretched_mesh_fp32(oracle_mod):
     case = _es_stretched_cases()["cavity_m16"]
     s, o = run_pair(case, 4, oracle_mod, precision="f32")
