@@ -95,12 +95,15 @@ def test_c2_full_size_other_forms_symmetry_and_mass(model, order):
     assert abs(W[0].sum() * (1.0 / 64) ** 3 - M0) <= 1e-12 * M0
 
 
-def test_c3_full_size_fp32_symmetry():
-    """C3 (96^3 x 28^3, FP32 storage, 4 per lane with empty slots)."""
+@pytest.mark.parametrize("order", [1, 2])
+def test_c3_full_size_fp32_symmetry(order):
+    """C3 (96^3 x 28^3, FP32 storage, 4 per lane with empty slots; at second
+    order on its 3x2 bricks)."""
     Solver = _solver()
-    case = cases.config("c3")
+    case = dataclasses.replace(cases.config("c3"), order=order)
     s = Solver(case, precision="f32")
     print(s.info(), flush=True)
+    assert s.info()["brick"][0] == (3 if order == 2 else 4)
     s.init_uniform()
     s.iterate(2)
     err = _mirror_error(s.fields(), case.n, 0, "uz")
